@@ -1,0 +1,255 @@
+#!/usr/bin/env python3
+"""Throughput of the radiance-cache autoencoder hot path on one MI355X.
+
+One timed step = one forward pass of the autoencoder over a batch of 4096
+cache-point maps of 64x64 (7 channels in, 3 out) in BF16 on MFMA, inputs
+already resident in HBM. The JSON line also carries the other legs of the
+metric (FP32 forward, FP8 forward, forward+backward, the training step with
+Adam), the roofline position of the dominant kernel measured live with HIP
+events, and the FP64 oracle timed on the host cores.
+
+Progress goes to stderr; stdout gets exactly one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "maps/s CAE fwd & fwd+bwd, 64x64 maps; BF16 vs FP32 at rel-err<=1e-2"
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+LAYERS = (("E1", False, 7, 32), ("E2", False, 32, 64), ("E3", False, 64, 128),
+          ("D3", True, 128, 64), ("D2", True, 128, 32), ("D1", True, 64, 3))
+ESIZE = {"f32": 4, "bf16": 2, "fp8": 1}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def layer_io(l, H):
+    din = (1, 2, 4, 8, 4, 2)[l]
+    dout = (2, 4, 8, 4, 2, 1)[l]
+    return H // din, H // dout
+
+
+def layer_cost(l, n, H, compute):
+    """Algorithmic FLOPs and HBM bytes of one forward launch of layer l.
+
+    FLOPs are nominal: 2 * Cout * Cin * 9 per output pixel of a convolution
+    and per input pixel of a transposed convolution. Bytes: the layer input
+    (float32 x for E1, else the stored activations), its output (float32 y
+    for D1), and the packed weights once.
+    """
+    name, tconv, cin, cout = LAYERS[l]
+    hin, hout = layer_io(l, H)
+    pin, pout = n * hin * hin, n * hout * hout
+    flops = 2.0 * cout * cin * 9 * (pin if tconv else pout)
+    es = ESIZE[compute]
+    bytes_in = pin * cin * (4 if l == 0 else es)
+    bytes_out = pout * cout * (4 if l == 5 else es)
+    bytes_w = cout * 9 * cin * es
+    return flops, bytes_in + bytes_out + bytes_w
+
+
+def gen_maps(n, H, chunk=512):
+    import numpy as np
+    import torch
+    from paper_1910_02480_amd import synth
+    x = torch.empty((n, H, H, 7), dtype=torch.float32)
+    for s in range(0, n, chunk):
+        k = min(chunk, n - s)
+        x[s:s + k] = torch.from_numpy(synth.radiance_maps(k, H, H, start=s))
+    return x
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def read_profile(B, h):
+    return B.drc_cae_profile_read(h)
+
+
+def cpu_baseline(x_sample_fn, H, budget_s):
+    """FP64 oracle forward on the host, on a bounded sample of the workload."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1910_02480_amd import synth
+    params = synth.init_params(0)
+    O.build()
+    x1 = x_sample_fn(1)
+    t0 = time.perf_counter()
+    O.forward(params, x1)
+    t1 = time.perf_counter() - t0
+    n = int(max(1, min(512, budget_s / max(t1, 1e-3))))
+    xs = x_sample_fn(n)
+    t0 = time.perf_counter()
+    acts = O.forward(params, xs)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    return {"value": n / dt, "unit": "maps/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle forward of maps 0..{n - 1} of the {H}x{H} workload "
+                      f"({dt:.1f} s, {threads} OpenMP threads)"}, acts["y"], n
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--maps", type=int, default=4096)
+    ap.add_argument("--res", type=int, default=64)
+    ap.add_argument("--train-maps", type=int, default=256)
+    ap.add_argument("--main-only", action="store_true", help="time only the headline leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the autoencoder path is built and measured on one "
+              "MI355X; multi-GPU sharding is design only (see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1910_02480_amd import binding as B
+    from paper_1910_02480_amd import synth
+    from paper_1910_02480_amd.cae import CAE, Trainer
+
+    dev = torch.device("cuda:0")
+    n, H = args.maps, args.res
+    log(f"generating {n} maps of {H}x{H}")
+    x_host = gen_maps(n, H)
+    x = x_host.to(dev)
+    params = torch.from_numpy(synth.init_params(0)).to(dev)
+    y = torch.empty((n, H, H, 3), dtype=torch.float32, device=dev)
+    legs = {}
+
+    # ---------------- headline: BF16 forward, profiled live
+    cae = CAE("bf16", params, device=dev)
+    ws = cae.workspace(n, H, H, B.DRC_WS_FORWARD)
+    fwd = lambda: B.drc_cae_forward(cae.h, x, y, None, ws)
+    for _ in range(args.warmup):
+        fwd()
+    torch.cuda.synchronize()
+    B.drc_cae_profile(cae.h, 1)
+    read_profile(B, cae.h)
+    log(f"timing bf16 forward: {args.steps} steps")
+    t = timed(fwd, args.steps, 0)
+    ms_l, calls_l = read_profile(B, cae.h)
+    B.drc_cae_profile(cae.h, 0)
+    y_bf16 = y[:8].cpu().numpy()
+    value = n / t
+    kernels = []
+    for l in range(6):
+        if calls_l[l] == 0:
+            continue
+        avg = ms_l[l] / calls_l[l] * 1e-3
+        fl, by = layer_cost(l, n, H, "bf16")
+        kernels.append({"kernel": f"forward {LAYERS[l][0]}", "avg_ms": avg * 1e3,
+                        "share": ms_l[l] / max(sum(ms_l[:6]), 1e-30),
+                        "GB/s": by / avg / 1e9, "TFLOP/s": fl / avg / 1e12,
+                        "alg_bytes": by, "alg_flops": fl})
+    dom = max(kernels, key=lambda k: k["avg_ms"] * 1.0)
+    ai = dom["alg_flops"] / dom["alg_bytes"]
+    ridge = PEAK_TFLOPS["bf16"] * 1e12 / (PEAK_HBM_GBS * 1e9)
+    if ai < ridge:
+        roof = {"bound": "hbm", "achieved": dom["GB/s"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": dom["GB/s"] / PEAK_HBM_GBS}
+    else:
+        roof = {"bound": "mfma", "achieved": dom["TFLOP/s"], "peak": PEAK_TFLOPS["bf16"],
+                "unit": "TFLOP/s", "frac": dom["TFLOP/s"] / PEAK_TFLOPS["bf16"]}
+    roof.update({"kernel": dom["kernel"], "traffic": None, "avg_ms": dom["avg_ms"],
+                 "alg_bytes_per_launch": dom["alg_bytes"], "alg_flops_per_launch": dom["alg_flops"]})
+    total_flops = sum(layer_cost(l, n, H, "bf16")[0] for l in range(6))
+    legs["bf16_fwd"] = {"maps_per_s": value, "ms": t * 1e3,
+                        "mfma_frac_flop_based": total_flops / t / (PEAK_TFLOPS["bf16"] * 1e12)}
+    log(f"bf16 forward: {value:,.0f} maps/s ({t * 1e3:.3f} ms / {n} maps)")
+
+    if not args.main_only:
+        # ---------------- FP32 and FP8 forward
+        for comp in ("f32", "fp8"):
+            c = CAE(comp, params, device=dev)
+            if comp == "fp8":
+                c.calibrate_fp8(x[:256])
+            w = c.workspace(n, H, H, B.DRC_WS_FORWARD)
+            tt = timed(lambda: B.drc_cae_forward(c.h, x, y, None, w), args.steps, args.warmup)
+            legs[f"{comp}_fwd"] = {"maps_per_s": n / tt, "ms": tt * 1e3,
+                                   "mfma_frac_flop_based": total_flops / tt / (PEAK_TFLOPS[comp] * 1e12)}
+            if comp == "f32":
+                y_f32 = y[:8].cpu().numpy()
+            if comp == "fp8":
+                y_fp8 = y[:8].cpu().numpy()
+            log(f"{comp} forward: {n / tt:,.0f} maps/s")
+            del c, w
+        # ---------------- forward + backward (activations saved, no optimizer)
+        for comp in ("bf16", "f32"):
+            c = CAE(comp, params, device=dev)
+            saved, _ = c.saved_buffer(n, H, H)
+            dy = torch.randn((n, H, H, 3), device=dev) * 1e-6
+            dp = torch.empty_like(params)
+            wf = c.workspace(n, H, H, B.DRC_WS_FORWARD)
+            wb = c.workspace(n, H, H, B.DRC_WS_BACKWARD)
+
+            def fb():
+                B.drc_cae_forward(c.h, x, y, saved, wf)
+                B.drc_cae_backward(c.h, x, dy, saved, dp, None, wb)
+            tt = timed(fb, max(3, args.steps // 2), 2)
+            legs[f"{comp}_fwd_bwd"] = {"maps_per_s": n / tt, "ms": tt * 1e3}
+            log(f"{comp} forward+backward: {n / tt:,.0f} maps/s")
+            del c, saved, dy, wf, wb
+        # ---------------- training step (fwd + L1 + bwd + Adam + repack), recompute on
+        nt = args.train_maps
+        xt, tg = synth.training_batch(nt, H)
+        xt, tg = torch.from_numpy(xt).to(dev), torch.from_numpy(tg).to(dev)
+        for comp in ("bf16", "f32"):
+            p = params.clone()
+            tr = Trainer(CAE(comp, device=dev, recompute=True), p)
+            tt = timed(lambda: tr.step(xt, tg), args.steps, args.warmup)
+            legs[f"{comp}_train_step"] = {"maps_per_s": nt / tt, "ms": tt * 1e3, "batch": nt,
+                                          "recompute": True}
+            log(f"{comp} train step (batch {nt}): {nt / tt:,.0f} maps/s, {tt * 1e3:.3f} ms")
+        legs["speedup_bf16_vs_f32"] = {
+            "fwd": legs["bf16_fwd"]["maps_per_s"] / legs["f32_fwd"]["maps_per_s"],
+            "fwd_bwd": legs["bf16_fwd_bwd"]["maps_per_s"] / legs["f32_fwd_bwd"]["maps_per_s"],
+            "train_step": legs["bf16_train_step"]["maps_per_s"] / legs["f32_train_step"]["maps_per_s"]}
+
+    out = {"metric": METRIC, "value": value, "unit": "maps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": f"cae_forward_{n}x{H}x{H}", "maps": n, "H": H, "W": H,
+                      "in_ch": 7, "out_ch": 3, "widths": [32, 64, 128], "parallelism": "single-gpu"},
+           "roofline": roof, "kernels": kernels, "legs": legs}
+
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host")
+        cb, y_ref, ns = cpu_baseline(lambda k: x_host[:k].numpy(), H, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        k = min(ns, 8)
+        def mr(yg):
+            a = np.abs(yg[:k] - y_ref[:k]).reshape(k, -1).max(1)
+            return float((a / np.abs(y_ref[:k]).reshape(k, -1).max(1)).max())
+        acc = {"bf16_max_rel": mr(y_bf16), "maps_checked": k}
+        if not args.main_only:
+            acc["f32_max_rel"] = mr(y_f32)
+            acc["fp8_max_rel"] = mr(y_fp8)
+        out["accuracy_vs_fp64_oracle"] = acc
+        log(f"oracle: {cb['value']:.2f} maps/s on {cb['cores']} threads; accuracy {acc}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,225 @@
+/*
+ * drc_cae.h - C ABI of the MI355X (gfx950) radiance-cache autoencoder.
+ *
+ * The library runs the data-parallel hot path of Deep Radiance Caching
+ * (Jiang & Kainz, arXiv 1910.02480): the convolutional autoencoder that
+ * turns each cache point's noisy hemispherical map (radiance, normals and
+ * distance, Sec. 4.3) into a clean radiance map R (Eq. 2), batched over many
+ * cache points, plus the training step of that network (L1 loss, Sec. 4.3;
+ * PyTorch's Adam, Sec. 5).
+ *
+ * Network (fully convolutional; one set of weights for every map size):
+ *   h1 = relu(conv(x; W1,b1))            7 -> 32,  H/2
+ *   h2 = relu(conv(h1; W2,b2))          32 -> 64,  H/4
+ *   h3 = relu(conv(h2; W3,b3))          64 -> 128, H/8
+ *   u3 = relu(tconv(h3; W4,b4))        128 -> 64,  H/4
+ *   u2 = relu(tconv([u3|h2]; W5,b5))   128 -> 32,  H/2
+ *   y  =      tconv([u2|h1]; W6,b6)     64 -> 3,   H     (linear by default)
+ * conv  = 3x3 cross-correlation, stride 2, zero padding 1;
+ * tconv = 3x3 transposed convolution, stride 2, padding 1, output padding 1
+ *         (y[p] gathers x[i] through kernel row k where p = 2i + k - 1);
+ * [a|b] = channel concatenation, decoder channels first (the skip
+ *         connections of the paper's U-Net-like design, Sec. 4.3).
+ *
+ * Conventions shared by every call:
+ * - Tensors are NHWC, contiguous, float32 at the boundary. x has 7 channels
+ *   in the order R, G, B, Nx, Ny, Nz, D (Sec. 4.3); y has R, G, B.
+ * - Maps are H x W with H and W multiples of 8 (three halvings) and >= 8.
+ * - Parameters are one flat float32 vector: layers E1 E2 E3 D3 D2 D1, each
+ *   W[co][kh][kw][ci] followed by b[co]; 206 819 values. Gradients, Adam's
+ *   m and v use the same layout.
+ * - All pointers named d_* are device pointers on the handle's device,
+ *   16-byte aligned (256-byte aligned for workspaces). The caller owns every
+ *   device buffer; the library owns only its handle, its packed low-precision
+ *   weight copies and its plans.
+ * - Calls only enqueue work on the given stream (hipStream_t passed as
+ *   void*; NULL = the default stream). They never synchronise the device and,
+ *   except the create calls, never allocate device memory.
+ * - Errors: arguments are validated on the host before anything is
+ *   enqueued; a failing call returns a status and enqueues nothing.
+ *   Asynchronous device faults surface as DRC_ERR_HIP from a later call.
+ *   drc_last_error() gives a thread-local text for the last failure.
+ * - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef DRC_CAE_H
+#define DRC_CAE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DRC_OK = 0,
+    DRC_ERR_INVALID_ARG = 1, /* null / misaligned pointer, bad enum value */
+    DRC_ERR_SHAPE = 2,       /* n < 1, H or W not a multiple of 8, ... */
+    DRC_ERR_UNSUPPORTED = 3, /* a configuration this build does not implement */
+    DRC_ERR_WORKSPACE = 4,   /* workspace smaller than required */
+    DRC_ERR_HIP = 5,         /* a HIP runtime call failed */
+    DRC_ERR_STATE = 6        /* call order: e.g. forward before set_params */
+} drc_status;
+
+typedef enum { DRC_F32 = 0, DRC_BF16 = 1, DRC_FP8_E4M3 = 2 } drc_dtype;
+
+/* Network description. Only in_ch = 7, out_ch = 3, widths = {32, 64, 128}
+ * are implemented; other values return DRC_ERR_UNSUPPORTED. compute selects
+ * the arithmetic of the layer GEMMs:
+ *   DRC_F32      float32 operands, float32 MFMA accumulation;
+ *   DRC_BF16     bfloat16 operands and stored activations (round to nearest
+ *                even), float32 accumulation, bias and activation;
+ *   DRC_FP8_E4M3 OCP e4m3 operands with per-tensor scales (inference only),
+ *                float32 accumulation; see drc_cae_calibrate_fp8.
+ * final_relu = 1 applies relu to y (the paper's output stage has a ReLU,
+ * Sec. 4.3); the default 0 keeps the output linear. Training calls require
+ * final_relu = 0. */
+typedef struct {
+    int in_ch;
+    int out_ch;
+    int widths[3];
+    int compute; /* drc_dtype */
+    int final_relu;
+} drc_cae_desc;
+
+/* Adam hyper-parameters (PyTorch's Adam, Sec. 5: lr = 6e-5). Doubles, as
+ * PyTorch keeps them: 1 - beta1, 1 - beta2, lr / (1 - beta1^t) and
+ * 1 / sqrt(1 - beta2^t) are formed in double precision and rounded once to
+ * float32 for the update. */
+typedef struct {
+    double lr;
+    double beta1;
+    double beta2;
+    double eps;
+} drc_adam_cfg;
+
+/* One map of a mixed-resolution frame: an h x w map whose input starts at
+ * element x_off of the packed input (7 channels per pixel) and whose output
+ * starts at element y_off of the packed output (3 channels per pixel). */
+typedef struct {
+    int h, w;
+    int64_t x_off, y_off;
+} drc_map_desc;
+
+typedef struct drc_cae drc_cae;
+typedef struct drc_plan drc_plan;
+
+/* Default description: 7 -> 3 channels, widths 32/64/128, given compute. */
+drc_cae_desc drc_cae_default_desc(int compute);
+
+/* Create a handle on the current HIP device. Allocates the handle's packed
+ * weight buffers (a few MB). *out is NULL on failure. */
+drc_status drc_cae_create(const drc_cae_desc* desc, drc_cae** out);
+void drc_cae_destroy(drc_cae* h);
+
+/* Number of float32 values in the flat parameter vector (206 819). */
+size_t drc_cae_num_params(const drc_cae* h);
+
+/* Convert the float32 master parameters d_params into the handle's packed
+ * weights (forward and transposed backward packs, in the compute type) and
+ * bias copy. Must be called before forward/backward; drc_cae_step repacks by
+ * itself after its update. For FP8 handles the weight scales are computed
+ * here (448 / max |W| per layer). */
+drc_status drc_cae_set_params(drc_cae* h, const float* d_params, void* stream);
+
+/* Activation recompute policy for training (default 0).
+ * 0: forward saves every activation (h1 h2 h3 u3 u2) in d_saved;
+ * 1: forward saves only the skip tensors h1 and h2; backward recomputes
+ *    h3, u3 and u2 from h2 into its workspace. Gradients are bitwise equal
+ *    either way. */
+drc_status drc_cae_set_recompute(drc_cae* h, int on);
+
+/* Bytes of the d_saved buffer for an n x H x W batch under the current
+ * policy, and the byte offsets of h1 h2 h3 u3 u2 inside it (each NHWC in
+ * the compute type: float32, bfloat16 bits, or e4m3 bytes holding value *
+ * scale); offsets of activations not saved under the policy are -1. */
+drc_status drc_cae_saved_size(const drc_cae* h, int n, int H, int W, size_t* bytes,
+                              int64_t offsets[5]);
+
+enum { DRC_WS_FORWARD = 1, DRC_WS_BACKWARD = 2, DRC_WS_STEP = 4, DRC_WS_CALIBRATE = 8 };
+
+/* Workspace bytes needed by the calls named in flags (an OR of DRC_WS_*)
+ * for an n x H x W batch. */
+drc_status drc_cae_workspace_size(const drc_cae* h, int n, int H, int W, int flags,
+                                  size_t* bytes);
+
+/* Forward pass (Sec. 4.3, Eq. 2's R): d_x [n,H,W,7] -> d_y [n,H,W,3].
+ * d_saved may be NULL (inference) or a buffer of drc_cae_saved_size bytes
+ * that receives the activations for a later drc_cae_backward; it must stay
+ * untouched until then. */
+drc_status drc_cae_forward(drc_cae* h, const float* d_x, float* d_y, int n, int H, int W,
+                           void* d_saved, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Backward pass: given d_dy = dL/dy [n,H,W,3] and the d_saved of the
+ * forward pass on d_x, writes dL/dparams (flat layout) to d_dparams and,
+ * when d_dx is not NULL, dL/dx [n,H,W,7]. ReLU derivatives use the rule
+ * relu'(z) = [z > 0] evaluated on the stored activations. Float32 and
+ * bfloat16 handles only. */
+drc_status drc_cae_backward(drc_cae* h, const float* d_x, const float* d_dy, const void* d_saved,
+                            float* d_dparams, float* d_dx, int n, int H, int W, void* d_ws,
+                            size_t ws_bytes, void* stream);
+
+/* One training step (Sec. 4.3 L1 loss, Sec. 5 Adam): forward on d_x, mean
+ * L1 loss against d_target [n,H,W,3] written to d_loss (one float, device),
+ * backward (recompute policy of the handle), Adam update of d_params with
+ * moments d_m, d_v at step count t (>= 1), then repack of the weights.
+ * dL/dy = sign(y - t) / (n H W 3) with sign(0) = 0. d_dparams may be NULL;
+ * when given it receives the gradient used by the update. */
+drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, float* d_v, int64_t t,
+                        const drc_adam_cfg* adam, const float* d_x, const float* d_target,
+                        float* d_loss, float* d_dparams, int n, int H, int W, void* d_ws,
+                        size_t ws_bytes, void* stream);
+
+/* FP8 handles: static per-tensor activation scales (448 / max |value|) from
+ * a float32 forward over the calibration batch d_x. Must follow set_params.
+ * The scales of x, [u2|h1], [u3|h2] and h3 are kept in the handle. */
+drc_status drc_cae_calibrate_fp8(drc_cae* h, const float* d_x, int n, int H, int W, void* d_ws,
+                                 size_t ws_bytes, void* stream);
+
+/* Copy the FP8 scales to host memory: out[0..5] weight scales E1..D1,
+ * out[6..9] activation scales x, [u2|h1], [u3|h2], h3. Synchronises the
+ * stream. */
+drc_status drc_cae_get_fp8_scales(const drc_cae* h, float out[10], void* stream);
+
+/* Mixed-resolution frames (many maps of different sizes, one pass).
+ * plan_create sorts the maps into resolution classes, builds per-layer work
+ * lists (tile shapes per resolution from the tuning cache file, NULL =
+ * built-in defaults) and uploads them. plan_launch runs the whole frame as
+ * one captured HIP graph of persistent kernels on the given stream; the
+ * graph is recorded on the first launch for a given (workspace, stream,
+ * x, y) and replayed afterwards. */
+drc_status drc_cae_plan_create(drc_cae* h, const drc_map_desc* maps, int count,
+                               const char* tune_cache, drc_plan** out);
+drc_status drc_cae_plan_workspace_size(const drc_plan* p, size_t* bytes);
+drc_status drc_cae_plan_launch(drc_plan* p, const float* d_x_packed, float* d_y_packed, void* d_ws,
+                               size_t ws_bytes, void* stream);
+void drc_cae_plan_destroy(drc_plan* p);
+
+/* Tile-shape tuning: time each implemented tile shape of every layer for
+ * an n x H x W forward batch on the given stream and write the fastest to
+ * the JSON cache file path (keyed by arch, precision, layer and
+ * resolution). Synchronises the stream. */
+drc_status drc_cae_autotune(drc_cae* h, int n, int H, int W, const float* d_x, void* d_ws,
+                            size_t ws_bytes, const char* tune_cache, void* stream);
+
+/* Tile shape (pixel blocks of 16 per wave) the forward uses for layer
+ * 0..5 (E1..D1) at resolution H; 0 = built-in default. */
+drc_status drc_cae_set_tile(drc_cae* h, int layer, int H, int npw);
+
+/* Kernel timing (profiling hook). enable = 1 creates a pool of HIP events
+ * and records one event pair on the call's stream around each group of
+ * kernel launches (per layer and direction); enable = 0 stops. Reading
+ * waits for the recorded events, adds their elapsed times per slot
+ * (ms[24], calls[24]) and clears the record. Slots: 0..5 forward GEMM of
+ * E1..D1, 6..11 backward-data GEMM of E1..D1, 12..17 weight gradient of
+ * E1..D1, 18 bias gradients, 19 L1 loss, 20 Adam and repack. */
+drc_status drc_cae_profile(drc_cae* h, int enable);
+drc_status drc_cae_profile_read(drc_cae* h, double ms[24], int64_t calls[24]);
+
+const char* drc_status_string(drc_status s);
+const char* drc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DRC_CAE_H */

@@ -1,0 +1,131 @@
+"""PyTorch-facing wrapper: a handle object that owns its workspace tensors,
+and a torch.autograd.Function whose forward and backward are the library's
+drc_cae_forward / drc_cae_backward. PyTorch supplies memory and streams only.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+
+def _aligned_bytes(nbytes: int, device) -> torch.Tensor:
+    """A uint8 device buffer of nbytes whose data pointer is 256-byte aligned."""
+    buf = torch.empty(max(nbytes, 1) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + max(nbytes, 1)]
+
+
+class CAE:
+    """One autoencoder handle (compute dtype 'f32', 'bf16' or 'fp8')."""
+
+    def __init__(self, compute: str = "bf16", params: torch.Tensor | None = None, device="cuda",
+                 final_relu: bool = False, recompute: bool = False):
+        self.device = torch.device(device)
+        self.compute = compute
+        desc = B.drc_cae_default_desc(B.DTYPES[compute])
+        desc.final_relu = int(final_relu)
+        with torch.cuda.device(self.device):
+            self.h = B.drc_cae_create(desc)
+        self.num_params = B.drc_cae_num_params(self.h)
+        B.drc_cae_set_recompute(self.h, int(recompute))
+        self._ws = {}
+        self.params = None
+        if params is not None:
+            self.set_params(params)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            B.drc_cae_destroy(h)
+            self.h = None
+
+    def set_params(self, params: torch.Tensor):
+        assert params.dtype == torch.float32 and params.numel() == self.num_params
+        self.params = params.contiguous()
+        B.drc_cae_set_params(self.h, self.params)
+
+    def set_recompute(self, on: bool):
+        B.drc_cae_set_recompute(self.h, int(on))
+        self._ws.clear()
+
+    def workspace(self, n, H, W, flags):
+        key = (n, H, W, flags)
+        if key not in self._ws:
+            self._ws[key] = _aligned_bytes(B.drc_cae_workspace_size(self.h, n, H, W, flags), self.device)
+        return self._ws[key]
+
+    def saved_buffer(self, n, H, W):
+        nbytes, offsets = B.drc_cae_saved_size(self.h, n, H, W)
+        return _aligned_bytes(nbytes, self.device), offsets
+
+    def forward(self, x: torch.Tensor, y: torch.Tensor | None = None, saved=None):
+        n, H, W, _ = x.shape
+        if y is None:
+            y = torch.empty((n, H, W, 3), dtype=torch.float32, device=x.device)
+        ws = self.workspace(n, H, W, B.DRC_WS_FORWARD)
+        B.drc_cae_forward(self.h, x, y, saved, ws)
+        return y
+
+    __call__ = forward
+
+    def backward(self, x, dy, saved, dparams=None, want_dx=False):
+        n, H, W, _ = x.shape
+        if dparams is None:
+            dparams = torch.empty(self.num_params, dtype=torch.float32, device=x.device)
+        dx = torch.empty_like(x) if want_dx else None
+        ws = self.workspace(n, H, W, B.DRC_WS_BACKWARD)
+        B.drc_cae_backward(self.h, x, dy, saved, dparams, dx, ws)
+        return dparams, dx
+
+    def calibrate_fp8(self, x):
+        n, H, W, _ = x.shape
+        ws = self.workspace(n, H, W, B.DRC_WS_CALIBRATE)
+        B.drc_cae_calibrate_fp8(self.h, x, ws)
+
+
+class Trainer:
+    """Adam training on the device: one drc_cae_step per call."""
+
+    def __init__(self, cae: CAE, params: torch.Tensor, lr=6e-5, betas=(0.9, 0.999), eps=1e-8):
+        self.cae = cae
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.t = 0
+        self.adam = B.drc_adam_cfg(lr, betas[0], betas[1], eps)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        cae.set_params(params)
+
+    def step(self, x, target, dparams=None):
+        n, H, W, _ = x.shape
+        ws = self.cae.workspace(n, H, W, B.DRC_WS_STEP)
+        self.t += 1
+        B.drc_cae_step(self.cae.h, self.params, self.m, self.v, self.t, self.adam, x, target, self.loss,
+                       dparams, ws)
+        return self.loss
+
+
+class CAEFunction(torch.autograd.Function):
+    """y = CAE(x; params) with the library's forward and backward kernels.
+
+    The parameters must already be packed into the handle (cae.set_params);
+    the params tensor is an input only so that autograd routes its gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, x, params, cae: CAE):
+        x = x.contiguous()
+        n, H, W, _ = x.shape
+        saved, _ = cae.saved_buffer(n, H, W)
+        y = cae.forward(x, saved=saved)
+        ctx.cae = cae
+        ctx.saved = saved
+        ctx.save_for_backward(x)
+        return y
+
+    @staticmethod
+    def backward(ctx, dy):
+        (x,) = ctx.saved_tensors
+        dparams, dx = ctx.cae.backward(x, dy.contiguous(), ctx.saved, want_dx=ctx.needs_input_grad[0])
+        return dx, dparams, None

@@ -1,0 +1,112 @@
+// Device-side building blocks shared by every kernel of the library:
+// storage types per precision, round-to-nearest-even casts, and one MFMA
+// "K step" per precision for gfx950 (CDNA4, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace drc {
+
+enum Prec : int { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i8v __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------- casts
+// float -> bfloat16, round to nearest even; NaN stays NaN (quiet bit set).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u)
+        return (u & 0x007fffffu) ? (uint16_t)((u >> 16) | 0x40u) : (uint16_t)(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float((uint32_t)h << 16);
+}
+
+// float -> OCP FP8 E4M3 ("e4m3fn": bias 7, no infinities, 0x7f = NaN),
+// round to nearest even, saturating at +-448 (infinities saturate too).
+__device__ __forceinline__ uint8_t f32_to_e4m3(float f) {
+    const uint32_t u = __float_as_uint(f);
+    const uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
+    const float a = fabsf(f);
+    if (a != a) return sign | 0x7f;
+    if (a >= 448.0f) return sign | 0x7e;
+    if (a < 0.015625f) {                      // below 2^-6: subnormal grid of 2^-9
+        const int r = (int)rintf(a * 512.0f);   // exact scaling, RNE; r in [0, 8]
+        return sign | (uint8_t)r;               // r == 8 is the smallest normal
+    }
+    const uint32_t au = __float_as_uint(a);
+    int e = (int)((au >> 23) & 0xffu) - 127 + 7;
+    const uint32_t mant = au & 0x7fffffu;
+    uint32_t r = (mant + 0x7ffffu + ((mant >> 20) & 1u)) >> 20;  // keep 3 bits, RNE
+    if (r == 8) { r = 0; e += 1; }
+    return sign | (uint8_t)((e << 3) | r);
+}
+__device__ __forceinline__ float e4m3_to_f32(uint8_t v) {
+    const uint32_t s = (v & 0x80u) << 24;
+    const uint32_t e = (v >> 3) & 0xfu, m = v & 7u;
+    if (e == 15 && m == 7) return __uint_as_float(0x7fc00000u | s);
+    float a = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;
+    return __uint_as_float(__float_as_uint(a) | s);
+}
+
+// ---------------------------------------------------------------- precision traits
+// Storage of one activation / weight element, and the MFMA K step.
+// Lane l of a wave supplies, for one K step, VW consecutive K elements of
+// row (l % 16) of the A operand and of column (l % 16) of the B operand,
+// namely K positions [VW * (l / 16), VW * (l / 16) + VW). The K order inside
+// a step is private to the kernel: A and B only have to agree.
+template <int P> struct Traits;
+
+template <> struct Traits<P_F32> {
+    typedef float T;
+    static constexpr int KS = 16;   // K per step: 4 x v_mfma_f32_16x16x4_f32
+    static constexpr int VW = 4;
+    typedef f4 V;                   // 16 bytes per lane
+    __device__ static __forceinline__ void mma(f4& acc, const V& a, const V& b) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
+    }
+    __device__ static __forceinline__ T from_f32(float v, float) { return v; }
+    __device__ static __forceinline__ float to_f32(T v) { return v; }
+};
+
+template <> struct Traits<P_BF16> {
+    typedef uint16_t T;
+    static constexpr int KS = 32;   // v_mfma_f32_16x16x32_bf16
+    static constexpr int VW = 8;
+    typedef uint4 V;                // 16 bytes per lane
+    __device__ static __forceinline__ void mma(f4& acc, const V& a, const V& b) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                      __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+    }
+    __device__ static __forceinline__ T from_f32(float v, float) { return f32_to_bf16(v); }
+    __device__ static __forceinline__ float to_f32(T v) { return bf16_to_f32(v); }
+};
+
+template <> struct Traits<P_FP8> {
+    typedef uint8_t T;
+    static constexpr int KS = 128;  // v_mfma_scale_f32_16x16x128_f8f6f4, both operands e4m3
+    static constexpr int VW = 32;
+    typedef i8v V;                  // 32 bytes per lane
+    __device__ static __forceinline__ void mma(f4& acc, const V& a, const V& b) {
+        // formats 0/0 = e4m3 for A and B; E8M0 block scales 127 = 1.0
+        acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 0, 0, 0, 127, 0, 127);
+    }
+    // fp8 values are stored pre-multiplied by the tensor's scale s
+    __device__ static __forceinline__ T from_f32(float v, float s) { return f32_to_e4m3(v * s); }
+    __device__ static __forceinline__ float to_f32(T v) { return e4m3_to_f32(v); }
+};
+
+template <typename V> __device__ __forceinline__ V vzero() {
+    V v;
+    __builtin_memset(&v, 0, sizeof(V));
+    return v;
+}
+
+}  // namespace drc

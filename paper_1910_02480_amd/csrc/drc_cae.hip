@@ -1,0 +1,494 @@
+// Host side of libdrc_cae: argument validation, the handle and its packed
+// weights, workspace layout, and the launch sequences of the forward pass,
+// the backward pass and the training step. All kernels live in the headers
+// included below; nothing here computes on the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "drc_cae.h"
+#include "common.h"
+#include "conv_layer.h"
+#include "aux_kernels.h"
+#include "internal.h"
+
+using namespace drc;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+drc_status drc_fail(drc_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+extern "C" const char* drc_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char* drc_status_string(drc_status s) {
+    switch (s) {
+        case DRC_OK: return "DRC_OK";
+        case DRC_ERR_INVALID_ARG: return "DRC_ERR_INVALID_ARG";
+        case DRC_ERR_SHAPE: return "DRC_ERR_SHAPE";
+        case DRC_ERR_UNSUPPORTED: return "DRC_ERR_UNSUPPORTED";
+        case DRC_ERR_WORKSPACE: return "DRC_ERR_WORKSPACE";
+        case DRC_ERR_HIP: return "DRC_ERR_HIP";
+        case DRC_ERR_STATE: return "DRC_ERR_STATE";
+    }
+    return "DRC_ERR_UNKNOWN";
+}
+
+// ------------------------------------------------------------------ network table
+const LayerDef kLayers[6] = {
+    {false, 7, 32}, {false, 32, 64}, {false, 64, 128},
+    {true, 128, 64}, {true, 128, 32}, {true, 64, 3},
+};
+
+long layer_w_offset(int l) {
+    long off = 0;
+    for (int i = 0; i < l; ++i) off += (long)kLayers[i].cout * 9 * kLayers[i].cin + kLayers[i].cout;
+    return off;
+}
+long layer_b_offset(int l) { return layer_w_offset(l) + (long)kLayers[l].cout * 9 * kLayers[l].cin; }
+static const long kNumParams = 206819;
+
+int prec_ks(int prec) { return prec == P_F32 ? 16 : (prec == P_BF16 ? 32 : 128); }
+int prec_esize(int prec) { return prec == P_F32 ? 4 : (prec == P_BF16 ? 2 : 1); }
+static int rup(int v, int m) { return (v + m - 1) / m * m; }
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Forward / backward-data GEMM geometry of layer l.
+GemmGeom gemm_geom(int l, bool backward, int prec) {
+    const LayerDef& L = kLayers[l];
+    GemmGeom g;
+    if (!backward) {
+        g.mode = L.tconv ? M_TCONV : M_CONV;
+        g.cin_eff = (l == 0) ? 8 : L.cin;
+        g.rows = L.cout;
+    } else {
+        g.mode = L.tconv ? M_CONV : M_TCONV;
+        g.cin_eff = (l == 5) ? (prec == P_F32 ? 4 : 8) : L.cout;
+        g.rows = L.cin;
+    }
+    g.rows_pad = rup(g.rows, 16);
+    g.nphase = g.mode == M_TCONV ? 4 : 1;
+    g.kstride = rup((g.mode == M_TCONV ? 4 : 9) * g.cin_eff, prec_ks(prec));
+    return g;
+}
+
+// ------------------------------------------------------------------ create / destroy
+extern "C" drc_cae_desc drc_cae_default_desc(int compute) {
+    drc_cae_desc d;
+    d.in_ch = 7;
+    d.out_ch = 3;
+    d.widths[0] = 32;
+    d.widths[1] = 64;
+    d.widths[2] = 128;
+    d.compute = compute;
+    d.final_relu = 0;
+    return d;
+}
+
+extern "C" drc_status drc_cae_create(const drc_cae_desc* desc, drc_cae** out) {
+    if (!out) return drc_fail(DRC_ERR_INVALID_ARG, "create: out is NULL");
+    *out = nullptr;
+    if (!desc) return drc_fail(DRC_ERR_INVALID_ARG, "create: desc is NULL");
+    if (desc->in_ch != 7 || desc->out_ch != 3 || desc->widths[0] != 32 || desc->widths[1] != 64 ||
+        desc->widths[2] != 128)
+        return drc_fail(DRC_ERR_UNSUPPORTED, "create: only the 7->32->64->128->64->32->3 network is built");
+    if (desc->compute < DRC_F32 || desc->compute > DRC_FP8_E4M3)
+        return drc_fail(DRC_ERR_INVALID_ARG, "create: unknown compute dtype %d", desc->compute);
+    if (desc->final_relu != 0 && desc->final_relu != 1)
+        return drc_fail(DRC_ERR_INVALID_ARG, "create: final_relu must be 0 or 1");
+    drc_cae* h = new drc_cae();
+    h->desc = *desc;
+    h->prec = desc->compute;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return drc_fail(DRC_ERR_HIP, "create: hipGetDevice failed");
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) {
+        h->arch = prop.gcnArchName;
+        h->num_cu = prop.multiProcessorCount;
+    }
+    auto alloc = [&](void** p, size_t bytes) -> bool {
+        return hipMalloc(p, align256(bytes)) == hipSuccess;
+    };
+    bool ok = true;
+    for (int l = 0; l < 6 && ok; ++l) {
+        GemmGeom gf = gemm_geom(l, false, h->prec);
+        h->wf_bytes[l] = (size_t)gf.nphase * gf.rows_pad * gf.kstride * prec_esize(h->prec);
+        ok = alloc(&h->wf[l], h->wf_bytes[l]);
+        if (ok && h->prec != P_FP8) {
+            GemmGeom gb = gemm_geom(l, true, h->prec);
+            h->wb_bytes[l] = (size_t)gb.nphase * gb.rows_pad * gb.kstride * prec_esize(h->prec);
+            ok = alloc(&h->wb[l], h->wb_bytes[l]);
+        }
+        if (ok && h->prec == P_FP8) {  // float32 packs for the calibration forward
+            GemmGeom gc = gemm_geom(l, false, P_F32);
+            ok = alloc(&h->wcal[l], (size_t)gc.nphase * gc.rows_pad * gc.kstride * 4);
+        }
+    }
+    ok = ok && alloc((void**)&h->bias, 512 * sizeof(float));
+    ok = ok && alloc((void**)&h->scales, 16 * sizeof(float));
+    ok = ok && alloc((void**)&h->amax, 16 * sizeof(unsigned));
+    if (!ok) {
+        drc_cae_destroy(h);
+        return drc_fail(DRC_ERR_HIP, "create: device allocation failed");
+    }
+    for (int i = 0; i < 16; ++i) h->host_scales[i] = 1.0f;
+    *out = h;
+    return DRC_OK;
+}
+
+extern "C" void drc_cae_destroy(drc_cae* h) {
+    if (!h) return;
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    for (int l = 0; l < 6; ++l) {
+        if (h->wf[l]) (void)hipFree(h->wf[l]);
+        if (h->wb[l]) (void)hipFree(h->wb[l]);
+        if (h->wcal[l]) (void)hipFree(h->wcal[l]);
+    }
+    if (h->bias) (void)hipFree(h->bias);
+    if (h->scales) (void)hipFree(h->scales);
+    if (h->amax) (void)hipFree(h->amax);
+    delete h;
+}
+
+extern "C" size_t drc_cae_num_params(const drc_cae* h) { return h ? (size_t)kNumParams : 0; }
+
+extern "C" drc_status drc_cae_set_recompute(drc_cae* h, int on) {
+    if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "set_recompute: handle is NULL");
+    if (on != 0 && on != 1) return drc_fail(DRC_ERR_INVALID_ARG, "set_recompute: on must be 0 or 1");
+    h->recompute = on;
+    return DRC_OK;
+}
+
+extern "C" drc_status drc_cae_set_tile(drc_cae* h, int layer, int H, int npw) {
+    if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "set_tile: handle is NULL");
+    if (layer < 0 || layer > 5) return drc_fail(DRC_ERR_INVALID_ARG, "set_tile: layer %d", layer);
+    if (npw != 0 && !npw_supported(h->prec, layer, false, npw))
+        return drc_fail(DRC_ERR_UNSUPPORTED, "set_tile: npw %d not built for layer %d", npw, layer);
+    if (npw == 0)
+        h->tile.erase({layer, H});
+    else
+        h->tile[{layer, H}] = npw;
+    return DRC_OK;
+}
+
+// ------------------------------------------------------------------ validation
+static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+drc_status check_shape(const char* who, int n, int H, int W) {
+    if (n < 1) return drc_fail(DRC_ERR_SHAPE, "%s: n = %d (must be >= 1)", who, n);
+    if (H < 8 || W < 8 || H % 8 || W % 8)
+        return drc_fail(DRC_ERR_SHAPE, "%s: H = %d, W = %d (must be multiples of 8, >= 8)", who, H, W);
+    if ((long)n * H * W > (1L << 31) / 8)
+        return drc_fail(DRC_ERR_SHAPE, "%s: n*H*W = %ld too large", who, (long)n * H * W);
+    return DRC_OK;
+}
+
+drc_status check_ptr(const char* who, const char* name, const void* p, size_t align, bool nullable) {
+    if (!p) return nullable ? DRC_OK : drc_fail(DRC_ERR_INVALID_ARG, "%s: %s is NULL", who, name);
+    if (!aligned(p, align))
+        return drc_fail(DRC_ERR_INVALID_ARG, "%s: %s not %zu-byte aligned", who, name, align);
+    return DRC_OK;
+}
+
+#define TRY(expr)                        \
+    do {                                 \
+        drc_status s_ = (expr);          \
+        if (s_ != DRC_OK) return s_;     \
+    } while (0)
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return drc_fail(DRC_ERR_HIP, "%s:%d %s: %s", __FILE__, __LINE__, #expr,           \
+                            hipGetErrorString(e_));                                           \
+    } while (0)
+
+drc_status check_launch(const char* who) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return drc_fail(DRC_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
+    return DRC_OK;
+}
+
+// ------------------------------------------------------------------ activations / workspace
+ActSizes act_sizes(int prec, int n, int H, int W) {
+    ActSizes a;
+    const long p1 = (long)n * (H / 2) * (W / 2), p2 = (long)n * (H / 4) * (W / 4),
+               p3 = (long)n * (H / 8) * (W / 8);
+    const int es = prec_esize(prec);
+    a.p0 = (long)n * H * W;
+    a.p1 = p1;
+    a.p2 = p2;
+    a.p3 = p3;
+    a.bytes[0] = align256(p1 * 32 * es);   // h1
+    a.bytes[1] = align256(p2 * 64 * es);   // h2
+    a.bytes[2] = align256(p3 * 128 * es);  // h3
+    a.bytes[3] = align256(p2 * 64 * es);   // u3
+    a.bytes[4] = align256(p1 * 32 * es);   // u2
+    return a;
+}
+
+// Saved-buffer layout under a recompute policy: offsets of h1..u2 (-1 = not saved).
+static size_t saved_layout(const ActSizes& a, int recompute, int64_t off[5]) {
+    size_t cur = 0;
+    for (int k = 0; k < 5; ++k) {
+        if (recompute && k >= 2) {
+            off[k] = -1;
+            continue;
+        }
+        off[k] = (int64_t)cur;
+        cur += a.bytes[k];
+    }
+    return cur;
+}
+
+extern "C" drc_status drc_cae_saved_size(const drc_cae* h, int n, int H, int W, size_t* bytes,
+                                         int64_t offsets[5]) {
+    if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "saved_size: handle is NULL");
+    if (!bytes) return drc_fail(DRC_ERR_INVALID_ARG, "saved_size: bytes is NULL");
+    TRY(check_shape("saved_size", n, H, W));
+    int64_t off[5];
+    *bytes = saved_layout(act_sizes(h->prec, n, H, W), h->recompute, off);
+    if (offsets)
+        for (int k = 0; k < 5; ++k) offsets[k] = off[k];
+    return DRC_OK;
+}
+
+// Weight-gradient reduction split for layer l: pixels per workgroup.
+void wgrad_split(int l, int n, int H, int W, long* per_block, int* nchunks) {
+    const LayerDef& L = kLayers[l];
+    int hin, win, hout, wout;
+    layer_io(l, H, W, &hin, &win, &hout, &wout);
+    const long K = (long)n * (L.tconv ? (long)hin * win : (long)hout * wout);
+    const int tiles = ((L.cout + 63) / 64) * ((L.cin + 63) / 64);
+    long want = std::max(1L, 2048L / (9L * tiles));
+    long pb = (K + want - 1) / want;
+    pb = std::max(256L, (pb + 15) / 16 * 16);
+    *per_block = pb;
+    *nchunks = (int)((K + pb - 1) / pb);
+}
+
+void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout) {
+    static const int din[6] = {1, 2, 4, 8, 4, 2};   // input = H / din
+    static const int dout[6] = {2, 4, 8, 4, 2, 1};  // output = H / dout
+    *hin = H / din[l];
+    *win = W / din[l];
+    *hout = H / dout[l];
+    *wout = W / dout[l];
+}
+
+static const long kBiasPerBlock = 1024;
+static const long kLossPerBlock = 16384;
+
+// Backward workspace: [recompute h3 u3 u2] [gradients] [wgrad partials] [bias partials]
+BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed) {
+    BwdLayout b;
+    ActSizes a = act_sizes(prec, n, H, W);
+    const int es = prec_esize(prec);
+    size_t cur = 0;
+    for (int k = 0; k < 3; ++k) b.recomp[k] = 0;
+    if (recompute_needed) {
+        b.recomp[0] = cur; cur += a.bytes[2];  // h3
+        b.recomp[1] = cur; cur += a.bytes[3];  // u3
+        b.recomp[2] = cur; cur += a.bytes[4];  // u2
+    }
+    b.dz_u2 = cur; cur += align256(a.p1 * 32 * es);
+    b.dh1s = cur; cur += align256(a.p1 * 32 * es);
+    b.dz_u3 = cur; cur += align256(a.p2 * 64 * es);
+    b.dh2s = cur; cur += align256(a.p2 * 64 * es);
+    b.dz_h3 = cur; cur += align256(a.p3 * 128 * es);
+    b.dz_h2 = cur; cur += align256(a.p2 * 64 * es);
+    b.dz_h1 = cur; cur += align256(a.p1 * 32 * es);
+    size_t wp = 0, bp = 0;
+    for (int l = 0; l < 6; ++l) {
+        long pb;
+        int nch;
+        wgrad_split(l, n, H, W, &pb, &nch);
+        wp = std::max(wp, (size_t)nch * 4 * 9 * kLayers[l].cout * kLayers[l].cin * sizeof(float));
+        int hin, win, hout, wout;
+        layer_io(l, H, W, &hin, &win, &hout, &wout);
+        const long np = (long)n * hout * wout;
+        const long nb = (np + kBiasPerBlock - 1) / kBiasPerBlock;
+        bp = std::max(bp, (size_t)nb * kLayers[l].cout * sizeof(float));
+    }
+    b.wpart = cur; cur += align256(wp);
+    b.bpart = cur; cur += align256(bp);
+    b.total = cur;
+    return b;
+}
+
+// Step workspace: [saved] [fwd scratch acts] [y] [dy] [loss partials] [dparams] [bwd]
+StepLayout step_layout(int prec, int n, int H, int W, int recompute) {
+    StepLayout s;
+    ActSizes a = act_sizes(prec, n, H, W);
+    int64_t off[5];
+    size_t cur = 0;
+    s.saved = cur;
+    cur += saved_layout(a, recompute, off);
+    s.fwd_scratch = cur;
+    if (recompute) cur += a.bytes[2] + a.bytes[3] + a.bytes[4];
+    s.y = cur; cur += align256(a.p0 * 3 * sizeof(float));
+    s.dy = cur; cur += align256(a.p0 * 3 * sizeof(float));
+    s.loss_part = cur;
+    cur += align256(((a.p0 * 3 + kLossPerBlock - 1) / kLossPerBlock) * sizeof(double));
+    s.dparams = cur; cur += align256(kNumParams * sizeof(float));
+    s.bwd = cur;
+    cur += bwd_layout(prec, n, H, W, recompute != 0).total;
+    s.total = cur;
+    return s;
+}
+
+extern "C" drc_status drc_cae_workspace_size(const drc_cae* h, int n, int H, int W, int flags,
+                                             size_t* bytes) {
+    if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "workspace_size: handle is NULL");
+    if (!bytes) return drc_fail(DRC_ERR_INVALID_ARG, "workspace_size: bytes is NULL");
+    if (flags & ~(DRC_WS_FORWARD | DRC_WS_BACKWARD | DRC_WS_STEP | DRC_WS_CALIBRATE) || !flags)
+        return drc_fail(DRC_ERR_INVALID_ARG, "workspace_size: bad flags 0x%x", flags);
+    TRY(check_shape("workspace_size", n, H, W));
+    size_t need = 0;
+    ActSizes a = act_sizes(h->prec, n, H, W);
+    if (flags & DRC_WS_FORWARD) {
+        size_t f = 0;
+        for (int k = 0; k < 5; ++k) f += a.bytes[k];
+        need = std::max(need, f);
+    }
+    if (flags & DRC_WS_BACKWARD) need = std::max(need, bwd_layout(h->prec, n, H, W, true).total);
+    if (flags & DRC_WS_STEP) need = std::max(need, step_layout(h->prec, n, H, W, h->recompute).total);
+    if (flags & DRC_WS_CALIBRATE) {
+        ActSizes c = act_sizes(P_F32, n, H, W);
+        size_t f = align256((size_t)c.p0 * 3 * sizeof(float));
+        for (int k = 0; k < 5; ++k) f += c.bytes[k];
+        need = std::max(need, f);
+    }
+    *bytes = need;
+    return DRC_OK;
+}
+
+// ------------------------------------------------------------------ parameter packing
+static drc_status pack_all(drc_cae* h, const float* d_params, hipStream_t s) {
+    // biases (float32 copy, at the bias offsets of a compact array)
+    for (int l = 0; l < 6; ++l) {
+        HIPCHK(hipMemcpyAsync(h->bias + bias_slot(l), d_params + layer_b_offset(l),
+                              kLayers[l].cout * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    if (h->prec == P_FP8) {
+        HIPCHK(hipMemsetAsync(h->amax, 0, 16 * sizeof(unsigned), s));
+        for (int l = 0; l < 6; ++l) {
+            const long cnt = (long)kLayers[l].cout * 9 * kLayers[l].cin;
+            hipLaunchKernelGGL(amax_f32_kernel, dim3(64), dim3(256), 0, s, d_params + layer_w_offset(l), cnt,
+                               h->amax + l);
+        }
+        hipLaunchKernelGGL(fp8_scale_kernel, dim3(1), dim3(64), 0, s, (const unsigned*)h->amax, h->scales, 6);
+        TRY(check_launch("set_params/fp8 scales"));
+    }
+    for (int l = 0; l < 6; ++l) {
+        for (int dir = 0; dir < 3; ++dir) {
+            void* dst = dir == 0 ? h->wf[l] : (dir == 1 ? h->wb[l] : h->wcal[l]);
+            if (!dst) continue;
+            const int prec = dir == 2 ? P_F32 : h->prec;
+            GemmGeom g = gemm_geom(l, dir == 1, prec);
+            PackArgs a;
+            a.w = d_params + layer_w_offset(l);
+            a.cout = kLayers[l].cout;
+            a.cin = kLayers[l].cin;
+            a.gemm_mode = g.mode;
+            a.transpose = dir == 1;
+            a.cin_eff = g.cin_eff;
+            a.rows_pad = g.rows_pad;
+            a.kstride = g.kstride;
+            a.nphase = g.nphase;
+            a.prec = prec;
+            a.scale = prec == P_FP8 ? h->scales + l : nullptr;
+            a.dst = dst;
+            const long total = (long)g.nphase * g.rows_pad * g.kstride;
+            const int blocks = (int)std::min(1024L, (total + 255) / 256);
+            hipLaunchKernelGGL(pack_weights_kernel, dim3(blocks), dim3(256), 0, s, a);
+        }
+    }
+    TRY(check_launch("set_params/pack"));
+    return DRC_OK;
+}
+
+extern "C" drc_status drc_cae_set_params(drc_cae* h, const float* d_params, void* stream) {
+    if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "set_params: handle is NULL");
+    TRY(check_ptr("set_params", "d_params", d_params, 4, false));
+    hipStream_t s = (hipStream_t)stream;
+    TRY(pack_all(h, d_params, s));
+    if (h->prec == P_FP8) {
+        HIPCHK(hipMemcpyAsync(h->host_scales, h->scales, 6 * sizeof(float), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    h->params_set = true;
+    h->packed_from = d_params;
+    return DRC_OK;
+}
+
+extern "C" drc_status drc_cae_get_fp8_scales(const drc_cae* h, float out[10], void* stream) {
+    if (!h || !out) return drc_fail(DRC_ERR_INVALID_ARG, "get_fp8_scales: NULL argument");
+    if (h->prec != P_FP8) return drc_fail(DRC_ERR_STATE, "get_fp8_scales: not an FP8 handle");
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    for (int i = 0; i < 10; ++i) out[i] = h->host_scales[i];
+    return DRC_OK;
+}
+
+// ------------------------------------------------------------------ profiling hook
+long prof_begin(drc_cae* h, int slot, hipStream_t s) {
+    if (!h->prof || h->ev_next + 2 > h->ev_pool.size()) return -1;
+    const size_t k = h->ev_next;
+    h->ev_next += 2;
+    if (hipEventRecord(h->ev_pool[k], s) != hipSuccess) return -1;
+    h->prof_rec.push_back({slot, k});
+    return (long)k;
+}
+
+void prof_end(drc_cae* h, long token, hipStream_t s) {
+    if (token < 0) return;
+    (void)hipEventRecord(h->ev_pool[(size_t)token + 1], s);
+}
+
+extern "C" drc_status drc_cae_profile(drc_cae* h, int enable) {
+    if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "profile: handle is NULL");
+    if (enable && h->ev_pool.empty()) {
+        h->ev_pool.resize(16384);
+        for (auto& e : h->ev_pool)
+            if (hipEventCreate(&e) != hipSuccess) return drc_fail(DRC_ERR_HIP, "profile: hipEventCreate failed");
+    }
+    h->prof = enable != 0;
+    return DRC_OK;
+}
+
+extern "C" drc_status drc_cae_profile_read(drc_cae* h, double ms[24], int64_t calls[24]) {
+    if (!h || !ms || !calls) return drc_fail(DRC_ERR_INVALID_ARG, "profile_read: NULL argument");
+    for (int i = 0; i < PROF_SLOTS; ++i) {
+        ms[i] = 0.0;
+        calls[i] = 0;
+    }
+    for (auto& r : h->prof_rec) {
+        if (hipEventSynchronize(h->ev_pool[r.second + 1]) != hipSuccess)
+            return drc_fail(DRC_ERR_HIP, "profile_read: event wait failed");
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, h->ev_pool[r.second], h->ev_pool[r.second + 1]) != hipSuccess)
+            return drc_fail(DRC_ERR_HIP, "profile_read: elapsed time failed");
+        ms[r.first] += t;
+        calls[r.first] += 1;
+    }
+    h->prof_rec.clear();
+    h->ev_next = 0;
+    return DRC_OK;
+}

@@ -1,0 +1,102 @@
+// Library-internal declarations shared by the host translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "drc_cae.h"
+
+struct LayerDef {
+    bool tconv;
+    int cin, cout;
+};
+extern const LayerDef kLayers[6];
+
+// Geometry of one layer GEMM (forward or backward-data).
+struct GemmGeom {
+    int mode;      // drc::M_CONV / drc::M_TCONV
+    int cin_eff;   // K elements per tap
+    int rows;      // GEMM rows (output channels)
+    int rows_pad;  // rows padded to 16
+    int nphase;    // 1 or 4
+    int kstride;   // K elements per packed row (padded to the MFMA K step)
+};
+
+struct drc_cae {
+    drc_cae_desc desc;
+    int prec = 0;
+    int device = 0;
+    std::string arch;
+    int num_cu = 256;
+    void* wf[6] = {};      // forward packs
+    void* wb[6] = {};      // backward-data (transposed) packs
+    void* wcal[6] = {};    // float32 forward packs of FP8 handles (calibration)
+    size_t wf_bytes[6] = {}, wb_bytes[6] = {};
+    float* bias = nullptr; // float32 biases, layer l at bias_slot(l)
+    float* scales = nullptr;   // [0..5] weight scales, [6..9] activation scales (FP8)
+    unsigned* amax = nullptr;  // scratch for amax reductions
+    float host_scales[16];
+    int recompute = 0;
+    bool params_set = false;
+    bool calibrated = false;
+    const float* packed_from = nullptr;
+    std::map<std::pair<int, int>, int> tile;  // (layer, H) -> pixel blocks per wave
+    // optional timing of kernel groups with events on the caller's stream
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_next = 0;
+    std::vector<std::pair<int, size_t>> prof_rec;  // (slot, index of the start event)
+};
+
+// Timing slots (drc_cae_profile_read): 0..5 forward GEMM of E1..D1,
+// 6..11 backward-data GEMM of E1..D1, 12..17 weight gradient of E1..D1,
+// 18 bias gradients, 19 L1 loss, 20 Adam and repack.
+enum { PROF_FWD = 0, PROF_BWD = 6, PROF_WGRAD = 12, PROF_BIAS = 18, PROF_LOSS = 19, PROF_ADAM = 20,
+       PROF_SLOTS = 24 };
+// Records the start event of a slot; returns a token for prof_end (or -1).
+long prof_begin(drc_cae* h, int slot, hipStream_t s);
+void prof_end(drc_cae* h, long token, hipStream_t s);
+
+struct ActSizes {
+    long p0, p1, p2, p3;  // pixels at H, H/2, H/4, H/8 (whole batch)
+    size_t bytes[5];      // h1 h2 h3 u3 u2
+};
+
+struct BwdLayout {
+    size_t recomp[3];
+    size_t dz_u2, dh1s, dz_u3, dh2s, dz_h3, dz_h2, dz_h1;
+    size_t wpart, bpart, total;
+};
+
+struct StepLayout {
+    size_t saved, fwd_scratch, y, dy, loss_part, dparams, bwd, total;
+};
+
+drc_status drc_fail(drc_status s, const char* fmt, ...);
+drc_status check_shape(const char* who, int n, int H, int W);
+drc_status check_ptr(const char* who, const char* name, const void* p, size_t align, bool nullable);
+drc_status check_launch(const char* who);
+
+long layer_w_offset(int l);
+long layer_b_offset(int l);
+inline int bias_slot(int l) {
+    static const int off[6] = {0, 32, 96, 224, 288, 320};
+    return off[l];
+}
+int prec_ks(int prec);
+int prec_esize(int prec);
+size_t align256(size_t v);
+GemmGeom gemm_geom(int l, bool backward, int prec);
+ActSizes act_sizes(int prec, int n, int H, int W);
+void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout);
+void wgrad_split(int l, int n, int H, int W, long* per_block, int* nchunks);
+BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed);
+StepLayout step_layout(int prec, int n, int H, int W, int recompute);
+
+// Tile shapes: pixel blocks of 16 per wave built for each layer GEMM.
+bool npw_supported(int prec, int layer, bool backward, int npw);
+int default_npw(int prec, int layer, bool backward);

@@ -1,0 +1,670 @@
+// Launch sequences of the autoencoder: forward (Sec. 4.3), backward, the
+// training step (L1 loss, Sec. 4.3; Adam, Sec. 5) and FP8 calibration.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "drc_cae.h"
+#include "common.h"
+#include "conv_layer.h"
+#include "aux_kernels.h"
+#include "internal.h"
+
+using namespace drc;
+
+#define TRY(expr)                    \
+    do {                             \
+        drc_status s_ = (expr);      \
+        if (s_ != DRC_OK) return s_; \
+    } while (0)
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return drc_fail(DRC_ERR_HIP, "%s:%d %s: %s", __FILE__, __LINE__, #expr,           \
+                            hipGetErrorString(e_));                                           \
+    } while (0)
+
+// ------------------------------------------------------------------ tile shapes
+static int rows_pad_of(int layer, bool backward) {
+    const int rows = backward ? kLayers[layer].cin : kLayers[layer].cout;
+    return (rows + 15) / 16 * 16;
+}
+
+bool npw_supported(int prec, int layer, bool backward, int npw) {
+    if (npw != 1 && npw != 2 && npw != 4 && npw != 8) return false;
+    if (backward && prec == P_FP8) return false;
+    return (rows_pad_of(layer, backward) / 16) * npw <= 16;
+}
+
+int default_npw(int prec, int layer, bool backward) {
+    (void)prec;
+    const int mt = rows_pad_of(layer, backward) / 16;
+    return mt >= 8 ? 2 : (mt >= 4 ? 4 : (mt >= 2 ? 4 : 8));
+}
+
+// ------------------------------------------------------------------ GEMM dispatch
+template <int P, int MODE, int CIN, int COUTP, int NPW, bool RAW, bool OF32>
+static void launch_one(const LayerArgs& a, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL((conv_layer_kernel<P, MODE, CIN, COUTP, NPW, RAW, OF32>), grid, dim3(256), 0, s, a);
+}
+
+template <int P, int MODE, int CIN, int COUTP, bool RAW, bool OF32>
+static drc_status launch_gemm(const LayerArgs& a, int npw, long npix, hipStream_t s) {
+    constexpr int MT = COUTP / 16;
+    const long per = 64L * npw;
+    dim3 grid((unsigned)((npix + per - 1) / per), MODE == M_TCONV ? 4 : 1);
+    switch (npw) {
+        case 1:
+            if constexpr (MT * 1 <= 16) { launch_one<P, MODE, CIN, COUTP, 1, RAW, OF32>(a, grid, s); return check_launch("gemm"); }
+            break;
+        case 2:
+            if constexpr (MT * 2 <= 16) { launch_one<P, MODE, CIN, COUTP, 2, RAW, OF32>(a, grid, s); return check_launch("gemm"); }
+            break;
+        case 4:
+            if constexpr (MT * 4 <= 16) { launch_one<P, MODE, CIN, COUTP, 4, RAW, OF32>(a, grid, s); return check_launch("gemm"); }
+            break;
+        case 8:
+            if constexpr (MT * 8 <= 16) { launch_one<P, MODE, CIN, COUTP, 8, RAW, OF32>(a, grid, s); return check_launch("gemm"); }
+            break;
+    }
+    return drc_fail(DRC_ERR_UNSUPPORTED, "gemm: tile npw=%d not built", npw);
+}
+
+template <int P>
+static drc_status run_gemm(int layer, bool bwd, const LayerArgs& a, int npw, hipStream_t s) {
+    const long npix = (long)a.nmaps * a.Hg * a.Wg;
+    if (!bwd) {
+        switch (layer) {
+            case 0: return launch_gemm<P, M_CONV, 8, 32, true, false>(a, npw, npix, s);
+            case 1: return launch_gemm<P, M_CONV, 32, 64, false, false>(a, npw, npix, s);
+            case 2: return launch_gemm<P, M_CONV, 64, 128, false, false>(a, npw, npix, s);
+            case 3: return launch_gemm<P, M_TCONV, 128, 64, false, false>(a, npw, npix, s);
+            case 4: return launch_gemm<P, M_TCONV, 128, 32, false, false>(a, npw, npix, s);
+            case 5: return launch_gemm<P, M_TCONV, 64, 16, false, true>(a, npw, npix, s);
+        }
+    } else {
+        if constexpr (P == P_FP8) {
+            return drc_fail(DRC_ERR_UNSUPPORTED, "backward: FP8 is inference only");
+        } else {
+            constexpr int D1C = (P == P_F32) ? 4 : 8;
+            switch (layer) {
+                case 5: return launch_gemm<P, M_CONV, D1C, 64, true, false>(a, npw, npix, s);
+                case 4: return launch_gemm<P, M_CONV, 32, 128, false, false>(a, npw, npix, s);
+                case 3: return launch_gemm<P, M_CONV, 64, 128, false, false>(a, npw, npix, s);
+                case 2: return launch_gemm<P, M_TCONV, 128, 64, false, false>(a, npw, npix, s);
+                case 1: return launch_gemm<P, M_TCONV, 64, 32, false, false>(a, npw, npix, s);
+                case 0: return launch_gemm<P, M_TCONV, 32, 16, false, true>(a, npw, npix, s);
+            }
+        }
+    }
+    return drc_fail(DRC_ERR_INVALID_ARG, "gemm: layer %d", layer);
+}
+
+static Seg seg_none() {
+    Seg s;
+    memset(&s, 0, sizeof s);
+    s.qscale = 1.0f;
+    return s;
+}
+static Seg seg_out(void* dst, int c, int relu, float qscale) {
+    Seg s = seg_none();
+    s.dst = dst;
+    s.c = c;
+    s.ld = c;
+    s.relu = relu;
+    s.qscale = qscale;
+    return s;
+}
+
+static LayerArgs base_args(int l, int n, int H, int W, bool bwd, const void* wpack, int kstride) {
+    LayerArgs a;
+    memset(&a, 0, sizeof a);
+    int hin, win, hout, wout;
+    layer_io(l, H, W, &hin, &win, &hout, &wout);
+    if (bwd) {  // the data gradient runs from the layer output back to its input
+        std::swap(hin, hout);
+        std::swap(win, wout);
+    }
+    const bool gemm_tconv = kLayers[l].tconv != bwd;
+    a.nmaps = n;
+    a.Hin = hin;
+    a.Win = win;
+    a.Hout = hout;
+    a.Wout = wout;
+    a.Hg = gemm_tconv ? hin : hout;
+    a.Wg = gemm_tconv ? win : wout;
+    a.wpack = wpack;
+    a.kstride = kstride;
+    a.acc_scale = 1.0f;
+    a.raw_qscale = 1.0f;
+    a.seg0 = seg_none();
+    a.seg1 = seg_none();
+    return a;
+}
+
+static int pick_npw(const drc_cae* h, int l, int H, int prec, bool bwd) {
+    if (!bwd) {
+        auto it = h->tile.find({l, H});
+        if (it != h->tile.end()) return it->second;
+    }
+    return default_npw(prec, l, bwd);
+}
+
+// ------------------------------------------------------------------ forward
+struct FwdBufs {
+    const float* x;
+    float* y;
+    void *h1, *h2, *h3, *u3, *u2;
+};
+
+// FP8 scale slots: 0..5 weights, 6 x, 7 [u2|h1], 8 [u3|h2], 9 h3.
+static const int kInScale[6] = {6, 7, 8, 9, 8, 7};
+static const int kOutScale[6] = {7, 8, 9, 8, 7, -1};
+
+// Runs layers [l0, l1] of the forward pass in precision P with packs.
+template <int P>
+static drc_status forward_seq(drc_cae* h, void* const* packs, const FwdBufs& b, int n, int H, int W,
+                              int l0, int l1, hipStream_t s) {
+    const float* sc = h->host_scales;
+    for (int l = l0; l <= l1; ++l) {
+        const GemmGeom g = gemm_geom(l, false, P);
+        LayerArgs a = base_args(l, n, H, W, false, packs[l], g.kstride);
+        a.bias = h->bias + bias_slot(l);
+        float qout = 1.0f;
+        if (P == P_FP8) {
+            a.acc_scale = 1.0f / (sc[kInScale[l]] * sc[l]);
+            if (kOutScale[l] >= 0) qout = sc[kOutScale[l]];
+        }
+        switch (l) {
+            case 0:
+                a.s0 = {b.x, 8, 7};
+                a.raw_c = 7;
+                a.raw_qscale = P == P_FP8 ? sc[6] : 1.0f;
+                a.seg0 = seg_out(b.h1, 32, 1, qout);
+                break;
+            case 1:
+                a.s0 = {b.h1, 32, 32};
+                a.seg0 = seg_out(b.h2, 64, 1, qout);
+                break;
+            case 2:
+                a.s0 = {b.h2, 64, 64};
+                a.seg0 = seg_out(b.h3, 128, 1, qout);
+                break;
+            case 3:
+                a.s0 = {b.h3, 128, 128};
+                a.seg0 = seg_out(b.u3, 64, 1, qout);
+                break;
+            case 4:
+                a.s0 = {b.u3, 64, 64};
+                a.s1 = {b.h2, 64, 64};
+                a.seg0 = seg_out(b.u2, 32, 1, qout);
+                break;
+            case 5:
+                a.s0 = {b.u2, 32, 32};
+                a.s1 = {b.h1, 32, 32};
+                a.seg0 = seg_out(b.y, 3, h->desc.final_relu, 1.0f);
+                break;
+        }
+        const long tok = prof_begin(h, PROF_FWD + l, s);
+        TRY(run_gemm<P>(l, false, a, pick_npw(h, l, H, P, false), s));
+        prof_end(h, tok, s);
+    }
+    return DRC_OK;
+}
+
+static drc_status forward_dispatch(drc_cae* h, const FwdBufs& b, int n, int H, int W, int l0, int l1,
+                                   hipStream_t s) {
+    switch (h->prec) {
+        case P_F32: return forward_seq<P_F32>(h, h->wf, b, n, H, W, l0, l1, s);
+        case P_BF16: return forward_seq<P_BF16>(h, h->wf, b, n, H, W, l0, l1, s);
+        case P_FP8: return forward_seq<P_FP8>(h, h->wf, b, n, H, W, l0, l1, s);
+    }
+    return drc_fail(DRC_ERR_STATE, "bad precision");
+}
+
+static drc_status check_ready(const drc_cae* h, const char* who) {
+    if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "%s: handle is NULL", who);
+    if (!h->params_set) return drc_fail(DRC_ERR_STATE, "%s: call drc_cae_set_params first", who);
+    if (h->prec == P_FP8 && !h->calibrated)
+        return drc_fail(DRC_ERR_STATE, "%s: FP8 handle needs drc_cae_calibrate_fp8 first", who);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != h->device)
+        return drc_fail(DRC_ERR_STATE, "%s: current device %d is not the handle's device %d", who, dev,
+                        h->device);
+    return DRC_OK;
+}
+
+extern "C" drc_status drc_cae_forward(drc_cae* h, const float* d_x, float* d_y, int n, int H, int W,
+                                      void* d_saved, void* d_ws, size_t ws_bytes, void* stream) {
+    TRY(check_ready(h, "forward"));
+    TRY(check_shape("forward", n, H, W));
+    TRY(check_ptr("forward", "d_x", d_x, 16, false));
+    TRY(check_ptr("forward", "d_y", d_y, 16, false));
+    TRY(check_ptr("forward", "d_saved", d_saved, 256, true));
+    TRY(check_ptr("forward", "d_ws", d_ws, 256, false));
+    size_t need = 0;
+    TRY(drc_cae_workspace_size(h, n, H, W, DRC_WS_FORWARD, &need));
+    if (ws_bytes < need)
+        return drc_fail(DRC_ERR_WORKSPACE, "forward: workspace %zu < %zu bytes", ws_bytes, need);
+    ActSizes a = act_sizes(h->prec, n, H, W);
+    char* ws = (char*)d_ws;
+    void* act[5];
+    size_t cur = 0;
+    for (int k = 0; k < 5; ++k) {
+        act[k] = ws + cur;
+        cur += a.bytes[k];
+    }
+    if (d_saved) {
+        size_t sb;
+        int64_t off[5];
+        TRY(drc_cae_saved_size(h, n, H, W, &sb, off));
+        for (int k = 0; k < 5; ++k)
+            if (off[k] >= 0) act[k] = (char*)d_saved + off[k];
+    }
+    FwdBufs b{d_x, d_y, act[0], act[1], act[2], act[3], act[4]};
+    return forward_dispatch(h, b, n, H, W, 0, 5, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ backward
+template <typename T>
+static drc_status bias_grad(const void* g, bool g_raw, int C, long npix, float* partial, float* out,
+                            float scale, hipStream_t s) {
+    const long per = 1024;
+    const int nb = (int)((npix + per - 1) / per);
+    int cp = 1;
+    while (cp < C) cp <<= 1;
+    if (g_raw)
+        hipLaunchKernelGGL(bias_partial_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)g, C, cp, C,
+                           npix, per, partial);
+    else
+        hipLaunchKernelGGL(bias_partial_kernel<T>, dim3(nb), dim3(256), 0, s, (const T*)g, C, cp, C, npix,
+                           per, partial);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3((C + 255) / 256), dim3(256), 0, s, (const float*)partial, nb,
+                       (long)C, scale, out);
+    return check_launch("bias_grad");
+}
+
+template <typename T>
+static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_raw, Src s0, Src s1,
+                              int a_raw_c, float* partial, float* out, float scale, hipStream_t s) {
+    WgradArgs a;
+    memset(&a, 0, sizeof a);
+    const LayerDef& L = kLayers[l];
+    layer_io(l, H, W, &a.Hin, &a.Win, &a.Hout, &a.Wout);
+    a.g = g;
+    a.gc = L.cout;
+    a.gld = L.cout;
+    a.g_raw = g_raw;
+    a.s0 = s0;
+    a.s1 = s1;
+    a.a_raw_c = a_raw_c;
+    a.mode = L.tconv ? M_TCONV : M_CONV;
+    a.nmaps = n;
+    a.cout = L.cout;
+    a.cin = L.cin;
+    int nch;
+    wgrad_split(l, n, H, W, &a.per_block, &nch);
+    a.co_tiles = (L.cout + 63) / 64;
+    a.ci_tiles = (L.cin + 63) / 64;
+    a.partial = partial;
+    hipLaunchKernelGGL(wgrad_kernel<T>, dim3(nch, 9, a.co_tiles * a.ci_tiles), dim3(256), 0, s, a);
+    const long count = 9L * L.cout * L.cin;
+    hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)std::min(1024L, (count + 255) / 256)), dim3(256), 0, s,
+                       (const float*)partial, nch * 4, L.cout, L.cin, scale, out);
+    return check_launch("weight_grad");
+}
+
+struct BwdBufs {
+    const float* x;
+    const float* dy;
+    const void *h1, *h2, *h3, *u3, *u2;
+    float* dparams;
+    float* dx;
+    char* ws;
+    BwdLayout L;
+};
+
+template <int P>
+static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W, float gscale,
+                               hipStream_t s) {
+    typedef typename Traits<P>::T T;
+    char* ws = b.ws;
+    const BwdLayout& L = b.L;
+    void* dz_u2 = ws + L.dz_u2;
+    void* dh1s = ws + L.dh1s;
+    void* dz_u3 = ws + L.dz_u3;
+    void* dh2s = ws + L.dh2s;
+    void* dz_h3 = ws + L.dz_h3;
+    void* dz_h2 = ws + L.dz_h2;
+    void* dz_h1 = ws + L.dz_h1;
+    float* wpart = (float*)(ws + L.wpart);
+    float* bpart = (float*)(ws + L.bpart);
+    ActSizes as = act_sizes(P, n, H, W);
+    float* dp = b.dparams;
+
+    // D1: y = tconv([u2|h1]); its data gradient is a stride-2 conv of dy.
+    {
+        const GemmGeom g = gemm_geom(5, true, P);
+        LayerArgs a = base_args(5, n, H, W, true, h->wb[5], g.kstride);
+        a.s0 = {b.dy, g.cin_eff, 3};
+        a.raw_c = 3;
+        a.seg0 = seg_out(dz_u2, 32, 0, 1.0f);
+        a.seg0.mask = b.u2;
+        a.seg0.ldm = 32;
+        a.seg1 = seg_out(dh1s, 32, 0, 1.0f);
+        { const long tok = prof_begin(h, PROF_BWD + 5, s);
+        TRY(run_gemm<P>(5, true, a, default_npw(P, 5, true), s));
+        prof_end(h, tok, s); }
+        { const long tok = prof_begin(h, PROF_WGRAD + 5, s);
+        TRY(weight_grad<T>(5, n, H, W, b.dy, true, Src{b.u2, 32, 32}, Src{b.h1, 32, 32}, 0, wpart,
+                           dp + layer_w_offset(5), gscale, s));
+        prof_end(h, tok, s); }
+        { const long tok = prof_begin(h, PROF_BIAS, s);
+        TRY(bias_grad<T>(b.dy, true, 3, as.p0, bpart, dp + layer_b_offset(5), gscale, s));
+        prof_end(h, tok, s); }
+    }
+    // D2: u2 = relu(tconv([u3|h2]))
+    {
+        const GemmGeom g = gemm_geom(4, true, P);
+        LayerArgs a = base_args(4, n, H, W, true, h->wb[4], g.kstride);
+        a.s0 = {dz_u2, 32, 32};
+        a.seg0 = seg_out(dz_u3, 64, 0, 1.0f);
+        a.seg0.mask = b.u3;
+        a.seg0.ldm = 64;
+        a.seg1 = seg_out(dh2s, 64, 0, 1.0f);
+        { const long tok = prof_begin(h, PROF_BWD + 4, s);
+        TRY(run_gemm<P>(4, true, a, default_npw(P, 4, true), s));
+        prof_end(h, tok, s); }
+        { const long tok = prof_begin(h, PROF_WGRAD + 4, s);
+        TRY(weight_grad<T>(4, n, H, W, dz_u2, false, Src{b.u3, 64, 64}, Src{b.h2, 64, 64}, 0, wpart,
+                           dp + layer_w_offset(4), gscale, s));
+        prof_end(h, tok, s); }
+        { const long tok = prof_begin(h, PROF_BIAS, s);
+        TRY(bias_grad<T>(dz_u2, false, 32, as.p1, bpart, dp + layer_b_offset(4), gscale, s));
+        prof_end(h, tok, s); }
+    }
+    // D3: u3 = relu(tconv(h3))
+    {
+        const GemmGeom g = gemm_geom(3, true, P);
+        LayerArgs a = base_args(3, n, H, W, true, h->wb[3], g.kstride);
+        a.s0 = {dz_u3, 64, 64};
+        a.seg0 = seg_out(dz_h3, 128, 0, 1.0f);
+        a.seg0.mask = b.h3;
+        a.seg0.ldm = 128;
+        { const long tok = prof_begin(h, PROF_BWD + 3, s);
+        TRY(run_gemm<P>(3, true, a, default_npw(P, 3, true), s));
+        prof_end(h, tok, s); }
+        { const long tok = prof_begin(h, PROF_WGRAD + 3, s);
+        TRY(weight_grad<T>(3, n, H, W, dz_u3, false, Src{b.h3, 128, 128}, Src{nullptr, 0, 0}, 0, wpart,
+                           dp + layer_w_offset(3), gscale, s));
+        prof_end(h, tok, s); }
+        { const long tok = prof_begin(h, PROF_BIAS, s);
+        TRY(bias_grad<T>(dz_u3, false, 64, as.p2, bpart, dp + layer_b_offset(3), gscale, s));
+        prof_end(h, tok, s); }
+    }
+    // E3: h3 = relu(conv(h2)); dh2 = skip part + encoder part
+    {
+        const GemmGeom g = gemm_geom(2, true, P);
+        LayerArgs a = base_args(2, n, H, W, true, h->wb[2], g.kstride);
+        a.s0 = {dz_h3, 128, 128};
+        a.seg0 = seg_out(dz_h2, 64, 0, 1.0f);
+        a.seg0.add = dh2s;
+        a.seg0.lda = 64;
+        a.seg0.mask = b.h2;
+        a.seg0.ldm = 64;
+        { const long tok = prof_begin(h, PROF_BWD + 2, s);
+        TRY(run_gemm<P>(2, true, a, default_npw(P, 2, true), s));
+        prof_end(h, tok, s); }
+        { const long tok = prof_begin(h, PROF_WGRAD + 2, s);
+        TRY(weight_grad<T>(2, n, H, W, dz_h3, false, Src{b.h2, 64, 64}, Src{nullptr, 0, 0}, 0, wpart,
+                           dp + layer_w_offset(2), gscale, s));
+        prof_end(h, tok, s); }
+        { const long tok = prof_begin(h, PROF_BIAS, s);
+        TRY(bias_grad<T>(dz_h3, false, 128, as.p3, bpart, dp + layer_b_offset(2), gscale, s));
+        prof_end(h, tok, s); }
+    }
+    // E2: h2 = relu(conv(h1))
+    {
+        const GemmGeom g = gemm_geom(1, true, P);
+        LayerArgs a = base_args(1, n, H, W, true, h->wb[1], g.kstride);
+        a.s0 = {dz_h2, 64, 64};
+        a.seg0 = seg_out(dz_h1, 32, 0, 1.0f);
+        a.seg0.add = dh1s;
+        a.seg0.lda = 32;
+        a.seg0.mask = b.h1;
+        a.seg0.ldm = 32;
+        { const long tok = prof_begin(h, PROF_BWD + 1, s);
+        TRY(run_gemm<P>(1, true, a, default_npw(P, 1, true), s));
+        prof_end(h, tok, s); }
+        { const long tok = prof_begin(h, PROF_WGRAD + 1, s);
+        TRY(weight_grad<T>(1, n, H, W, dz_h2, false, Src{b.h1, 32, 32}, Src{nullptr, 0, 0}, 0, wpart,
+                           dp + layer_w_offset(1), gscale, s));
+        prof_end(h, tok, s); }
+        { const long tok = prof_begin(h, PROF_BIAS, s);
+        TRY(bias_grad<T>(dz_h2, false, 64, as.p2, bpart, dp + layer_b_offset(1), gscale, s));
+        prof_end(h, tok, s); }
+    }
+    // E1: h1 = relu(conv(x))
+    {
+        { const long tok = prof_begin(h, PROF_WGRAD + 0, s);
+        TRY(weight_grad<T>(0, n, H, W, dz_h1, false, Src{b.x, 7, 7}, Src{nullptr, 0, 0}, 7, wpart,
+                           dp + layer_w_offset(0), gscale, s));
+        prof_end(h, tok, s); }
+        { const long tok = prof_begin(h, PROF_BIAS, s);
+        TRY(bias_grad<T>(dz_h1, false, 32, as.p1, bpart, dp + layer_b_offset(0), gscale, s));
+        prof_end(h, tok, s); }
+        if (b.dx) {
+            const GemmGeom g = gemm_geom(0, true, P);
+            LayerArgs a = base_args(0, n, H, W, true, h->wb[0], g.kstride);
+            a.s0 = {dz_h1, 32, 32};
+            a.acc_scale = gscale;
+            a.seg0 = seg_out(b.dx, 7, 0, 1.0f);
+            { const long tok = prof_begin(h, PROF_BWD + 0, s);
+            TRY(run_gemm<P>(0, true, a, default_npw(P, 0, true), s));
+            prof_end(h, tok, s); }
+        }
+    }
+    return DRC_OK;
+}
+
+// Recompute h3, u3 and u2 from the saved h2 (layers E3, D3, D2).
+static drc_status recompute_acts(drc_cae* h, BwdBufs& b, int n, int H, int W, hipStream_t s) {
+    FwdBufs f{nullptr, nullptr, const_cast<void*>(b.h1), const_cast<void*>(b.h2), b.ws + b.L.recomp[0],
+              b.ws + b.L.recomp[1], b.ws + b.L.recomp[2]};
+    TRY(forward_dispatch(h, f, n, H, W, 2, 4, s));
+    b.h3 = f.h3;
+    b.u3 = f.u3;
+    b.u2 = f.u2;
+    return DRC_OK;
+}
+
+static drc_status backward_dispatch(drc_cae* h, BwdBufs& b, int n, int H, int W, float gscale,
+                                    hipStream_t s) {
+    if (h->prec == P_F32) return backward_seq<P_F32>(h, b, n, H, W, gscale, s);
+    if (h->prec == P_BF16) return backward_seq<P_BF16>(h, b, n, H, W, gscale, s);
+    return drc_fail(DRC_ERR_UNSUPPORTED, "backward: FP8 handles are inference only");
+}
+
+extern "C" drc_status drc_cae_backward(drc_cae* h, const float* d_x, const float* d_dy,
+                                       const void* d_saved, float* d_dparams, float* d_dx, int n, int H,
+                                       int W, void* d_ws, size_t ws_bytes, void* stream) {
+    TRY(check_ready(h, "backward"));
+    if (h->prec == P_FP8) return drc_fail(DRC_ERR_UNSUPPORTED, "backward: FP8 handles are inference only");
+    if (h->desc.final_relu) return drc_fail(DRC_ERR_UNSUPPORTED, "backward: final_relu = 1 is inference only");
+    TRY(check_shape("backward", n, H, W));
+    TRY(check_ptr("backward", "d_x", d_x, 16, false));
+    TRY(check_ptr("backward", "d_dy", d_dy, 16, false));
+    TRY(check_ptr("backward", "d_saved", d_saved, 256, false));
+    TRY(check_ptr("backward", "d_dparams", d_dparams, 16, false));
+    TRY(check_ptr("backward", "d_dx", d_dx, 16, true));
+    TRY(check_ptr("backward", "d_ws", d_ws, 256, false));
+    size_t need = 0;
+    TRY(drc_cae_workspace_size(h, n, H, W, DRC_WS_BACKWARD, &need));
+    if (ws_bytes < need)
+        return drc_fail(DRC_ERR_WORKSPACE, "backward: workspace %zu < %zu bytes", ws_bytes, need);
+    size_t sb;
+    int64_t off[5];
+    TRY(drc_cae_saved_size(h, n, H, W, &sb, off));
+    BwdBufs b;
+    b.x = d_x;
+    b.dy = d_dy;
+    const char* sv = (const char*)d_saved;
+    b.h1 = sv + off[0];
+    b.h2 = sv + off[1];
+    b.h3 = off[2] >= 0 ? sv + off[2] : nullptr;
+    b.u3 = off[3] >= 0 ? sv + off[3] : nullptr;
+    b.u2 = off[4] >= 0 ? sv + off[4] : nullptr;
+    b.dparams = d_dparams;
+    b.dx = d_dx;
+    b.ws = (char*)d_ws;
+    b.L = bwd_layout(h->prec, n, H, W, true);
+    hipStream_t s = (hipStream_t)stream;
+    if (h->recompute) TRY(recompute_acts(h, b, n, H, W, s));
+    return backward_dispatch(h, b, n, H, W, 1.0f, s);
+}
+
+// ------------------------------------------------------------------ training step
+extern "C" drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, float* d_v, int64_t t,
+                                   const drc_adam_cfg* adam, const float* d_x, const float* d_target,
+                                   float* d_loss, float* d_dparams, int n, int H, int W, void* d_ws,
+                                   size_t ws_bytes, void* stream) {
+    if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "step: handle is NULL");
+    if (h->prec == P_FP8) return drc_fail(DRC_ERR_UNSUPPORTED, "step: FP8 handles are inference only");
+    if (h->desc.final_relu) return drc_fail(DRC_ERR_UNSUPPORTED, "step: final_relu = 1 is inference only");
+    TRY(check_shape("step", n, H, W));
+    TRY(check_ptr("step", "d_params", d_params, 16, false));
+    TRY(check_ptr("step", "d_m", d_m, 16, false));
+    TRY(check_ptr("step", "d_v", d_v, 16, false));
+    TRY(check_ptr("step", "d_x", d_x, 16, false));
+    TRY(check_ptr("step", "d_target", d_target, 16, false));
+    TRY(check_ptr("step", "d_loss", d_loss, 4, false));
+    TRY(check_ptr("step", "d_dparams", d_dparams, 16, true));
+    TRY(check_ptr("step", "d_ws", d_ws, 256, false));
+    if (!adam) return drc_fail(DRC_ERR_INVALID_ARG, "step: adam is NULL");
+    if (t < 1) return drc_fail(DRC_ERR_INVALID_ARG, "step: t = %lld (must be >= 1)", (long long)t);
+    if (!(adam->lr > 0) || !(adam->beta1 >= 0 && adam->beta1 < 1) || !(adam->beta2 >= 0 && adam->beta2 < 1) ||
+        !(adam->eps >= 0))
+        return drc_fail(DRC_ERR_INVALID_ARG, "step: bad Adam hyper-parameters");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != h->device)
+        return drc_fail(DRC_ERR_STATE, "step: current device is not the handle's device");
+    const StepLayout S = step_layout(h->prec, n, H, W, h->recompute);
+    if (ws_bytes < S.total)
+        return drc_fail(DRC_ERR_WORKSPACE, "step: workspace %zu < %zu bytes", ws_bytes, S.total);
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+
+    if (!h->params_set || h->packed_from != d_params) TRY(drc_cae_set_params(h, d_params, stream));
+
+    // forward: skip tensors in the saved region, the rest in scratch (recompute) or saved
+    ActSizes a = act_sizes(h->prec, n, H, W);
+    int64_t off[5];
+    size_t sb;
+    TRY(drc_cae_saved_size(h, n, H, W, &sb, off));
+    void* act[5];
+    size_t scur = S.fwd_scratch;
+    for (int k = 0; k < 5; ++k) {
+        if (off[k] >= 0) {
+            act[k] = ws + S.saved + off[k];
+        } else {
+            act[k] = ws + scur;
+            scur += a.bytes[k];
+        }
+    }
+    float* y = (float*)(ws + S.y);
+    float* dy = (float*)(ws + S.dy);
+    FwdBufs fb{d_x, y, act[0], act[1], act[2], act[3], act[4]};
+    TRY(forward_dispatch(h, fb, n, H, W, 0, 5, s));
+
+    // L1 loss (mean) and dL/dy; dy is stored as sign(y - t) and the 1/M
+    // factor is applied once, to the parameter gradients.
+    const long M = a.p0 * 3;
+    const int nparts = (int)((M + 16383) / 16384);
+    const long ltok = prof_begin(h, PROF_LOSS, s);
+    hipLaunchKernelGGL(l1_partial_kernel, dim3(nparts), dim3(256), 0, s, (const float*)y, d_target, M, 16384L,
+                       1.0f, dy, (double*)(ws + S.loss_part));
+    hipLaunchKernelGGL(l1_final_kernel, dim3(1), dim3(256), 0, s, (const double*)(ws + S.loss_part), nparts, M,
+                       d_loss);
+    prof_end(h, ltok, s);
+    TRY(check_launch("step/l1"));
+
+    BwdBufs b;
+    b.x = d_x;
+    b.dy = dy;
+    b.h1 = act[0];
+    b.h2 = act[1];
+    b.h3 = act[2];
+    b.u3 = act[3];
+    b.u2 = act[4];
+    b.dparams = d_dparams ? d_dparams : (float*)(ws + S.dparams);
+    b.dx = nullptr;
+    b.ws = ws + S.bwd;
+    b.L = bwd_layout(h->prec, n, H, W, h->recompute != 0);
+    if (h->recompute) TRY(recompute_acts(h, b, n, H, W, s));
+    TRY(backward_dispatch(h, b, n, H, W, (float)(1.0 / (double)M), s));
+
+    // Adam (PyTorch form), then repack the weights from the new masters.
+    const double bc1 = 1.0 - std::pow(adam->beta1, (double)t);
+    const double bc2 = 1.0 - std::pow(adam->beta2, (double)t);
+    const long P = (long)drc_cae_num_params(h);
+    const long atok = prof_begin(h, PROF_ADAM, s);
+    hipLaunchKernelGGL(adam_kernel, dim3((int)((P + 255) / 256)), dim3(256), 0, s, d_params, d_m, d_v,
+                       (const float*)b.dparams, P, (float)adam->beta1, (float)(1.0 - adam->beta1),
+                       (float)adam->beta2, (float)(1.0 - adam->beta2), (float)(adam->lr / bc1),
+                       (float)(1.0 / std::sqrt(bc2)), (float)adam->eps);
+    TRY(check_launch("step/adam"));
+    const drc_status st = drc_cae_set_params(h, d_params, stream);
+    prof_end(h, atok, s);
+    return st;
+}
+
+// ------------------------------------------------------------------ FP8 calibration
+extern "C" drc_status drc_cae_calibrate_fp8(drc_cae* h, const float* d_x, int n, int H, int W, void* d_ws,
+                                            size_t ws_bytes, void* stream) {
+    if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "calibrate_fp8: handle is NULL");
+    if (h->prec != P_FP8) return drc_fail(DRC_ERR_STATE, "calibrate_fp8: not an FP8 handle");
+    if (!h->params_set) return drc_fail(DRC_ERR_STATE, "calibrate_fp8: call drc_cae_set_params first");
+    TRY(check_shape("calibrate_fp8", n, H, W));
+    TRY(check_ptr("calibrate_fp8", "d_x", d_x, 16, false));
+    TRY(check_ptr("calibrate_fp8", "d_ws", d_ws, 256, false));
+    size_t need = 0;
+    TRY(drc_cae_workspace_size(h, n, H, W, DRC_WS_CALIBRATE, &need));
+    if (ws_bytes < need)
+        return drc_fail(DRC_ERR_WORKSPACE, "calibrate_fp8: workspace %zu < %zu bytes", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    ActSizes a = act_sizes(P_F32, n, H, W);
+    char* ws = (char*)d_ws;
+    void* act[5];
+    size_t cur = 0;
+    for (int k = 0; k < 5; ++k) {
+        act[k] = ws + cur;
+        cur += a.bytes[k];
+    }
+    float* y = (float*)(ws + cur);
+    FwdBufs b{d_x, y, act[0], act[1], act[2], act[3], act[4]};
+    TRY(forward_seq<P_F32>(h, h->wcal, b, n, H, W, 0, 5, s));
+    HIPCHK(hipMemsetAsync(h->amax + 6, 0, 6 * sizeof(unsigned), s));
+    const long cnt[6] = {a.p0 * 7, a.p1 * 32, a.p2 * 64, a.p3 * 128, a.p2 * 64, a.p1 * 32};
+    const float* src[6] = {d_x, (const float*)act[0], (const float*)act[1], (const float*)act[2],
+                           (const float*)act[3], (const float*)act[4]};
+    for (int k = 0; k < 6; ++k)
+        hipLaunchKernelGGL(amax_f32_kernel, dim3(256), dim3(256), 0, s, src[k], cnt[k], h->amax + 6 + k);
+    TRY(check_launch("calibrate_fp8/amax"));
+    unsigned am[6];
+    HIPCHK(hipMemcpyAsync(am, h->amax + 6, sizeof am, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float v[6];
+    for (int k = 0; k < 6; ++k) memcpy(&v[k], &am[k], 4);
+    auto sc = [](float m) { return m > 0.0f ? 448.0f / m : 1.0f; };
+    h->host_scales[6] = sc(v[0]);                 // x
+    h->host_scales[7] = sc(std::max(v[1], v[5])); // [u2|h1]
+    h->host_scales[8] = sc(std::max(v[2], v[4])); // [u3|h2]
+    h->host_scales[9] = sc(v[3]);                 // h3
+    HIPCHK(hipMemcpyAsync(h->scales + 6, h->host_scales + 6, 4 * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->calibrated = true;
+    return DRC_OK;
+}

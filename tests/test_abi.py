@@ -1,0 +1,102 @@
+"""C-ABI contract checks that run without a GPU: the library loads, exports
+every function the header declares, and rejects bad arguments on the host
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "drc_cae.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(drc_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1910_02480_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libdrc_cae.so is not built (run __graft_entry__.build())")
+    binding.lib()
+    return binding
+
+
+def test_exports_every_declared_symbol(B):
+    names = _declared()
+    assert len(names) >= 20
+    L = ctypes.CDLL(B.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # the binding exposes the same names
+    assert not [n for n in names if not hasattr(B, n)]
+
+
+def test_status_strings(B):
+    for k, name in B.STATUS_NAMES.items():
+        assert B.drc_status_string(k) == name
+
+
+def test_default_desc(B):
+    d = B.drc_cae_default_desc(B.DRC_BF16)
+    assert (d.in_ch, d.out_ch, list(d.widths), d.compute, d.final_relu) == (7, 3, [32, 64, 128], 1, 0)
+
+
+def _expect(B, status, fn, *args):
+    with pytest.raises(B.DrcError) as e:
+        fn(*args)
+    assert e.value.status == status, str(e.value)
+
+
+def test_create_rejects_bad_descriptions(B):
+    d = B.drc_cae_default_desc(B.DRC_F32)
+    d.widths[2] = 256
+    _expect(B, 3, B.drc_cae_create, d)
+    d = B.drc_cae_default_desc(B.DRC_F32)
+    d.in_ch = 6
+    _expect(B, 3, B.drc_cae_create, d)
+    d = B.drc_cae_default_desc(9)
+    _expect(B, 1, B.drc_cae_create, d)
+    d = B.drc_cae_default_desc(B.DRC_F32)
+    d.final_relu = 2
+    _expect(B, 1, B.drc_cae_create, d)
+    L = B.lib()
+    assert L.drc_cae_create(None, None) == 1
+    h = ctypes.c_void_p()
+    assert L.drc_cae_create(None, ctypes.byref(h)) == 1 and h.value is None
+
+
+def test_null_handle_rejected(B):
+    L = B.lib()
+    sz = ctypes.c_size_t()
+    assert L.drc_cae_workspace_size(None, 1, 8, 8, 1, ctypes.byref(sz)) == 1
+    assert L.drc_cae_saved_size(None, 1, 8, 8, ctypes.byref(sz), None) == 1
+    assert L.drc_cae_forward(None, None, None, 1, 8, 8, None, None, 0, None) == 1
+    assert L.drc_cae_backward(None, None, None, None, None, None, 1, 8, 8, None, 0, None) == 1
+    assert L.drc_cae_set_params(None, None, None) == 1
+    assert L.drc_cae_set_recompute(None, 1) == 1
+    assert L.drc_cae_num_params(None) == 0
+    L.drc_cae_destroy(None)
+    assert "NULL" in B.drc_last_error()
+
+
+def test_no_device_reports_hip_error(B):
+    """Without a GPU the create call fails with DRC_ERR_HIP instead of crashing."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    _expect(B, 5, B.drc_cae_create, B.drc_cae_default_desc(B.DRC_BF16))
+
+
+def test_product_path_never_imports_oracle():
+    """The HIP path and its binding share no code with the oracle."""
+    pkg = os.path.join(ROOT, "paper_1910_02480_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in txt.lower() or f == "synth.py", f

@@ -1,0 +1,216 @@
+"""GPU parity of the forward pass against the FP64 oracle (needs gfx950).
+
+Gates (per output map m, max_rel = max|y - r| / max|r|):
+* FP32 path: max over maps of max_rel <= 1e-5 against the FP64 oracle;
+* BF16 path: <= 1e-2;
+* FP8 path: reported (and bounded loosely) only.
+Per-layer checks feed the oracle the GPU's own stored layer inputs, rounded
+to the compute precision with PyTorch's casts, so they pin each kernel (and
+its rounding) separately from error propagation.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1910_02480_amd import synth
+from tests.helpers import (ACT_SHAPES, layer_params, max_rel_per_map, mean_rel_per_map, round_to,
+                           saved_acts)
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def params():
+    return synth.init_params(0)
+
+
+@pytest.fixture(scope="module")
+def params_dev(params):
+    return torch.from_numpy(params).to(DEV)
+
+
+def _cae(compute, params_dev, calib_x=None, **kw):
+    from paper_1910_02480_amd.cae import CAE
+    c = CAE(compute, params_dev, device=DEV, **kw)
+    if compute == "fp8":
+        c.calibrate_fp8(calib_x)
+    return c
+
+
+def _run(cae, x_np, want_saved=False):
+    x = torch.from_numpy(x_np).to(DEV)
+    n, H, W, _ = x_np.shape
+    saved, off = cae.saved_buffer(n, H, W) if want_saved else (None, None)
+    y = cae.forward(x, saved=saved)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), saved, off
+
+
+@pytest.mark.parametrize("compute,gate", [("f32", 1e-5), ("bf16", 1e-2)])
+def test_forward_batch16_32x32(oracle, params, params_dev, compute, gate):
+    """Batch of 16 maps of 32x32 (the paper's map size, Sec. 4.3)."""
+    x = synth.radiance_maps(16, 32, 32)
+    y, _, _ = _run(_cae(compute, params_dev), x)
+    r = oracle.forward(params, x)["y"]
+    mr = max_rel_per_map(y, r)
+    print(f"{compute} 16x32x32: max_rel max {mr.max():.3e} mean {mr.mean():.3e} "
+          f"mean_rel {mean_rel_per_map(y, r).mean():.3e}")
+    assert mr.max() <= gate
+
+
+@pytest.mark.parametrize("compute,gate", [("f32", 1e-5), ("bf16", 1e-2)])
+@pytest.mark.parametrize("n,H,W", [(1, 8, 8), (2, 8, 24), (3, 40, 40), (2, 64, 64), (1, 128, 128),
+                                   (5, 24, 16)])
+def test_forward_shapes(oracle, params, params_dev, compute, gate, n, H, W):
+    """Smallest map, non-square maps, ragged tile tails (40x40: 25-pixel bottleneck), 128x128."""
+    x = synth.radiance_maps(n, H, W, seed=7)
+    y, _, _ = _run(_cae(compute, params_dev), x)
+    r = oracle.forward(params, x)["y"]
+    assert max_rel_per_map(y, r).max() <= gate
+
+
+def _layer_refs(oracle, params, x, acts, compute, scales=None):
+    """Oracle output of each layer on the GPU's own (rounded) inputs."""
+    sc = scales or {}
+
+    def rnd(a, name):
+        return round_to(a, compute, sc.get(name, 1.0))
+
+    def W(k, name):
+        w, b = layer_params(params, k)
+        return round_to(w, compute, sc.get(name, 1.0)), b.astype(np.float64)
+
+    refs = {}
+    w, b = W(0, "w0")
+    refs["h1"] = oracle.conv_s2(rnd(x, "x"), w, b)
+    w, b = W(1, "w1")
+    refs["h2"] = oracle.conv_s2(acts["h1"], w, b)
+    w, b = W(2, "w2")
+    refs["h3"] = oracle.conv_s2(acts["h2"], w, b)
+    w, b = W(3, "w3")
+    refs["u3"] = oracle.tconv_s2(acts["h3"], w, b)
+    w, b = W(4, "w4")
+    refs["u2"] = oracle.tconv_s2(np.concatenate([acts["u3"], acts["h2"]], -1), w, b)
+    w, b = W(5, "w5")
+    refs["y"] = oracle.tconv_s2(np.concatenate([acts["u2"], acts["h1"]], -1), w, b)
+    for k in ("h1", "h2", "h3", "u3", "u2"):
+        refs[k] = np.maximum(refs[k], 0.0)
+    return refs
+
+
+def test_layers_f32(oracle, params, params_dev):
+    x = synth.radiance_maps(4, 32, 32)
+    cae = _cae("f32", params_dev)
+    y, saved, off = _run(cae, x, want_saved=True)
+    acts = saved_acts(saved, off, 4, 32, 32, "f32")
+    refs = _layer_refs(oracle, params, x, acts, "f32")
+    for name in ("h1", "h2", "h3", "u3", "u2"):
+        mr = max_rel_per_map(acts[name], refs[name])
+        print(f"layer {name}: max_rel {mr.max():.2e}")
+        assert mr.max() <= 1e-5, name
+    assert max_rel_per_map(y, refs["y"]).max() <= 1e-5
+
+
+def _half_ulp_bf16(v):
+    a = np.abs(v)
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    return np.where(a > 0, 2.0 ** (e - 8), 0.0)
+
+
+def test_layers_bf16_round_to_nearest_even(oracle, params, params_dev):
+    """Each stored BF16 activation is the RNE rounding of the exact layer
+    output on the GPU's own BF16 inputs (allowing for the FP32 accumulation
+    near a rounding tie)."""
+    x = synth.radiance_maps(4, 32, 32)
+    cae = _cae("bf16", params_dev)
+    y, saved, off = _run(cae, x, want_saved=True)
+    acts = saved_acts(saved, off, 4, 32, 32, "bf16")
+    refs = _layer_refs(oracle, params, x, acts, "bf16")
+    for name in ("h1", "h2", "h3", "u3", "u2"):
+        g, r = acts[name], refs[name]
+        err = np.abs(g - r)
+        tol = _half_ulp_bf16(r) * (1 + 1e-3) + 1e-6 * np.abs(r).max()
+        frac_ok = np.mean(err <= tol)
+        print(f"layer {name}: within half-ulp {frac_ok:.6f}, max err/ulp "
+              f"{np.max(err / np.maximum(2 * _half_ulp_bf16(r), 1e-30)):.3f}")
+        assert frac_ok >= 0.999, name
+        assert np.all(err <= 2 * _half_ulp_bf16(r) + 1e-5 * np.abs(r).max()), name
+    assert max_rel_per_map(y, refs["y"]).max() <= 1e-5
+
+
+def test_fp8_forward_reported(oracle, params, params_dev):
+    """FP8 e4m3 inference (per-tensor scales from a 64-map calibration batch): error reported."""
+    calib = torch.from_numpy(synth.radiance_maps(64, 32, 32, seed=11)).to(DEV)
+    cae = _cae("fp8", params_dev, calib_x=calib)
+    x = synth.radiance_maps(8, 32, 32)
+    y, saved, off = _run(cae, x, want_saved=True)
+    r = oracle.forward(params, x)["y"]
+    mr = max_rel_per_map(y, r)
+    me = mean_rel_per_map(y, r)
+    print(f"fp8 8x32x32: max_rel max {mr.max():.3e} mean {mr.mean():.3e}; mean_rel {me.mean():.3e}")
+    assert np.all(np.isfinite(y))
+    assert mr.max() <= 0.25
+    # per-layer: stored e4m3 values are within one e4m3 step of the exact layer output
+    from paper_1910_02480_amd import binding as B
+    s = B.drc_cae_get_fp8_scales(cae.h)
+    scales = {"x": s[6], "h1": s[7], "u2": s[7], "h2": s[8], "u3": s[8], "h3": s[9]}
+    for k in range(6):
+        scales[f"w{k}"] = s[k]
+    acts = saved_acts(saved, off, 8, 32, 32, "fp8", scales)
+    refs = _layer_refs(oracle, params, x, acts, "fp8", scales)
+    for name in ("h1", "h2", "h3", "u3", "u2"):
+        exp = round_to(refs[name], "fp8", scales[name])
+        g = acts[name]
+        # one e4m3 step at exp (3 mantissa bits), floored at the subnormal step
+        step = np.maximum(np.abs(exp) * 2.0 ** -3, 2.0 ** -9 / scales[name])
+        d = (np.abs(g - exp) / step).ravel()
+        worst = np.argsort(d)[-3:]
+        print(f"fp8 layer {name}: exact {np.mean(d == 0):.5f}, max steps {d.max():.3f}; worst "
+              + str([(float(g.ravel()[i]), float(exp.ravel()[i]), float(refs[name].ravel()[i]))
+                     for i in worst]))
+        assert np.mean(d == 0) >= 0.99, name
+        assert d.max() <= 1.01, name
+
+
+def test_batch_composition_independence(params_dev):
+    """A map's output does not depend on the other maps in its batch (bitwise)."""
+    x = synth.radiance_maps(64, 32, 32)
+    for compute in ("f32", "bf16"):
+        cae = _cae(compute, params_dev)
+        yb, _, _ = _run(cae, x)
+        for k in (0, 17, 63):
+            y1, _, _ = _run(cae, x[k:k + 1])
+            np.testing.assert_array_equal(y1[0], yb[k])
+
+
+def test_run_to_run_determinism(params_dev):
+    x = synth.radiance_maps(32, 64, 64)
+    for compute in ("f32", "bf16"):
+        cae = _cae(compute, params_dev)
+        a, _, _ = _run(cae, x)
+        b, _, _ = _run(cae, x)
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("compute,gate", [("f32", 1e-5), ("bf16", 1e-2)])
+def test_full_size_4096x64x64_sampled(oracle, params, params_dev, compute, gate):
+    """The benchmark configuration (4096 maps of 64x64); the oracle checks a
+    sample of maps one by one (maps are independent)."""
+    n, H = 4096, 64
+    x = torch.empty((n, H, H, 7), dtype=torch.float32)
+    for s in range(0, n, 512):
+        x[s:s + 512] = torch.from_numpy(synth.radiance_maps(512, H, H, start=s))
+    cae = _cae(compute, params_dev)
+    xd = x.to(DEV)
+    y = cae.forward(xd)
+    torch.cuda.synchronize()
+    sample = [0, 1, 777, 2048, 3333, 4095]
+    xs = x[sample].numpy()
+    r = oracle.forward(params, xs)["y"]
+    ys = y[sample].cpu().numpy()
+    mr = max_rel_per_map(ys, r)
+    print(f"{compute} 4096x64x64 sampled max_rel {mr.max():.3e}")
+    assert mr.max() <= gate
+    assert torch.isfinite(y).all()
