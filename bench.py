@@ -16,6 +16,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 METRIC = "maps/s CAE fwd & fwd+bwd, 64x64 maps; BF16 vs FP32 at rel-err<=1e-2"
@@ -82,7 +83,7 @@ def read_profile(B, h):
     return B.drc_cae_profile_read(h)
 
 
-def cpu_baseline(x_sample_fn, H, budget_s):
+def cpu_baseline(x_sample_fn, H, budget_s, len_x):
     """FP64 oracle forward on the host, on a bounded sample of the workload."""
     import numpy as np
     from oracle import oracle as O
@@ -93,7 +94,7 @@ def cpu_baseline(x_sample_fn, H, budget_s):
     t0 = time.perf_counter()
     O.forward(params, x1)
     t1 = time.perf_counter() - t0
-    n = int(max(1, min(512, budget_s / max(t1, 1e-3))))
+    n = int(max(1, min(len_x, budget_s / max(t1, 1e-3))))
     xs = x_sample_fn(n)
     t0 = time.perf_counter()
     acts = O.forward(params, xs)
@@ -102,6 +103,55 @@ def cpu_baseline(x_sample_fn, H, budget_s):
     return {"value": n / dt, "unit": "maps/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle forward of maps 0..{n - 1} of the {H}x{H} workload "
                       f"({dt:.1f} s, {threads} OpenMP threads)"}, acts["y"], n
+
+
+def mixed_frame_leg(cae, tune_path, args):
+    """6000 cache points (50 % 32x32, 35 % 64x64, 15 % 128x128, shuffled),
+    BF16, one persistent hipGraph-captured pass per frame; p50/p99 latency
+    over replays. Tile shapes come from the autotuner, run per resolution."""
+    import numpy as np
+    import torch
+    from paper_1910_02480_amd import binding as B
+    from paper_1910_02480_amd import synth
+    dev = cae.device
+    res = synth.mixed_resolutions(args.frame_maps)
+    log(f"mixed frame: generating {len(res)} maps")
+    x, xo, yo = synth.mixed_frame(res)
+    ny = int((res.astype(np.int64) ** 2).sum()) * 3
+    for r in (32, 64, 128):
+        k = {32: 512, 64: 256, 128: 64}[r]
+        xt = torch.from_numpy(synth.radiance_maps(k, r, r, seed=5)).to(dev)
+        B.drc_cae_autotune(cae.h, xt, cae.workspace(k, r, r, B.DRC_WS_AUTOTUNE), tune_path)
+        del xt
+    maps = [(int(r), int(r), int(xo[m]), int(yo[m])) for m, r in enumerate(res)]
+    plan = B.drc_cae_plan_create(cae.h, maps, tune_path)
+    try:
+        nb = B.drc_cae_plan_workspace_size(plan)
+        wsb = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        ws = wsb[(-wsb.data_ptr()) % 256:]
+        xd = torch.from_numpy(x).to(dev)
+        yd = torch.empty(ny, device=dev)
+        stream = torch.cuda.Stream(device=dev)
+        torch.cuda.synchronize()
+        reps = args.frame_reps
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        with torch.cuda.stream(stream):
+            for _ in range(10):
+                B.drc_cae_plan_launch(plan, xd, yd, ws)
+            for e0, e1 in ev:
+                e0.record(stream)
+                B.drc_cae_plan_launch(plan, xd, yd, ws)
+                e1.record(stream)
+        torch.cuda.synchronize()
+        lat = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+        p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+        flops = sum(13392.0 * int(r) * int(r) for r in res)
+        log(f"mixed frame ({len(res)} maps): p50 {p50:.3f} ms, p99 {p99:.3f} ms, {len(res) / p50 * 1e3:,.0f} maps/s")
+        return {"maps": len(res), "p50_ms": p50, "p99_ms": p99, "maps_per_s": len(res) / p50 * 1e3,
+                "replays": reps, "gflop_per_frame": flops / 1e9,
+                "mfma_frac_flop_based": flops / (p50 * 1e-3) / (PEAK_TFLOPS["bf16"] * 1e12)}
+    finally:
+        B.drc_cae_plan_destroy(plan)
 
 
 def main():
@@ -115,6 +165,8 @@ def main():
     ap.add_argument("--main-only", action="store_true", help="time only the headline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--frame-maps", type=int, default=6000)
+    ap.add_argument("--frame-reps", type=int, default=200)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -140,6 +192,9 @@ def main():
 
     # ---------------- headline: BF16 forward, profiled live
     cae = CAE("bf16", params, device=dev)
+    tune_path = os.path.join(tempfile.gettempdir(), f"drc_tune_{os.getpid()}.jsonl")
+    log("autotuning tile shapes for the headline batch")
+    B.drc_cae_autotune(cae.h, x, cae.workspace(n, H, H, B.DRC_WS_AUTOTUNE), tune_path)
     ws = cae.workspace(n, H, H, B.DRC_WS_FORWARD)
     fwd = lambda: B.drc_cae_forward(cae.h, x, y, None, ws)
     for _ in range(args.warmup):
@@ -222,6 +277,8 @@ def main():
             legs[f"{comp}_train_step"] = {"maps_per_s": nt / tt, "ms": tt * 1e3, "batch": nt,
                                           "recompute": True}
             log(f"{comp} train step (batch {nt}): {nt / tt:,.0f} maps/s, {tt * 1e3:.3f} ms")
+        # ---------------- mixed-resolution frame: one graph replay per frame
+        legs["bf16_mixed_frame"] = mixed_frame_leg(cae, tune_path, args)
         legs["speedup_bf16_vs_f32"] = {
             "fwd": legs["bf16_fwd"]["maps_per_s"] / legs["f32_fwd"]["maps_per_s"],
             "fwd_bwd": legs["bf16_fwd_bwd"]["maps_per_s"] / legs["f32_fwd_bwd"]["maps_per_s"],
@@ -236,7 +293,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
-        cb, y_ref, ns = cpu_baseline(lambda k: x_host[:k].numpy(), H, args.cpu_seconds)
+        cb, y_ref, ns = cpu_baseline(lambda k: x_host[:k].numpy(), H, args.cpu_seconds, n)
         out["cpu_baseline"] = cb
         k = min(ns, 8)
         def mr(yg):

@@ -136,7 +136,7 @@ drc_status drc_cae_set_recompute(drc_cae* h, int on);
 drc_status drc_cae_saved_size(const drc_cae* h, int n, int H, int W, size_t* bytes,
                               int64_t offsets[5]);
 
-enum { DRC_WS_FORWARD = 1, DRC_WS_BACKWARD = 2, DRC_WS_STEP = 4, DRC_WS_CALIBRATE = 8 };
+enum { DRC_WS_FORWARD = 1, DRC_WS_BACKWARD = 2, DRC_WS_STEP = 4, DRC_WS_CALIBRATE = 8, DRC_WS_AUTOTUNE = 16 };
 
 /* Workspace bytes needed by the calls named in flags (an OR of DRC_WS_*)
  * for an n x H x W batch. */

@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "DRC_OK", 1: "DRC_ERR_INVALID_ARG", 2: "DRC_ERR_SHAPE", 3: "D
                 4: "DRC_ERR_WORKSPACE", 5: "DRC_ERR_HIP", 6: "DRC_ERR_STATE"}
 DRC_F32, DRC_BF16, DRC_FP8_E4M3 = 0, 1, 2
 DTYPES = {"f32": DRC_F32, "bf16": DRC_BF16, "fp8": DRC_FP8_E4M3}
-DRC_WS_FORWARD, DRC_WS_BACKWARD, DRC_WS_STEP, DRC_WS_CALIBRATE = 1, 2, 4, 8
+DRC_WS_FORWARD, DRC_WS_BACKWARD, DRC_WS_STEP, DRC_WS_CALIBRATE, DRC_WS_AUTOTUNE = 1, 2, 4, 8, 16
 
 
 class DrcError(RuntimeError):

@@ -180,10 +180,12 @@ extern "C" drc_status drc_cae_set_tile(drc_cae* h, int layer, int H, int npw) {
     if (layer < 0 || layer > 5) return drc_fail(DRC_ERR_INVALID_ARG, "set_tile: layer %d", layer);
     if (npw != 0 && !npw_supported(h->prec, layer, false, npw))
         return drc_fail(DRC_ERR_UNSUPPORTED, "set_tile: npw %d not built for layer %d", npw, layer);
-    if (npw == 0)
+    if (npw == 0) {
         h->tile.erase({layer, H});
-    else
+        h->tile_px.erase({layer, H});
+    } else {
         h->tile[{layer, H}] = npw;
+    }
     return DRC_OK;
 }
 
@@ -358,7 +360,7 @@ extern "C" drc_status drc_cae_workspace_size(const drc_cae* h, int n, int H, int
                                              size_t* bytes) {
     if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "workspace_size: handle is NULL");
     if (!bytes) return drc_fail(DRC_ERR_INVALID_ARG, "workspace_size: bytes is NULL");
-    if (flags & ~(DRC_WS_FORWARD | DRC_WS_BACKWARD | DRC_WS_STEP | DRC_WS_CALIBRATE) || !flags)
+    if (flags & ~(DRC_WS_FORWARD | DRC_WS_BACKWARD | DRC_WS_STEP | DRC_WS_CALIBRATE | DRC_WS_AUTOTUNE) || !flags)
         return drc_fail(DRC_ERR_INVALID_ARG, "workspace_size: bad flags 0x%x", flags);
     TRY(check_shape("workspace_size", n, H, W));
     size_t need = 0;
@@ -370,6 +372,11 @@ extern "C" drc_status drc_cae_workspace_size(const drc_cae* h, int n, int H, int
     }
     if (flags & DRC_WS_BACKWARD) need = std::max(need, bwd_layout(h->prec, n, H, W, true).total);
     if (flags & DRC_WS_STEP) need = std::max(need, step_layout(h->prec, n, H, W, h->recompute).total);
+    if (flags & DRC_WS_AUTOTUNE) {
+        size_t f = align256((size_t)a.p0 * 3 * sizeof(float));
+        for (int k = 0; k < 5; ++k) f += a.bytes[k];
+        need = std::max(need, f);
+    }
     if (flags & DRC_WS_CALIBRATE) {
         ActSizes c = act_sizes(P_F32, n, H, W);
         size_t f = align256((size_t)c.p0 * 3 * sizeof(float));

@@ -44,7 +44,8 @@ struct drc_cae {
     bool params_set = false;
     bool calibrated = false;
     const float* packed_from = nullptr;
-    std::map<std::pair<int, int>, int> tile;  // (layer, H) -> pixel blocks per wave
+    std::map<std::pair<int, int>, int> tile;     // (layer, H) -> pixel blocks per wave
+    std::map<std::pair<int, int>, int> tile_px;  // (layer, H) -> GEMM pixels per work item
     // optional timing of kernel groups with events on the caller's stream
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -96,6 +97,33 @@ void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout);
 void wgrad_split(int l, int n, int H, int W, long* per_block, int* nchunks);
 BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed);
 StepLayout step_layout(int prec, int n, int H, int W, int recompute);
+
+// Buffers of one forward pass over a batch of equal-size maps. x_off/y_off
+// (device, per map, may be NULL) place each map's input/output inside packed
+// buffers of a mixed-resolution frame.
+struct FwdBufs {
+    const float* x;
+    float* y;
+    void *h1, *h2, *h3, *u3, *u2;
+    const long* x_off;
+    const long* y_off;
+};
+
+// One resolution class of a forward launch: its maps, buffers and the tile
+// shape per layer (0 = default).
+struct FwdClass {
+    FwdBufs b;
+    int n, H, W;
+    int tile_px[6];
+    int npw[6];
+};
+
+drc_status forward_dispatch(drc_cae* h, const FwdBufs& b, int n, int H, int W, int l0, int l1,
+                            hipStream_t s);
+template <int P>
+drc_status forward_classes(drc_cae* h, void* const* packs, const FwdClass* fc, int nclass, int l0, int l1,
+                           hipStream_t s);
+int pick_npw(const drc_cae* h, int l, int H, int prec, bool bwd);
 
 // Tile shapes: pixel blocks of 16 per wave built for each layer GEMM.
 bool npw_supported(int prec, int layer, bool backward, int npw);

@@ -40,50 +40,90 @@ bool npw_supported(int prec, int layer, bool backward, int npw) {
 }
 
 int default_npw(int prec, int layer, bool backward) {
-    (void)prec;
     const int mt = rows_pad_of(layer, backward) / 16;
-    return mt >= 8 ? 2 : (mt >= 4 ? 4 : (mt >= 2 ? 4 : 8));
+    const int npw = mt >= 8 ? 2 : (mt >= 4 ? 4 : (mt >= 2 ? 4 : 8));
+    // FP8 operands are 32 bytes per lane: halve the tile to stay out of scratch
+    return prec == P_FP8 ? std::max(1, npw / 2) : npw;
 }
 
 // ------------------------------------------------------------------ GEMM dispatch
+// Compile-time facts of one layer-GEMM instantiation: K step, packed row
+// length, LDS bytes for the weight pack and whether it is staged in LDS.
+template <int P, int MODE, int CIN, int COUTP>
+struct GemmCfg {
+    static constexpr int KS = (P == P_F32) ? 16 : (P == P_BF16 ? 32 : 128);
+    static constexpr int ES = (P == P_F32) ? 4 : (P == P_BF16 ? 2 : 1);
+    static constexpr int KSTRIDE = (((MODE == M_TCONV ? 4 : 9) * CIN) + KS - 1) / KS * KS;
+    static constexpr int LDS = COUTP * wlds_row_bytes(KSTRIDE, ES);
+    static constexpr bool WLDS = LDS <= 80 * 1024;
+};
+
 template <int P, int MODE, int CIN, int COUTP, int NPW, bool RAW, bool OF32>
-static void launch_one(const LayerArgs& a, dim3 grid, hipStream_t s) {
-    hipLaunchKernelGGL((conv_layer_kernel<P, MODE, CIN, COUTP, NPW, RAW, OF32>), grid, dim3(256), 0, s, a);
+static drc_status launch_one(const LayerArgs& a, dim3 grid, hipStream_t s) {
+    typedef GemmCfg<P, MODE, CIN, COUTP> C;
+    auto kern = conv_layer_kernel<P, MODE, CIN, COUTP, NPW, RAW, OF32, C::WLDS>;
+    const int lds = C::WLDS ? C::LDS : 0;
+    if (lds > 64 * 1024) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+                hipSuccess)
+                return drc_fail(DRC_ERR_HIP, "gemm: cannot raise the LDS limit to %d bytes", lds);
+            attr_set = true;
+        }
+    }
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, a);
+    return check_launch("gemm");
 }
 
+// Numbers the work items of every class and launches the persistent grid.
 template <int P, int MODE, int CIN, int COUTP, bool RAW, bool OF32>
-static drc_status launch_gemm(const LayerArgs& a, int npw, long npix, hipStream_t s) {
+static drc_status launch_gemm(LayerArgs& a, int npw, int num_cu, hipStream_t s) {
+    typedef GemmCfg<P, MODE, CIN, COUTP> C;
+    if (a.kstride != C::KSTRIDE) return drc_fail(DRC_ERR_STATE, "gemm: weight pack stride mismatch");
+    long items = 0;
+    for (int c = 0; c < a.nclass; ++c) {
+        ClassGeom& G = a.cls[c];
+        const long npix = (long)G.nmaps * G.Hg * G.Wg;
+        if (G.tile_px <= 0) G.tile_px = 64 * npw;
+        G.item0 = items;
+        G.items = (npix + G.tile_px - 1) / G.tile_px;
+        items += G.items;
+    }
+    a.total_items = items;
+    if (items == 0) return DRC_OK;
+    const int nphase = MODE == M_TCONV ? 4 : 1;
+    const int per_cu = C::WLDS ? std::max(1, std::min(4, (160 * 1024) / C::LDS)) : 4;
+    const long want = ((long)num_cu * per_cu + nphase - 1) / nphase;
+    dim3 grid((unsigned)std::min(items, want), nphase);
     constexpr int MT = COUTP / 16;
-    const long per = 64L * npw;
-    dim3 grid((unsigned)((npix + per - 1) / per), MODE == M_TCONV ? 4 : 1);
     switch (npw) {
         case 1:
-            if constexpr (MT * 1 <= 16) { launch_one<P, MODE, CIN, COUTP, 1, RAW, OF32>(a, grid, s); return check_launch("gemm"); }
+            if constexpr (MT * 1 <= 16) return launch_one<P, MODE, CIN, COUTP, 1, RAW, OF32>(a, grid, s);
             break;
         case 2:
-            if constexpr (MT * 2 <= 16) { launch_one<P, MODE, CIN, COUTP, 2, RAW, OF32>(a, grid, s); return check_launch("gemm"); }
+            if constexpr (MT * 2 <= 16) return launch_one<P, MODE, CIN, COUTP, 2, RAW, OF32>(a, grid, s);
             break;
         case 4:
-            if constexpr (MT * 4 <= 16) { launch_one<P, MODE, CIN, COUTP, 4, RAW, OF32>(a, grid, s); return check_launch("gemm"); }
+            if constexpr (MT * 4 <= 16) return launch_one<P, MODE, CIN, COUTP, 4, RAW, OF32>(a, grid, s);
             break;
         case 8:
-            if constexpr (MT * 8 <= 16) { launch_one<P, MODE, CIN, COUTP, 8, RAW, OF32>(a, grid, s); return check_launch("gemm"); }
+            if constexpr (MT * 8 <= 16) return launch_one<P, MODE, CIN, COUTP, 8, RAW, OF32>(a, grid, s);
             break;
     }
     return drc_fail(DRC_ERR_UNSUPPORTED, "gemm: tile npw=%d not built", npw);
 }
 
 template <int P>
-static drc_status run_gemm(int layer, bool bwd, const LayerArgs& a, int npw, hipStream_t s) {
-    const long npix = (long)a.nmaps * a.Hg * a.Wg;
+drc_status run_gemm(int layer, bool bwd, LayerArgs& a, int npw, int num_cu, hipStream_t s) {
     if (!bwd) {
         switch (layer) {
-            case 0: return launch_gemm<P, M_CONV, 8, 32, true, false>(a, npw, npix, s);
-            case 1: return launch_gemm<P, M_CONV, 32, 64, false, false>(a, npw, npix, s);
-            case 2: return launch_gemm<P, M_CONV, 64, 128, false, false>(a, npw, npix, s);
-            case 3: return launch_gemm<P, M_TCONV, 128, 64, false, false>(a, npw, npix, s);
-            case 4: return launch_gemm<P, M_TCONV, 128, 32, false, false>(a, npw, npix, s);
-            case 5: return launch_gemm<P, M_TCONV, 64, 16, false, true>(a, npw, npix, s);
+            case 0: return launch_gemm<P, M_CONV, 8, 32, true, false>(a, npw, num_cu, s);
+            case 1: return launch_gemm<P, M_CONV, 32, 64, false, false>(a, npw, num_cu, s);
+            case 2: return launch_gemm<P, M_CONV, 64, 128, false, false>(a, npw, num_cu, s);
+            case 3: return launch_gemm<P, M_TCONV, 128, 64, false, false>(a, npw, num_cu, s);
+            case 4: return launch_gemm<P, M_TCONV, 128, 32, false, false>(a, npw, num_cu, s);
+            case 5: return launch_gemm<P, M_TCONV, 64, 16, false, true>(a, npw, num_cu, s);
         }
     } else {
         if constexpr (P == P_FP8) {
@@ -91,17 +131,20 @@ static drc_status run_gemm(int layer, bool bwd, const LayerArgs& a, int npw, hip
         } else {
             constexpr int D1C = (P == P_F32) ? 4 : 8;
             switch (layer) {
-                case 5: return launch_gemm<P, M_CONV, D1C, 64, true, false>(a, npw, npix, s);
-                case 4: return launch_gemm<P, M_CONV, 32, 128, false, false>(a, npw, npix, s);
-                case 3: return launch_gemm<P, M_CONV, 64, 128, false, false>(a, npw, npix, s);
-                case 2: return launch_gemm<P, M_TCONV, 128, 64, false, false>(a, npw, npix, s);
-                case 1: return launch_gemm<P, M_TCONV, 64, 32, false, false>(a, npw, npix, s);
-                case 0: return launch_gemm<P, M_TCONV, 32, 16, false, true>(a, npw, npix, s);
+                case 5: return launch_gemm<P, M_CONV, D1C, 64, true, false>(a, npw, num_cu, s);
+                case 4: return launch_gemm<P, M_CONV, 32, 128, false, false>(a, npw, num_cu, s);
+                case 3: return launch_gemm<P, M_CONV, 64, 128, false, false>(a, npw, num_cu, s);
+                case 2: return launch_gemm<P, M_TCONV, 128, 64, false, false>(a, npw, num_cu, s);
+                case 1: return launch_gemm<P, M_TCONV, 64, 32, false, false>(a, npw, num_cu, s);
+                case 0: return launch_gemm<P, M_TCONV, 32, 16, false, true>(a, npw, num_cu, s);
             }
         }
     }
     return drc_fail(DRC_ERR_INVALID_ARG, "gemm: layer %d", layer);
 }
+template drc_status run_gemm<P_F32>(int, bool, LayerArgs&, int, int, hipStream_t);
+template drc_status run_gemm<P_BF16>(int, bool, LayerArgs&, int, int, hipStream_t);
+template drc_status run_gemm<P_FP8>(int, bool, LayerArgs&, int, int, hipStream_t);
 
 static Seg seg_none() {
     Seg s;
@@ -119,9 +162,10 @@ static Seg seg_out(void* dst, int c, int relu, float qscale) {
     return s;
 }
 
-static LayerArgs base_args(int l, int n, int H, int W, bool bwd, const void* wpack, int kstride) {
-    LayerArgs a;
-    memset(&a, 0, sizeof a);
+// Geometry of layer l's forward (or backward-data) GEMM for n maps of H x W.
+ClassGeom class_geom(int l, int n, int H, int W, bool bwd) {
+    ClassGeom G;
+    memset(&G, 0, sizeof G);
     int hin, win, hout, wout;
     layer_io(l, H, W, &hin, &win, &hout, &wout);
     if (bwd) {  // the data gradient runs from the layer output back to its input
@@ -129,23 +173,30 @@ static LayerArgs base_args(int l, int n, int H, int W, bool bwd, const void* wpa
         std::swap(win, wout);
     }
     const bool gemm_tconv = kLayers[l].tconv != bwd;
-    a.nmaps = n;
-    a.Hin = hin;
-    a.Win = win;
-    a.Hout = hout;
-    a.Wout = wout;
-    a.Hg = gemm_tconv ? hin : hout;
-    a.Wg = gemm_tconv ? win : wout;
+    G.nmaps = n;
+    G.Hin = hin;
+    G.Win = win;
+    G.Hout = hout;
+    G.Wout = wout;
+    G.Hg = gemm_tconv ? hin : hout;
+    G.Wg = gemm_tconv ? win : wout;
+    G.seg0 = seg_none();
+    G.seg1 = seg_none();
+    return G;
+}
+
+static LayerArgs layer_args(const void* wpack, int kstride) {
+    LayerArgs a;
+    memset(&a, 0, sizeof a);
+    a.nclass = 1;
     a.wpack = wpack;
     a.kstride = kstride;
     a.acc_scale = 1.0f;
     a.raw_qscale = 1.0f;
-    a.seg0 = seg_none();
-    a.seg1 = seg_none();
     return a;
 }
 
-static int pick_npw(const drc_cae* h, int l, int H, int prec, bool bwd) {
+int pick_npw(const drc_cae* h, int l, int H, int prec, bool bwd) {
     if (!bwd) {
         auto it = h->tile.find({l, H});
         if (it != h->tile.end()) return it->second;
@@ -154,69 +205,100 @@ static int pick_npw(const drc_cae* h, int l, int H, int prec, bool bwd) {
 }
 
 // ------------------------------------------------------------------ forward
-struct FwdBufs {
-    const float* x;
-    float* y;
-    void *h1, *h2, *h3, *u3, *u2;
-};
-
 // FP8 scale slots: 0..5 weights, 6 x, 7 [u2|h1], 8 [u3|h2], 9 h3.
 static const int kInScale[6] = {6, 7, 8, 9, 8, 7};
 static const int kOutScale[6] = {7, 8, 9, 8, 7, -1};
 
-// Runs layers [l0, l1] of the forward pass in precision P with packs.
+// Tensors of forward layer l for one class of maps.
+static void fwd_tensors(int l, const FwdBufs& b, int final_relu, float qout, ClassGeom& G) {
+    switch (l) {
+        case 0:
+            G.s0 = {b.x, 8, 7};
+            G.in_off = b.x_off;
+            G.seg0 = seg_out(b.h1, 32, 1, qout);
+            break;
+        case 1:
+            G.s0 = {b.h1, 32, 32};
+            G.seg0 = seg_out(b.h2, 64, 1, qout);
+            break;
+        case 2:
+            G.s0 = {b.h2, 64, 64};
+            G.seg0 = seg_out(b.h3, 128, 1, qout);
+            break;
+        case 3:
+            G.s0 = {b.h3, 128, 128};
+            G.seg0 = seg_out(b.u3, 64, 1, qout);
+            break;
+        case 4:
+            G.s0 = {b.u3, 64, 64};
+            G.s1 = {b.h2, 64, 64};
+            G.seg0 = seg_out(b.u2, 32, 1, qout);
+            break;
+        case 5:
+            G.s0 = {b.u2, 32, 32};
+            G.s1 = {b.h1, 32, 32};
+            G.seg0 = seg_out(b.y, 3, final_relu, 1.0f);
+            G.out_off = b.y_off;
+            break;
+    }
+}
+
+// Runs layers [l0, l1] of the forward pass in precision P with packs, over
+// nclass classes of maps (one launch per layer covers all classes).
 template <int P>
-static drc_status forward_seq(drc_cae* h, void* const* packs, const FwdBufs& b, int n, int H, int W,
-                              int l0, int l1, hipStream_t s) {
+drc_status forward_classes(drc_cae* h, void* const* packs, const FwdClass* fc, int nclass, int l0, int l1,
+                           hipStream_t s) {
+    if (nclass < 1 || nclass > kMaxClasses) return drc_fail(DRC_ERR_INVALID_ARG, "forward: %d classes", nclass);
     const float* sc = h->host_scales;
     for (int l = l0; l <= l1; ++l) {
         const GemmGeom g = gemm_geom(l, false, P);
-        LayerArgs a = base_args(l, n, H, W, false, packs[l], g.kstride);
+        LayerArgs a = layer_args(packs[l], g.kstride);
         a.bias = h->bias + bias_slot(l);
         float qout = 1.0f;
         if (P == P_FP8) {
             a.acc_scale = 1.0f / (sc[kInScale[l]] * sc[l]);
             if (kOutScale[l] >= 0) qout = sc[kOutScale[l]];
         }
-        switch (l) {
-            case 0:
-                a.s0 = {b.x, 8, 7};
-                a.raw_c = 7;
-                a.raw_qscale = P == P_FP8 ? sc[6] : 1.0f;
-                a.seg0 = seg_out(b.h1, 32, 1, qout);
-                break;
-            case 1:
-                a.s0 = {b.h1, 32, 32};
-                a.seg0 = seg_out(b.h2, 64, 1, qout);
-                break;
-            case 2:
-                a.s0 = {b.h2, 64, 64};
-                a.seg0 = seg_out(b.h3, 128, 1, qout);
-                break;
-            case 3:
-                a.s0 = {b.h3, 128, 128};
-                a.seg0 = seg_out(b.u3, 64, 1, qout);
-                break;
-            case 4:
-                a.s0 = {b.u3, 64, 64};
-                a.s1 = {b.h2, 64, 64};
-                a.seg0 = seg_out(b.u2, 32, 1, qout);
-                break;
-            case 5:
-                a.s0 = {b.u2, 32, 32};
-                a.s1 = {b.h1, 32, 32};
-                a.seg0 = seg_out(b.y, 3, h->desc.final_relu, 1.0f);
-                break;
+        if (l == 0) {
+            a.raw_c = 7;
+            a.raw_qscale = P == P_FP8 ? sc[6] : 1.0f;
         }
+        a.nclass = nclass;
+        int npw = 0;
+        for (int c = 0; c < nclass; ++c) {
+            a.cls[c] = class_geom(l, fc[c].n, fc[c].H, fc[c].W, false);
+            fwd_tensors(l, fc[c].b, h->desc.final_relu, qout, a.cls[c]);
+            a.cls[c].tile_px = fc[c].tile_px[l];
+            if (a.cls[c].tile_px <= 0) {
+                auto it = h->tile_px.find({l, fc[c].H});
+                if (it != h->tile_px.end()) a.cls[c].tile_px = it->second;
+            }
+        }
+        npw = fc[0].npw[l] > 0 ? fc[0].npw[l] : pick_npw(h, l, fc[0].H, P, false);
         const long tok = prof_begin(h, PROF_FWD + l, s);
-        TRY(run_gemm<P>(l, false, a, pick_npw(h, l, H, P, false), s));
+        TRY(run_gemm<P>(l, false, a, npw, h->num_cu, s));
         prof_end(h, tok, s);
     }
     return DRC_OK;
 }
+template drc_status forward_classes<P_F32>(drc_cae*, void* const*, const FwdClass*, int, int, int, hipStream_t);
+template drc_status forward_classes<P_BF16>(drc_cae*, void* const*, const FwdClass*, int, int, int, hipStream_t);
+template drc_status forward_classes<P_FP8>(drc_cae*, void* const*, const FwdClass*, int, int, int, hipStream_t);
 
-static drc_status forward_dispatch(drc_cae* h, const FwdBufs& b, int n, int H, int W, int l0, int l1,
-                                   hipStream_t s) {
+template <int P>
+static drc_status forward_seq(drc_cae* h, void* const* packs, const FwdBufs& b, int n, int H, int W,
+                              int l0, int l1, hipStream_t s) {
+    FwdClass fc;
+    memset(&fc, 0, sizeof fc);
+    fc.b = b;
+    fc.n = n;
+    fc.H = H;
+    fc.W = W;
+    return forward_classes<P>(h, packs, &fc, 1, l0, l1, s);
+}
+
+drc_status forward_dispatch(drc_cae* h, const FwdBufs& b, int n, int H, int W, int l0, int l1,
+                            hipStream_t s) {
     switch (h->prec) {
         case P_F32: return forward_seq<P_F32>(h, h->wf, b, n, H, W, l0, l1, s);
         case P_BF16: return forward_seq<P_BF16>(h, h->wf, b, n, H, W, l0, l1, s);
@@ -264,7 +346,7 @@ extern "C" drc_status drc_cae_forward(drc_cae* h, const float* d_x, float* d_y, 
         for (int k = 0; k < 5; ++k)
             if (off[k] >= 0) act[k] = (char*)d_saved + off[k];
     }
-    FwdBufs b{d_x, d_y, act[0], act[1], act[2], act[3], act[4]};
+    FwdBufs b{d_x, d_y, act[0], act[1], act[2], act[3], act[4], nullptr, nullptr};
     return forward_dispatch(h, b, n, H, W, 0, 5, (hipStream_t)stream);
 }
 
@@ -348,15 +430,17 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
     // D1: y = tconv([u2|h1]); its data gradient is a stride-2 conv of dy.
     {
         const GemmGeom g = gemm_geom(5, true, P);
-        LayerArgs a = base_args(5, n, H, W, true, h->wb[5], g.kstride);
-        a.s0 = {b.dy, g.cin_eff, 3};
+        LayerArgs a = layer_args(h->wb[5], g.kstride);
+        ClassGeom& G = a.cls[0];
+        G = class_geom(5, n, H, W, true);
+        G.s0 = {b.dy, g.cin_eff, 3};
         a.raw_c = 3;
-        a.seg0 = seg_out(dz_u2, 32, 0, 1.0f);
-        a.seg0.mask = b.u2;
-        a.seg0.ldm = 32;
-        a.seg1 = seg_out(dh1s, 32, 0, 1.0f);
+        G.seg0 = seg_out(dz_u2, 32, 0, 1.0f);
+        G.seg0.mask = b.u2;
+        G.seg0.ldm = 32;
+        G.seg1 = seg_out(dh1s, 32, 0, 1.0f);
         { const long tok = prof_begin(h, PROF_BWD + 5, s);
-        TRY(run_gemm<P>(5, true, a, default_npw(P, 5, true), s));
+        TRY(run_gemm<P>(5, true, a, default_npw(P, 5, true), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 5, s);
         TRY(weight_grad<T>(5, n, H, W, b.dy, true, Src{b.u2, 32, 32}, Src{b.h1, 32, 32}, 0, wpart,
@@ -369,14 +453,16 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
     // D2: u2 = relu(tconv([u3|h2]))
     {
         const GemmGeom g = gemm_geom(4, true, P);
-        LayerArgs a = base_args(4, n, H, W, true, h->wb[4], g.kstride);
-        a.s0 = {dz_u2, 32, 32};
-        a.seg0 = seg_out(dz_u3, 64, 0, 1.0f);
-        a.seg0.mask = b.u3;
-        a.seg0.ldm = 64;
-        a.seg1 = seg_out(dh2s, 64, 0, 1.0f);
+        LayerArgs a = layer_args(h->wb[4], g.kstride);
+        ClassGeom& G = a.cls[0];
+        G = class_geom(4, n, H, W, true);
+        G.s0 = {dz_u2, 32, 32};
+        G.seg0 = seg_out(dz_u3, 64, 0, 1.0f);
+        G.seg0.mask = b.u3;
+        G.seg0.ldm = 64;
+        G.seg1 = seg_out(dh2s, 64, 0, 1.0f);
         { const long tok = prof_begin(h, PROF_BWD + 4, s);
-        TRY(run_gemm<P>(4, true, a, default_npw(P, 4, true), s));
+        TRY(run_gemm<P>(4, true, a, default_npw(P, 4, true), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 4, s);
         TRY(weight_grad<T>(4, n, H, W, dz_u2, false, Src{b.u3, 64, 64}, Src{b.h2, 64, 64}, 0, wpart,
@@ -389,13 +475,15 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
     // D3: u3 = relu(tconv(h3))
     {
         const GemmGeom g = gemm_geom(3, true, P);
-        LayerArgs a = base_args(3, n, H, W, true, h->wb[3], g.kstride);
-        a.s0 = {dz_u3, 64, 64};
-        a.seg0 = seg_out(dz_h3, 128, 0, 1.0f);
-        a.seg0.mask = b.h3;
-        a.seg0.ldm = 128;
+        LayerArgs a = layer_args(h->wb[3], g.kstride);
+        ClassGeom& G = a.cls[0];
+        G = class_geom(3, n, H, W, true);
+        G.s0 = {dz_u3, 64, 64};
+        G.seg0 = seg_out(dz_h3, 128, 0, 1.0f);
+        G.seg0.mask = b.h3;
+        G.seg0.ldm = 128;
         { const long tok = prof_begin(h, PROF_BWD + 3, s);
-        TRY(run_gemm<P>(3, true, a, default_npw(P, 3, true), s));
+        TRY(run_gemm<P>(3, true, a, default_npw(P, 3, true), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 3, s);
         TRY(weight_grad<T>(3, n, H, W, dz_u3, false, Src{b.h3, 128, 128}, Src{nullptr, 0, 0}, 0, wpart,
@@ -408,15 +496,17 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
     // E3: h3 = relu(conv(h2)); dh2 = skip part + encoder part
     {
         const GemmGeom g = gemm_geom(2, true, P);
-        LayerArgs a = base_args(2, n, H, W, true, h->wb[2], g.kstride);
-        a.s0 = {dz_h3, 128, 128};
-        a.seg0 = seg_out(dz_h2, 64, 0, 1.0f);
-        a.seg0.add = dh2s;
-        a.seg0.lda = 64;
-        a.seg0.mask = b.h2;
-        a.seg0.ldm = 64;
+        LayerArgs a = layer_args(h->wb[2], g.kstride);
+        ClassGeom& G = a.cls[0];
+        G = class_geom(2, n, H, W, true);
+        G.s0 = {dz_h3, 128, 128};
+        G.seg0 = seg_out(dz_h2, 64, 0, 1.0f);
+        G.seg0.add = dh2s;
+        G.seg0.lda = 64;
+        G.seg0.mask = b.h2;
+        G.seg0.ldm = 64;
         { const long tok = prof_begin(h, PROF_BWD + 2, s);
-        TRY(run_gemm<P>(2, true, a, default_npw(P, 2, true), s));
+        TRY(run_gemm<P>(2, true, a, default_npw(P, 2, true), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 2, s);
         TRY(weight_grad<T>(2, n, H, W, dz_h3, false, Src{b.h2, 64, 64}, Src{nullptr, 0, 0}, 0, wpart,
@@ -429,15 +519,17 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
     // E2: h2 = relu(conv(h1))
     {
         const GemmGeom g = gemm_geom(1, true, P);
-        LayerArgs a = base_args(1, n, H, W, true, h->wb[1], g.kstride);
-        a.s0 = {dz_h2, 64, 64};
-        a.seg0 = seg_out(dz_h1, 32, 0, 1.0f);
-        a.seg0.add = dh1s;
-        a.seg0.lda = 32;
-        a.seg0.mask = b.h1;
-        a.seg0.ldm = 32;
+        LayerArgs a = layer_args(h->wb[1], g.kstride);
+        ClassGeom& G = a.cls[0];
+        G = class_geom(1, n, H, W, true);
+        G.s0 = {dz_h2, 64, 64};
+        G.seg0 = seg_out(dz_h1, 32, 0, 1.0f);
+        G.seg0.add = dh1s;
+        G.seg0.lda = 32;
+        G.seg0.mask = b.h1;
+        G.seg0.ldm = 32;
         { const long tok = prof_begin(h, PROF_BWD + 1, s);
-        TRY(run_gemm<P>(1, true, a, default_npw(P, 1, true), s));
+        TRY(run_gemm<P>(1, true, a, default_npw(P, 1, true), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 1, s);
         TRY(weight_grad<T>(1, n, H, W, dz_h2, false, Src{b.h1, 32, 32}, Src{nullptr, 0, 0}, 0, wpart,
@@ -458,12 +550,14 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         prof_end(h, tok, s); }
         if (b.dx) {
             const GemmGeom g = gemm_geom(0, true, P);
-            LayerArgs a = base_args(0, n, H, W, true, h->wb[0], g.kstride);
-            a.s0 = {dz_h1, 32, 32};
+            LayerArgs a = layer_args(h->wb[0], g.kstride);
+            ClassGeom& G = a.cls[0];
+            G = class_geom(0, n, H, W, true);
+            G.s0 = {dz_h1, 32, 32};
             a.acc_scale = gscale;
-            a.seg0 = seg_out(b.dx, 7, 0, 1.0f);
+            G.seg0 = seg_out(b.dx, 7, 0, 1.0f);
             { const long tok = prof_begin(h, PROF_BWD + 0, s);
-            TRY(run_gemm<P>(0, true, a, default_npw(P, 0, true), s));
+            TRY(run_gemm<P>(0, true, a, default_npw(P, 0, true), h->num_cu, s));
             prof_end(h, tok, s); }
         }
     }
@@ -473,7 +567,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
 // Recompute h3, u3 and u2 from the saved h2 (layers E3, D3, D2).
 static drc_status recompute_acts(drc_cae* h, BwdBufs& b, int n, int H, int W, hipStream_t s) {
     FwdBufs f{nullptr, nullptr, const_cast<void*>(b.h1), const_cast<void*>(b.h2), b.ws + b.L.recomp[0],
-              b.ws + b.L.recomp[1], b.ws + b.L.recomp[2]};
+              b.ws + b.L.recomp[1], b.ws + b.L.recomp[2], nullptr, nullptr};
     TRY(forward_dispatch(h, f, n, H, W, 2, 4, s));
     b.h3 = f.h3;
     b.u3 = f.u3;
@@ -576,7 +670,7 @@ extern "C" drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, floa
     }
     float* y = (float*)(ws + S.y);
     float* dy = (float*)(ws + S.dy);
-    FwdBufs fb{d_x, y, act[0], act[1], act[2], act[3], act[4]};
+    FwdBufs fb{d_x, y, act[0], act[1], act[2], act[3], act[4], nullptr, nullptr};
     TRY(forward_dispatch(h, fb, n, H, W, 0, 5, s));
 
     // L1 loss (mean) and dL/dy; dy is stored as sign(y - t) and the 1/M
@@ -644,7 +738,7 @@ extern "C" drc_status drc_cae_calibrate_fp8(drc_cae* h, const float* d_x, int n,
         cur += a.bytes[k];
     }
     float* y = (float*)(ws + cur);
-    FwdBufs b{d_x, y, act[0], act[1], act[2], act[3], act[4]};
+    FwdBufs b{d_x, y, act[0], act[1], act[2], act[3], act[4], nullptr, nullptr};
     TRY(forward_seq<P_F32>(h, h->wcal, b, n, H, W, 0, 5, s));
     HIPCHK(hipMemsetAsync(h->amax + 6, 0, 6 * sizeof(unsigned), s));
     const long cnt[6] = {a.p0 * 7, a.p1 * 32, a.p2 * 64, a.p3 * 128, a.p2 * 64, a.p1 * 32};

@@ -1,0 +1,135 @@
+"""Mixed-resolution frames (one persistent, graph-captured pass over maps of
+several sizes) and the tile autotuner (needs gfx950).
+
+A map's output must not depend on the frame it sits in: the plan's result
+for every map is compared bitwise with a uniform forward of that map's
+resolution class, on every replay of the captured graph (with other eager
+work between replays), and a sample is checked against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1910_02480_amd import binding as B
+from paper_1910_02480_amd import synth
+from tests.helpers import max_rel_per_map
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def params():
+    return synth.init_params(0)
+
+
+def _frame(sizes):
+    """Packed frame of maps with the given (h, w) sizes."""
+    pix = np.array([h * w for h, w in sizes], dtype=np.int64)
+    xo = np.concatenate([[0], np.cumsum(pix * 7)[:-1]])
+    yo = np.concatenate([[0], np.cumsum(pix * 3)[:-1]])
+    x = np.empty(int(pix.sum()) * 7, dtype=np.float32)
+    for m, (h, w) in enumerate(sizes):
+        x[xo[m]:xo[m] + h * w * 7] = synth.radiance_map(m, h, w).reshape(-1)
+    return x, xo, yo, int(pix.sum()) * 3
+
+
+@pytest.mark.parametrize("compute,gate", [("bf16", 1e-2), ("f32", 1e-5)])
+def test_plan_mixed_frame(oracle, params, compute, gate):
+    from paper_1910_02480_amd.cae import CAE
+    res = synth.mixed_resolutions(60)
+    sizes = [(int(r), int(r)) for r in res] + [(24, 40), (24, 40), (24, 40)]
+    x, xo, yo, ny = _frame(sizes)
+    cae = CAE(compute, torch.from_numpy(params).to(DEV), device=DEV)
+    maps = [(h, w, int(xo[m]), int(yo[m])) for m, (h, w) in enumerate(sizes)]
+    plan = B.drc_cae_plan_create(cae.h, maps)
+    try:
+        ws = torch.empty(B.drc_cae_plan_workspace_size(plan) + 256, dtype=torch.uint8, device=DEV)
+        ws = ws[(-ws.data_ptr()) % 256:]
+        xd = torch.from_numpy(x).to(DEV)
+        # reference: uniform forward of each map on its own
+        ref = {}
+        for m, (h, w) in enumerate(sizes):
+            xm = xd[xo[m]:xo[m] + h * w * 7].view(1, h, w, 7)
+            ref[m] = cae.forward(xm).cpu().numpy().reshape(-1)
+        outs = []
+        stream = torch.cuda.Stream(device=DEV)  # a capturable (non-null) stream
+        torch.cuda.synchronize()
+        for rep in range(3):
+            with torch.cuda.stream(stream):
+                yd = torch.full((ny,), float("nan"), device=DEV)
+                B.drc_cae_plan_launch(plan, xd, yd, ws)      # captured once, then replayed
+                junk = torch.randn(1 << 20, device=DEV).sum()  # eager work between replays
+            torch.cuda.synchronize()
+            y = yd.cpu().numpy()
+            for m, (h, w) in enumerate(sizes):
+                np.testing.assert_array_equal(y[yo[m]:yo[m] + h * w * 3], ref[m], err_msg=f"rep {rep} map {m}")
+            outs.append(y)
+            del junk
+        # null stream: direct launches, same result
+        yd = torch.zeros((ny,), device=DEV)
+        B.drc_cae_plan_launch(plan, xd, yd, ws, stream=0)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(yd.cpu().numpy(), outs[0])
+    finally:
+        B.drc_cae_plan_destroy(plan)
+    # oracle on one map of each size
+    seen = {}
+    for m, s in enumerate(sizes):
+        seen.setdefault(s, m)
+    for (h, w), m in seen.items():
+        r = oracle.forward(params, synth.radiance_map(m, h, w)[None])["y"]
+        g = outs[0][yo[m]:yo[m] + h * w * 3].reshape(1, h, w, 3)
+        assert max_rel_per_map(g, r).max() <= gate, (h, w)
+
+
+def test_plan_validation(params):
+    from paper_1910_02480_amd.cae import CAE
+    cae = CAE("bf16", torch.from_numpy(params).to(DEV), device=DEV)
+    with pytest.raises(B.DrcError) as e:
+        B.drc_cae_plan_create(cae.h, [])
+    assert e.value.status == 2
+    with pytest.raises(B.DrcError) as e:
+        B.drc_cae_plan_create(cae.h, [(30, 32, 0, 0)])
+    assert e.value.status == 2
+    with pytest.raises(B.DrcError) as e:
+        B.drc_cae_plan_create(cae.h, [(8 * (k + 1), 8, 0, 0) for k in range(5)])
+    assert e.value.status == 3
+    plan = B.drc_cae_plan_create(cae.h, [(32, 32, 0, 0)])
+    try:
+        need = B.drc_cae_plan_workspace_size(plan)
+        ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+        x = torch.zeros(32 * 32 * 7, device=DEV)
+        y = torch.zeros(32 * 32 * 3, device=DEV)
+        with pytest.raises(B.DrcError) as e:
+            B.drc_cae_plan_launch(plan, x, y, ws[: need - 256] if need > 256 else ws[:0])
+        assert e.value.status in (1, 4)
+    finally:
+        B.drc_cae_plan_destroy(plan)
+
+
+def test_autotune_keeps_results_bitwise(tmp_path, params):
+    """Tile shapes change the schedule only: outputs stay bitwise equal."""
+    from paper_1910_02480_amd.cae import CAE
+    cae = CAE("bf16", torch.from_numpy(params).to(DEV), device=DEV)
+    x = torch.from_numpy(synth.radiance_maps(64, 64, 64)).to(DEV)
+    y0 = cae.forward(x).cpu().numpy()
+    cache = str(tmp_path / "tune.jsonl")
+    n, H, W = 64, 64, 64
+    ws = cae.workspace(n, H, W, B.DRC_WS_AUTOTUNE)
+    B.drc_cae_autotune(cae.h, x, ws, cache)
+    lines = open(cache).read().strip().split("\n")
+    assert len(lines) == 6 and all('"layer"' in ln and '"npw"' in ln for ln in lines)
+    y1 = cae.forward(x).cpu().numpy()
+    np.testing.assert_array_equal(y0, y1)
+    # a plan reads the cache and agrees too
+    maps = [(64, 64, k * 64 * 64 * 7, k * 64 * 64 * 3) for k in range(n)]
+    plan = B.drc_cae_plan_create(cae.h, maps, cache)
+    try:
+        w2 = torch.empty(B.drc_cae_plan_workspace_size(plan), dtype=torch.uint8, device=DEV)
+        yd = torch.empty(n * H * W * 3, device=DEV)
+        B.drc_cae_plan_launch(plan, x.reshape(-1), yd, w2)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(yd.cpu().numpy(), y0.reshape(-1))
+    finally:
+        B.drc_cae_plan_destroy(plan)
