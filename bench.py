@@ -165,6 +165,9 @@ def main():
     ap.add_argument("--main-only", action="store_true", help="time only the headline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--frame-maps", type=int, default=6000)
     ap.add_argument("--frame-reps", type=int, default=200)
     args = ap.parse_args()
@@ -190,11 +193,19 @@ def main():
     y = torch.empty((n, H, H, 3), dtype=torch.float32, device=dev)
     legs = {}
 
+    if args.copy_calib:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # ---------------- headline: BF16 forward, profiled live
     cae = CAE("bf16", params, device=dev)
     tune_path = os.path.join(tempfile.gettempdir(), f"drc_tune_{os.getpid()}.jsonl")
-    log("autotuning tile shapes for the headline batch")
-    B.drc_cae_autotune(cae.h, x, cae.workspace(n, H, H, B.DRC_WS_AUTOTUNE), tune_path)
+    if not args.no_autotune:
+        log("autotuning tile shapes for the headline batch")
+        B.drc_cae_autotune(cae.h, x, cae.workspace(n, H, H, B.DRC_WS_AUTOTUNE), tune_path)
     ws = cae.workspace(n, H, H, B.DRC_WS_FORWARD)
     fwd = lambda: B.drc_cae_forward(cae.h, x, y, None, ws)
     for _ in range(args.warmup):
@@ -264,6 +275,16 @@ def main():
                 B.drc_cae_backward(c.h, x, dy, saved, dp, None, wb)
             tt = timed(fb, max(3, args.steps // 2), 2)
             legs[f"{comp}_fwd_bwd"] = {"maps_per_s": n / tt, "ms": tt * 1e3}
+            # one more pass with the timing hook on: where the backward time goes
+            B.drc_cae_profile(c.h, 1)
+            B.drc_cae_profile_read(c.h)
+            fb()
+            ms_s, calls_s = B.drc_cae_profile_read(c.h)
+            B.drc_cae_profile(c.h, 0)
+            names = [f"fwd {LAYERS[l][0]}" for l in range(6)] + [f"dgrad {LAYERS[l][0]}" for l in range(6)] + \
+                    [f"wgrad {LAYERS[l][0]}" for l in range(6)] + ["bias grads", "loss", "adam"]
+            legs[f"{comp}_fwd_bwd"]["breakdown_ms"] = {names[k]: round(ms_s[k], 4) for k in range(21)
+                                                       if calls_s[k]}
             log(f"{comp} forward+backward: {n / tt:,.0f} maps/s")
             del c, saved, dy, wf, wb
         # ---------------- training step (fwd + L1 + bwd + Adam + repack), recompute on

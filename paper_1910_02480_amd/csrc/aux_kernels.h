@@ -123,10 +123,13 @@ static __global__ void l1_final_kernel(const double* partial, int nparts, long c
 }
 
 // ------------------------------------------------------------------ bias gradient
-// partial[b][c] = sum over the block's pixel range of g[pix][c].
+// Column sums of a [npix][C] tensor in two fixed-order stages:
+// colsum_partial: block b sums rows [b*per, (b+1)*per) into partial[b][c];
+// colsum_final: one workgroup per column adds the partials (strided per
+// thread, then a tree in LDS) and scales.
 template <typename TG>
-__global__ __launch_bounds__(256) void bias_partial_kernel(const TG* g, int C, int cpow2, int ld,
-                                                           long npix, long per_block, float* partial) {
+__global__ __launch_bounds__(256) void colsum_partial_kernel(const TG* g, int C, int cpow2, int ld, long npix,
+                                                             long per_block, float* partial) {
     __shared__ float red[256];
     const int c = threadIdx.x % cpow2, po = threadIdx.x / cpow2, stride = 256 / cpow2;
     const long b0 = blockIdx.x * per_block, b1 = min(npix, b0 + per_block);
@@ -142,144 +145,205 @@ __global__ __launch_bounds__(256) void bias_partial_kernel(const TG* g, int C, i
     if (po == 0 && c < C) partial[(long)blockIdx.x * C + c] = red[threadIdx.x];
 }
 
-// out[e] = scale * sum_s partial[s][e], fixed order over s.
-static __global__ void sum_partials_kernel(const float* partial, int nslots, long count, float scale,
-                                    float* out) {
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count;
-         e += (long)gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        for (int k = 0; k < nslots; ++k) s += partial[(long)k * count + e];
-        out[e] = s * scale;
+static __global__ __launch_bounds__(256) void colsum_final_kernel(const float* partial, int nblocks, int C,
+                                                                  float scale, float* out) {
+    __shared__ float red[256];
+    const int c = blockIdx.x;
+    float s = 0.0f;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partial[(long)b * C + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[c] = red[0] * scale;
 }
 
 // ------------------------------------------------------------------ weight gradient
-// dW[co][kh][kw][ci] = sum_k G_t[k][co] * A_t[k][ci] with t = 3 kh + kw.
-// Convolution layer: k runs over output pixels (n,p,q); G_t = g[n,p,q];
-//   A_t = a[n, 2p+kh-1, 2q+kw-1] (0 outside).
-// Transposed convolution layer: k runs over input pixels (n,i,j);
-//   G_t = g[n, 2i+kh-1, 2j+kw-1] (0 outside); A_t = a[n,i,j].
-// One workgroup handles one tap, one 64x64 (co, ci) tile and one range of
-// k; each of its 4 waves takes every 4th group of 4 pixels and writes its
-// own partial sum slot, reduced later in a fixed order. FP32 MFMA
-// (16x16x4): lane l feeds pixel k0 + l/16 and the 4 channels
-// 4 (l % 16) .. +3 of the tile, issuing one MFMA per (A element, B element)
-// pair, so block (ja, jb) holds channels (4i + ja, 4i' + jb).
+// dW of a stride-2 3x3 layer as one reduction over "reduction pixels"
+// (n,u,v) on an Hr x Wr grid, with two operands:
+//   plain    P[n,u,v][cp]                       (tap independent)
+//   gathered Q[n, 2u+kh-1, 2v+kw-1][cq]          (zero outside Hq x Wq)
+//   D[j = t*cq + c][cp] = sum_(n,u,v) Q_t[.][c] * P[.][cp],  t = 3 kh + kw.
+// Convolution layer: reduction over its output pixels, P = output gradient
+// (cp = Cout), Q = layer input (cq = Cin): dW[co][t][ci] = D[t*Cin+ci][co].
+// Transposed convolution layer: reduction over its input pixels, P = layer
+// input (cp = Cin), Q = output gradient (cq = Cout), since output pixel
+// 2i+kh-1 receives input pixel i through row kh: dW[co][t][ci] = D[t*Cout+co][ci].
+// MFMA rows are the flattened (tap, channel) pairs j, so 3- and 7-channel
+// layers waste little, and all nine taps come out of one pass over the data.
+//
+// Schedule: FP32 MFMA 16x16x4, K = 4 reduction pixels per MFMA (one per
+// 16-lane group). A workgroup owns one tile of JB x PB blocks of 16x16 and a
+// range of reduction pixels split into 4 contiguous quarters, one per wave.
+// With VEC = 4 a lane loads 4 consecutive channels at once and feeds them to
+// 4 MFMA blocks (block i holds rows/columns 4r+i of its 64-wide group); the
+// loads of the next U pixel groups are issued before the MFMAs of the
+// current ones. Each wave writes its own partial tile (no atomics); partial
+// tiles are added later in a fixed order.
 struct WgradArgs {
-    const void* g; int gc; int gld; int g_raw;  // g_raw: g is float32
-    Src s0, s1; int a_raw_c;                    // a_raw_c > 0: s0 float32 with that many channels
-    int mode;                                   // layer kind: M_CONV or M_TCONV
-    int nmaps, Hin, Win, Hout, Wout;
-    int cout, cin;
-    long per_block;                             // reduction pixels per workgroup
-    int co_tiles, ci_tiles;
-    float* partial;                             // [slot][9][cout][cin]
+    const void* p; const void* p2;  // plain operand: channels [0, pc0) from p, the rest from p2
+    int p_raw, pc, pc0, pld, p2ld;  // p_raw: float32 source
+    const void* q;                  // gathered operand
+    int q_raw, qc, qld;
+    int nmaps, Hr, Wr, Hq, Wq;
+    long per_block;                 // reduction pixels per workgroup
+    int jtiles;                     // tiles along j (blockIdx.y = jt + jtiles * pt)
+    float* partial;                 // [slot = 4*chunk + wave][9*qc][pc]
 };
 
-template <typename TG, typename TA>
-__device__ __forceinline__ f4 ld4(const TG* p, int navail) {
-    f4 v = {0.f, 0.f, 0.f, 0.f};
-    if (navail >= 4) {
-        v.x = to_float<TG>(p[0]); v.y = to_float<TG>(p[1]);
-        v.z = to_float<TG>(p[2]); v.w = to_float<TG>(p[3]);
+template <typename T, int VEC>
+__device__ __forceinline__ void ld_vec(const void* base, bool raw, long idx, int navail, float (&o)[VEC]) {
+    if constexpr (VEC == 1) {
+        o[0] = navail > 0 ? (raw ? ((const float*)base)[idx] : to_float<T>(((const T*)base)[idx])) : 0.0f;
     } else {
-        if (navail > 0) v.x = to_float<TG>(p[0]);
-        if (navail > 1) v.y = to_float<TG>(p[1]);
-        if (navail > 2) v.z = to_float<TG>(p[2]);
+        if (navail >= 4) {
+            if (raw) {
+                const float4 v = *(const float4*)((const float*)base + idx);
+                o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+            } else if constexpr (sizeof(T) == 4) {
+                const float4 v = *(const float4*)((const float*)base + idx);
+                o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+            } else {
+                const uint2 v = *(const uint2*)((const T*)base + idx);
+                o[0] = bf16_to_f32((uint16_t)(v.x & 0xffff));
+                o[1] = bf16_to_f32((uint16_t)(v.x >> 16));
+                o[2] = bf16_to_f32((uint16_t)(v.y & 0xffff));
+                o[3] = bf16_to_f32((uint16_t)(v.y >> 16));
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                o[e] = (e < navail) ? (raw ? ((const float*)base)[idx + e] : to_float<T>(((const T*)base)[idx + e]))
+                                    : 0.0f;
+        }
     }
-    return v;
 }
 
-template <typename T>
+template <typename T, int JB, int PB, int VEC>
 __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
+    static_assert(JB % VEC == 0 && PB % VEC == 0, "vector loads feed VEC blocks");
+    constexpr int U = 4;           // pixel groups in flight per wave
+    constexpr int JG = JB / VEC;   // load groups along j
+    constexpr int PG = PB / VEC;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kq = lane >> 4, r16 = lane & 15;
-    const int t = blockIdx.y;
-    const int kh = t / 3, kw = t % 3;
-    const int cot = blockIdx.z % a.co_tiles, cit = blockIdx.z / a.co_tiles;
-    const int co0 = cot * 64 + 4 * r16, ci0 = cit * 64 + 4 * r16;
-    const long Kh = (a.mode == M_CONV) ? a.Hout : a.Hin;
-    const long Kw = (a.mode == M_CONV) ? a.Wout : a.Win;
-    const long K = (long)a.nmaps * Kh * Kw;
+    const int jt = blockIdx.y % a.jtiles, pt = blockIdx.y / a.jtiles;
+    const int J = 9 * a.qc;
+    // Row j of block (group jg, element i) for this lane: VEC == 4 ->
+    // jg*64 + 4*r16 + i; VEC == 1 -> block jg*16 + r16.
+    int tkh[JG], tkw[JG], tch[JG], jav[JG];
+#pragma unroll
+    for (int b = 0; b < JG; ++b) {
+        const int j = (jt * JB) * 16 + b * 16 * VEC + VEC * r16;
+        const int t = j < J ? j / a.qc : 9;
+        tch[b] = j < J ? j - t * a.qc : 0;
+        tkh[b] = t / 3;
+        tkw[b] = t - 3 * (t / 3);
+        // channels of this tap available from j on (vector loads never cross a tap)
+        jav[b] = j < J ? min(VEC, a.qc - tch[b]) : 0;
+    }
+    int pch[PG], pav[PG];
+#pragma unroll
+    for (int b = 0; b < PG; ++b) {
+        pch[b] = (pt * PB) * 16 + b * 16 * VEC + VEC * r16;
+        pav[b] = pch[b] < a.pc ? min(VEC, a.pc - pch[b]) : 0;
+    }
+    const int hw = a.Hr * a.Wr;
+    const long K = (long)a.nmaps * hw;
     const long k_begin = blockIdx.x * a.per_block;
     const long k_end = min(K, k_begin + a.per_block);
+    const long quarter = ((a.per_block + 15) / 16) * 4;  // multiple of 4 pixels
+    const long w_begin = k_begin + wave * quarter;
+    const long w_end = min(k_end, w_begin + quarter);
 
-    f4 acc[4][4];
+    f4 acc[JB][PB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < JB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < PB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (long kb = k_begin + wave * 4; kb < k_end; kb += 16) {
-        const long k = kb + kq;
-        f4 gv = {0.f, 0.f, 0.f, 0.f}, av = {0.f, 0.f, 0.f, 0.f};
-        if (k < k_end) {
-            const int n = (int)(k / (Kh * Kw));
-            const int rem = (int)(k - (long)n * Kh * Kw);
-            const int u = rem / (int)Kw, v = rem % (int)Kw;
-            long gpix = -1, apix = -1;
-            if (a.mode == M_CONV) {
-                gpix = k;
-                const int i = 2 * u + kh - 1, j = 2 * v + kw - 1;
-                if ((unsigned)i < (unsigned)a.Hin && (unsigned)j < (unsigned)a.Win)
-                    apix = ((long)n * a.Hin + i) * a.Win + j;
-            } else {
-                apix = k;
-                const int p = 2 * u + kh - 1, q = 2 * v + kw - 1;
-                if ((unsigned)p < (unsigned)a.Hout && (unsigned)q < (unsigned)a.Wout)
-                    gpix = ((long)n * a.Hout + p) * a.Wout + q;
-            }
-            if (gpix >= 0 && apix >= 0) {
-                if (a.g_raw)
-                    gv = ld4<float, float>((const float*)a.g + gpix * a.gld + co0, a.cout - co0);
+    float qv[2][U][JG][VEC], pv[2][U][PG][VEC];
+    auto load = [&](int buf, long k0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long k = k0 + 4 * u + kq;
+            const bool ok = k < w_end;
+            const int kk = ok ? (int)k : 0;
+            const int n = kk / hw;
+            const int rem = kk - n * hw;
+            const int uu = rem / a.Wr, vv = rem - (rem / a.Wr) * a.Wr;
+#pragma unroll
+            for (int b = 0; b < PG; ++b) {
+                const int c = pch[b];
+                if (c < a.pc0)
+                    ld_vec<T, VEC>(a.p, a.p_raw, (long)kk * a.pld + c, ok ? pav[b] : 0, pv[buf][u][b]);
                 else
-                    gv = ld4<T, T>((const T*)a.g + gpix * a.gld + co0, a.cout - co0);
-                if (a.a_raw_c > 0) {
-                    av = ld4<float, float>((const float*)a.s0.p + apix * a.s0.ld + ci0, a.cin - ci0);
-                } else if (ci0 < a.s0.c) {
-                    av = ld4<T, T>((const T*)a.s0.p + apix * a.s0.ld + ci0, a.s0.c - ci0);
-                } else {
-                    av = ld4<T, T>((const T*)a.s1.p + apix * a.s1.ld + (ci0 - a.s0.c),
-                                   a.cin - ci0);
-                }
+                    ld_vec<T, VEC>(a.p2, false, (long)kk * a.p2ld + (c - a.pc0), ok ? pav[b] : 0, pv[buf][u][b]);
+            }
+#pragma unroll
+            for (int b = 0; b < JG; ++b) {
+                const int i = 2 * uu + tkh[b] - 1, jj = 2 * vv + tkw[b] - 1;
+                const bool in = ok && (unsigned)i < (unsigned)a.Hq && (unsigned)jj < (unsigned)a.Wq;
+                ld_vec<T, VEC>(a.q, a.q_raw, (((long)n * a.Hq + (in ? i : 0)) * a.Wq + (in ? jj : 0)) * a.qld + tch[b],
+                               in ? jav[b] : 0, qv[buf][u][b]);
             }
         }
-        const float ga[4] = {gv.x, gv.y, gv.z, gv.w};
-        const float aa[4] = {av.x, av.y, av.z, av.w};
+    };
+    int cur = 0;
+    if (w_begin < w_end) load(0, w_begin);
+    for (long k0 = w_begin; k0 < w_end; k0 += 4 * U) {
+        if (k0 + 4 * U < w_end) load(cur ^ 1, k0 + 4 * U);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[i], aa[j], acc[i][j], 0, 0, 0);
+            for (int bj = 0; bj < JG; ++bj)
+#pragma unroll
+                for (int ej = 0; ej < VEC; ++ej)
+#pragma unroll
+                    for (int bp = 0; bp < PG; ++bp)
+#pragma unroll
+                        for (int ep = 0; ep < VEC; ++ep)
+                            acc[bj * VEC + ej][bp * VEC + ep] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                qv[cur][u][bj][ej], pv[cur][u][bp][ep], acc[bj * VEC + ej][bp * VEC + ep], 0, 0, 0);
+        cur ^= 1;
     }
 
-    // D[row][col] of block (i, j): lane holds rows 4*kq + r, column r16.
-    const long slot = (long)blockIdx.x * 4 + wave;
-    float* out = a.partial + (slot * 9 + t) * (long)a.cout * a.cin;
+    // D row (4*kq + r) of block (bj*VEC + ej) <-> j; column r16 of block (bp*VEC + ep) <-> cp.
+    float* out = a.partial + ((long)blockIdx.x * 4 + wave) * J * a.pc;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int bj = 0; bj < JG; ++bj)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int ej = 0; ej < VEC; ++ej)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int co = cot * 64 + 4 * (4 * kq + r) + i;
-                const int ci = cit * 64 + 4 * r16 + j;
-                if (co < a.cout && ci < a.cin) out[(long)co * a.cin + ci] = acc[i][j][r];
-            }
+            for (int bp = 0; bp < PG; ++bp)
+#pragma unroll
+                for (int ep = 0; ep < VEC; ++ep)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 4 * kq + r;
+                        const int j = (jt * JB) * 16 + bj * 16 * VEC + VEC * row + ej;
+                        const int cp = (pt * PB) * 16 + bp * 16 * VEC + VEC * r16 + ep;
+                        if (j < J && cp < a.pc) out[(long)j * a.pc + cp] = acc[bj * VEC + ej][bp * VEC + ep][r];
+                    }
 }
 
-// dW in parameter layout from partial[slot][t][co][ci]: fixed-order sum.
-static __global__ void wgrad_final_kernel(const float* partial, int nslots, int cout, int cin, float scale,
-                                   float* dw) {
-    const long count = 9L * cout * cin;
+// dW in the parameter layout from partial[chunk][j][cp] (fixed-order sum).
+// q_is_cout: 1 for transposed-convolution layers (j = t*Cout + co, cp = ci),
+// 0 for convolution layers (j = t*Cin + ci, cp = co).
+static __global__ void wgrad_final_kernel(const float* partial, int nchunks, int qc, int pc, int q_is_cout,
+                                          float scale, float* dw) {
+    const long count = 9L * qc * pc;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count;
          e += (long)gridDim.x * blockDim.x) {
-        // e indexes the partial layout [t][co][ci]
-        const int ci = (int)(e % cin);
-        const int co = (int)((e / cin) % cout);
-        const int t = (int)(e / ((long)cin * cout));
+        const int cp = (int)(e % pc);
+        const int j = (int)(e / pc);
+        const int t = j / qc, c = j - (j / qc) * qc;
         float s = 0.0f;
-        for (int k = 0; k < nslots; ++k) s += partial[(long)k * count + e];
+        for (int k = 0; k < nchunks; ++k) s += partial[(long)k * count + e];
+        const int co = q_is_cout ? c : cp, ci = q_is_cout ? cp : c;
+        const int cin = q_is_cout ? pc : qc;
         dw[((long)co * 9 + t) * cin + ci] = s * scale;
     }
 }

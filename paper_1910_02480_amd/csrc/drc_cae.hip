@@ -272,18 +272,34 @@ extern "C" drc_status drc_cae_saved_size(const drc_cae* h, int n, int H, int W, 
     return DRC_OK;
 }
 
-// Weight-gradient reduction split for layer l: pixels per workgroup.
-void wgrad_split(int l, int n, int H, int W, long* per_block, int* nchunks) {
+// Weight-gradient work split for layer l (see wgrad_kernel): MFMA tile
+// blocks, reduction pixels per workgroup and number of reduction chunks.
+WgradPlan wgrad_plan(int l, int n, int H, int W) {
     const LayerDef& L = kLayers[l];
     int hin, win, hout, wout;
     layer_io(l, H, W, &hin, &win, &hout, &wout);
-    const long K = (long)n * (L.tconv ? (long)hin * win : (long)hout * wout);
-    const int tiles = ((L.cout + 63) / 64) * ((L.cin + 63) / 64);
-    long want = std::max(1L, 2048L / (9L * tiles));
+    WgradPlan w;
+    w.qc = L.tconv ? L.cout : L.cin;  // gathered operand channels
+    w.pc = L.tconv ? L.cin : L.cout;  // plain operand channels
+    w.Hr = L.tconv ? hin : hout;
+    w.Wr = L.tconv ? win : wout;
+    const int jblocks = (9 * w.qc + 15) / 16, pblocks = (w.pc + 15) / 16;
+    w.JB = jblocks >= 4 ? 4 : 2;
+    w.PB = (w.JB == 4 && pblocks <= 2) ? 2 : 4;
+    w.VEC = (w.JB == 4 && w.PB == 4 && w.qc % 4 == 0 && w.pc % 4 == 0) ? 4 : 1;
+    w.jtiles = (jblocks + w.JB - 1) / w.JB;
+    w.ptiles = (pblocks + w.PB - 1) / w.PB;
+    const long K = (long)n * w.Hr * w.Wr;
+    // about 2048 workgroups, at most 256 chunks and 64 MB of partial tiles
+    const long per_chunk_floats = 4L * 9 * w.qc * w.pc;
+    long want = std::max(1L, std::min(256L, 2048L / (w.jtiles * w.ptiles)));
+    want = std::max(1L, std::min(want, (16L << 20) / per_chunk_floats));
     long pb = (K + want - 1) / want;
-    pb = std::max(256L, (pb + 15) / 16 * 16);
-    *per_block = pb;
-    *nchunks = (int)((K + pb - 1) / pb);
+    pb = std::max(64L, (pb + 15) / 16 * 16);
+    w.per_block = pb;
+    w.nchunks = (int)((K + pb - 1) / pb);
+    w.partial_floats = (size_t)w.nchunks * per_chunk_floats;  // 4 wave slots per chunk
+    return w;
 }
 
 void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout) {
@@ -295,8 +311,14 @@ void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout) {
     *wout = W / dout[l];
 }
 
-static const long kBiasPerBlock = 1024;
 static const long kLossPerBlock = 16384;
+
+// Column-sum (bias gradient) split: at most 1024 fixed row ranges.
+void colsum_split(long npix, int* nblocks, long* per_block) {
+    const long nb = std::max(1L, std::min(1024L, (npix + 255) / 256));
+    *per_block = (npix + nb - 1) / nb;
+    *nblocks = (int)((npix + *per_block - 1) / *per_block);
+}
 
 // Backward workspace: [recompute h3 u3 u2] [gradients] [wgrad partials] [bias partials]
 BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed) {
@@ -319,14 +341,12 @@ BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed) {
     b.dz_h1 = cur; cur += align256(a.p1 * 32 * es);
     size_t wp = 0, bp = 0;
     for (int l = 0; l < 6; ++l) {
-        long pb;
-        int nch;
-        wgrad_split(l, n, H, W, &pb, &nch);
-        wp = std::max(wp, (size_t)nch * 4 * 9 * kLayers[l].cout * kLayers[l].cin * sizeof(float));
+        wp = std::max(wp, wgrad_plan(l, n, H, W).partial_floats * sizeof(float));
         int hin, win, hout, wout;
         layer_io(l, H, W, &hin, &win, &hout, &wout);
-        const long np = (long)n * hout * wout;
-        const long nb = (np + kBiasPerBlock - 1) / kBiasPerBlock;
+        int nb;
+        long per;
+        colsum_split((long)n * hout * wout, &nb, &per);
         bp = std::max(bp, (size_t)nb * kLayers[l].cout * sizeof(float));
     }
     b.wpart = cur; cur += align256(wp);

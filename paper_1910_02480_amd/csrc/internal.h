@@ -94,7 +94,13 @@ size_t align256(size_t v);
 GemmGeom gemm_geom(int l, bool backward, int prec);
 ActSizes act_sizes(int prec, int n, int H, int W);
 void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout);
-void wgrad_split(int l, int n, int H, int W, long* per_block, int* nchunks);
+struct WgradPlan {
+    int qc, pc, Hr, Wr, JB, PB, VEC, jtiles, ptiles, nchunks;
+    long per_block;
+    size_t partial_floats;
+};
+WgradPlan wgrad_plan(int l, int n, int H, int W);
+void colsum_split(long npix, int* nblocks, long* per_block);
 BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed);
 StepLayout step_layout(int prec, int n, int H, int W, int recompute);
 

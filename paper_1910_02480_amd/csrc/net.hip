@@ -46,105 +46,12 @@ int default_npw(int prec, int layer, bool backward) {
     return prec == P_FP8 ? std::max(1, npw / 2) : npw;
 }
 
-// ------------------------------------------------------------------ GEMM dispatch
-// Compile-time facts of one layer-GEMM instantiation: K step, packed row
-// length, LDS bytes for the weight pack and whether it is staged in LDS.
-template <int P, int MODE, int CIN, int COUTP>
-struct GemmCfg {
-    static constexpr int KS = (P == P_F32) ? 16 : (P == P_BF16 ? 32 : 128);
-    static constexpr int ES = (P == P_F32) ? 4 : (P == P_BF16 ? 2 : 1);
-    static constexpr int KSTRIDE = (((MODE == M_TCONV ? 4 : 9) * CIN) + KS - 1) / KS * KS;
-    static constexpr int LDS = COUTP * wlds_row_bytes(KSTRIDE, ES);
-    static constexpr bool WLDS = LDS <= 80 * 1024;
-};
-
-template <int P, int MODE, int CIN, int COUTP, int NPW, bool RAW, bool OF32>
-static drc_status launch_one(const LayerArgs& a, dim3 grid, hipStream_t s) {
-    typedef GemmCfg<P, MODE, CIN, COUTP> C;
-    auto kern = conv_layer_kernel<P, MODE, CIN, COUTP, NPW, RAW, OF32, C::WLDS>;
-    const int lds = C::WLDS ? C::LDS : 0;
-    if (lds > 64 * 1024) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
-                hipSuccess)
-                return drc_fail(DRC_ERR_HIP, "gemm: cannot raise the LDS limit to %d bytes", lds);
-            attr_set = true;
-        }
-    }
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, a);
-    return check_launch("gemm");
-}
-
-// Numbers the work items of every class and launches the persistent grid.
-template <int P, int MODE, int CIN, int COUTP, bool RAW, bool OF32>
-static drc_status launch_gemm(LayerArgs& a, int npw, int num_cu, hipStream_t s) {
-    typedef GemmCfg<P, MODE, CIN, COUTP> C;
-    if (a.kstride != C::KSTRIDE) return drc_fail(DRC_ERR_STATE, "gemm: weight pack stride mismatch");
-    long items = 0;
-    for (int c = 0; c < a.nclass; ++c) {
-        ClassGeom& G = a.cls[c];
-        const long npix = (long)G.nmaps * G.Hg * G.Wg;
-        if (G.tile_px <= 0) G.tile_px = 64 * npw;
-        G.item0 = items;
-        G.items = (npix + G.tile_px - 1) / G.tile_px;
-        items += G.items;
-    }
-    a.total_items = items;
-    if (items == 0) return DRC_OK;
-    const int nphase = MODE == M_TCONV ? 4 : 1;
-    const int per_cu = C::WLDS ? std::max(1, std::min(4, (160 * 1024) / C::LDS)) : 4;
-    const long want = ((long)num_cu * per_cu + nphase - 1) / nphase;
-    dim3 grid((unsigned)std::min(items, want), nphase);
-    constexpr int MT = COUTP / 16;
-    switch (npw) {
-        case 1:
-            if constexpr (MT * 1 <= 16) return launch_one<P, MODE, CIN, COUTP, 1, RAW, OF32>(a, grid, s);
-            break;
-        case 2:
-            if constexpr (MT * 2 <= 16) return launch_one<P, MODE, CIN, COUTP, 2, RAW, OF32>(a, grid, s);
-            break;
-        case 4:
-            if constexpr (MT * 4 <= 16) return launch_one<P, MODE, CIN, COUTP, 4, RAW, OF32>(a, grid, s);
-            break;
-        case 8:
-            if constexpr (MT * 8 <= 16) return launch_one<P, MODE, CIN, COUTP, 8, RAW, OF32>(a, grid, s);
-            break;
-    }
-    return drc_fail(DRC_ERR_UNSUPPORTED, "gemm: tile npw=%d not built", npw);
-}
-
+// Layer-GEMM launches, instantiated per precision in gemm_*.hip.
 template <int P>
-drc_status run_gemm(int layer, bool bwd, LayerArgs& a, int npw, int num_cu, hipStream_t s) {
-    if (!bwd) {
-        switch (layer) {
-            case 0: return launch_gemm<P, M_CONV, 8, 32, true, false>(a, npw, num_cu, s);
-            case 1: return launch_gemm<P, M_CONV, 32, 64, false, false>(a, npw, num_cu, s);
-            case 2: return launch_gemm<P, M_CONV, 64, 128, false, false>(a, npw, num_cu, s);
-            case 3: return launch_gemm<P, M_TCONV, 128, 64, false, false>(a, npw, num_cu, s);
-            case 4: return launch_gemm<P, M_TCONV, 128, 32, false, false>(a, npw, num_cu, s);
-            case 5: return launch_gemm<P, M_TCONV, 64, 16, false, true>(a, npw, num_cu, s);
-        }
-    } else {
-        if constexpr (P == P_FP8) {
-            return drc_fail(DRC_ERR_UNSUPPORTED, "backward: FP8 is inference only");
-        } else {
-            constexpr int D1C = (P == P_F32) ? 4 : 8;
-            switch (layer) {
-                case 5: return launch_gemm<P, M_CONV, D1C, 64, true, false>(a, npw, num_cu, s);
-                case 4: return launch_gemm<P, M_CONV, 32, 128, false, false>(a, npw, num_cu, s);
-                case 3: return launch_gemm<P, M_CONV, 64, 128, false, false>(a, npw, num_cu, s);
-                case 2: return launch_gemm<P, M_TCONV, 128, 64, false, false>(a, npw, num_cu, s);
-                case 1: return launch_gemm<P, M_TCONV, 64, 32, false, false>(a, npw, num_cu, s);
-                case 0: return launch_gemm<P, M_TCONV, 32, 16, false, true>(a, npw, num_cu, s);
-            }
-        }
-    }
-    return drc_fail(DRC_ERR_INVALID_ARG, "gemm: layer %d", layer);
-}
-template drc_status run_gemm<P_F32>(int, bool, LayerArgs&, int, int, hipStream_t);
-template drc_status run_gemm<P_BF16>(int, bool, LayerArgs&, int, int, hipStream_t);
-template drc_status run_gemm<P_FP8>(int, bool, LayerArgs&, int, int, hipStream_t);
+drc_status run_gemm(int layer, bool bwd, LayerArgs& a, int npw, int num_cu, hipStream_t s);
+extern template drc_status run_gemm<P_F32>(int, bool, LayerArgs&, int, int, hipStream_t);
+extern template drc_status run_gemm<P_BF16>(int, bool, LayerArgs&, int, int, hipStream_t);
+extern template drc_status run_gemm<P_FP8>(int, bool, LayerArgs&, int, int, hipStream_t);
 
 static Seg seg_none() {
     Seg s;
@@ -354,48 +261,78 @@ extern "C" drc_status drc_cae_forward(drc_cae* h, const float* d_x, float* d_y, 
 template <typename T>
 static drc_status bias_grad(const void* g, bool g_raw, int C, long npix, float* partial, float* out,
                             float scale, hipStream_t s) {
-    const long per = 1024;
-    const int nb = (int)((npix + per - 1) / per);
+    int nb;
+    long per;
+    colsum_split(npix, &nb, &per);
     int cp = 1;
     while (cp < C) cp <<= 1;
     if (g_raw)
-        hipLaunchKernelGGL(bias_partial_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)g, C, cp, C,
+        hipLaunchKernelGGL(colsum_partial_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)g, C, cp, C,
                            npix, per, partial);
     else
-        hipLaunchKernelGGL(bias_partial_kernel<T>, dim3(nb), dim3(256), 0, s, (const T*)g, C, cp, C, npix,
+        hipLaunchKernelGGL(colsum_partial_kernel<T>, dim3(nb), dim3(256), 0, s, (const T*)g, C, cp, C, npix,
                            per, partial);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3((C + 255) / 256), dim3(256), 0, s, (const float*)partial, nb,
-                       (long)C, scale, out);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(C), dim3(256), 0, s, (const float*)partial, nb, C, scale, out);
     return check_launch("bias_grad");
 }
 
+// Weight gradient of layer l. g: gradient at the layer output (pre-
+// activation; float32 when g_raw), s0/s1: the layer input (a concatenation
+// for D2 and D1; float32 x with a_raw_c channels for E1).
 template <typename T>
 static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_raw, Src s0, Src s1,
                               int a_raw_c, float* partial, float* out, float scale, hipStream_t s) {
+    const LayerDef& L = kLayers[l];
+    const WgradPlan wp = wgrad_plan(l, n, H, W);
+    int hin, win, hout, wout;
+    layer_io(l, H, W, &hin, &win, &hout, &wout);
     WgradArgs a;
     memset(&a, 0, sizeof a);
-    const LayerDef& L = kLayers[l];
-    layer_io(l, H, W, &a.Hin, &a.Win, &a.Hout, &a.Wout);
-    a.g = g;
-    a.gc = L.cout;
-    a.gld = L.cout;
-    a.g_raw = g_raw;
-    a.s0 = s0;
-    a.s1 = s1;
-    a.a_raw_c = a_raw_c;
-    a.mode = L.tconv ? M_TCONV : M_CONV;
+    if (!L.tconv) {  // plain = output gradient, gathered = layer input
+        a.p = g;
+        a.p_raw = g_raw;
+        a.pc = L.cout;
+        a.pc0 = L.cout;
+        a.pld = L.cout;
+        a.q = s0.p;
+        a.q_raw = a_raw_c > 0;
+        a.qc = L.cin;
+        a.qld = s0.ld;
+        a.Hq = hin;
+        a.Wq = win;
+    } else {         // plain = layer input (maybe a concatenation), gathered = output gradient
+        a.p = s0.p;
+        a.p2 = s1.p;
+        a.p_raw = 0;
+        a.pc = L.cin;
+        a.pc0 = s0.c;
+        a.pld = s0.ld;
+        a.p2ld = s1.ld;
+        a.q = g;
+        a.q_raw = g_raw;
+        a.qc = L.cout;
+        a.qld = L.cout;
+        a.Hq = hout;
+        a.Wq = wout;
+    }
     a.nmaps = n;
-    a.cout = L.cout;
-    a.cin = L.cin;
-    int nch;
-    wgrad_split(l, n, H, W, &a.per_block, &nch);
-    a.co_tiles = (L.cout + 63) / 64;
-    a.ci_tiles = (L.cin + 63) / 64;
+    a.Hr = wp.Hr;
+    a.Wr = wp.Wr;
+    a.per_block = wp.per_block;
+    a.jtiles = wp.jtiles;
     a.partial = partial;
-    hipLaunchKernelGGL(wgrad_kernel<T>, dim3(nch, 9, a.co_tiles * a.ci_tiles), dim3(256), 0, s, a);
-    const long count = 9L * L.cout * L.cin;
-    hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)std::min(1024L, (count + 255) / 256)), dim3(256), 0, s,
-                       (const float*)partial, nch * 4, L.cout, L.cin, scale, out);
+    dim3 grid(wp.nchunks, wp.jtiles * wp.ptiles);
+    if (wp.VEC == 4)
+        hipLaunchKernelGGL((wgrad_kernel<T, 4, 4, 4>), grid, dim3(256), 0, s, a);
+    else if (wp.JB == 4 && wp.PB == 4)
+        hipLaunchKernelGGL((wgrad_kernel<T, 4, 4, 1>), grid, dim3(256), 0, s, a);
+    else if (wp.JB == 4)
+        hipLaunchKernelGGL((wgrad_kernel<T, 4, 2, 1>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((wgrad_kernel<T, 2, 4, 1>), grid, dim3(256), 0, s, a);
+    const long count = 9L * wp.qc * wp.pc;
+    hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)std::min(2048L, (count + 255) / 256)), dim3(256), 0, s,
+                       (const float*)partial, 4 * wp.nchunks, wp.qc, wp.pc, (int)L.tconv, scale, out);
     return check_launch("weight_grad");
 }
 
