@@ -197,7 +197,7 @@ def main():
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)  # 256 MiB
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 2.0, out=dst)  # one elementwise kernel: reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         del src, dst
     # ---------------- headline: BF16 forward, profiled live

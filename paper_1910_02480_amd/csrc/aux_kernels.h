@@ -14,41 +14,59 @@ namespace drc {
 struct PackArgs {
     const float* w;
     int cout, cin;      // layer shape
-    int gemm_mode;      // M_CONV or M_TCONV: the GEMM this pack feeds
+    int gemm_mode;      // M_CONV, M_TCONV_PAIRS or M_TCONV_MERGED: the GEMM this pack feeds
     int transpose;
-    int cin_eff;        // K elements per tap
-    int rows_pad;       // GEMM rows, padded to 16
+    int cin_eff;        // K elements per tap / neighbour
+    int rows_pad;       // GEMM rows per block, padded to 16
     int kstride;        // K elements per row
-    int nphase;         // 1 (conv) or 4 (tconv)
+    int nblk;           // blocks of rows: 1, or 9 (phase, neighbour) pairs
     int prec;
     const float* scale; // FP8: device pointer to the weight scale, else null
     void* dst;
 };
 
+// Weight pack element e of the layout [blk][row][k]:
+//  M_CONV          k = tap * cin_eff + c, tap = 3 kh + kw;
+//  M_TCONV_PAIRS   block = (phase, neighbour) pair, k = c;
+//  M_TCONV_MERGED  row = phase * rows + r, k = neighbour * cin_eff + c,
+//                  zero where the phase does not use the neighbour.
+// Forward pack: row = co, c = ci. Transposed pack (backward data pass):
+// row = ci, c = co.
 static __global__ void pack_weights_kernel(PackArgs a) {
-    const long total = (long)a.nphase * a.rows_pad * a.kstride;
+    const long total = (long)a.nblk * a.rows_pad * a.kstride;
+    const int rows = a.transpose ? a.cin : a.cout;
+    const int chans = a.transpose ? a.cout : a.cin;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
         const int k = (int)(e % a.kstride);
-        const int row = (int)((e / a.kstride) % a.rows_pad);
-        const int phase = (int)(e / ((long)a.kstride * a.rows_pad));
-        const int t = k / a.cin_eff, c = k % a.cin_eff;
-        const int rows = a.transpose ? a.cin : a.cout;
-        const int chans = a.transpose ? a.cout : a.cin;
+        int row = (int)((e / a.kstride) % a.rows_pad);
+        const int blk = (int)(e / ((long)a.kstride * a.rows_pad));
         float v = 0.0f;
-        int kh, kw, ntaps;
+        int kh = 0, kw = 0, c = 0;
+        bool ok = false;
         if (a.gemm_mode == M_CONV) {
-            ntaps = 9;
+            const int t = k / a.cin_eff;
+            c = k % a.cin_eff;
             kh = t / 3;
             kw = t % 3;
-        } else {
-            const int py = phase >> 1, px = phase & 1;
-            ntaps = (py ? 2 : 1) * (px ? 2 : 1);
-            const int tr = px ? (t >> 1) : t, tc = px ? (t & 1) : 0;
-            kh = py ? (tr == 0 ? 0 : 2) : 1;
-            kw = px ? (tc == 0 ? 0 : 2) : 1;
+            ok = t < 9 && row < rows;
+        } else if (a.gemm_mode == M_TCONV_PAIRS) {
+            const int ph = pair_phase(blk), nb = pair_nb(blk);
+            kh = tap_kh(ph, nb);
+            kw = tap_kw(ph, nb);
+            c = k;
+            ok = row < rows;
+        } else {  // merged rows: (phase, r)
+            const int ph = row / rows, nb = k / a.cin_eff;
+            c = k % a.cin_eff;
+            ok = ph < 4 && nb < 4 && phase_uses(ph, nb);
+            if (ok) {
+                kh = tap_kh(ph, nb);
+                kw = tap_kw(ph, nb);
+                row -= ph * rows;
+            }
         }
-        if (row < rows && c < chans && t < ntaps) {
+        if (ok && c < chans) {
             const int co = a.transpose ? c : row;
             const int ci = a.transpose ? row : c;
             v = a.w[((co * 3 + kh) * 3 + kw) * a.cin + ci];

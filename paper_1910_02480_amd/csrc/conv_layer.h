@@ -32,7 +32,26 @@
 
 namespace drc {
 
-enum Mode : int { M_CONV = 0, M_TCONV = 1 };
+enum Mode : int {
+    M_CONV = 0,          // stride-2 convolution, taps in 3x3 order
+    M_TCONV = 1,         // transposed convolution (one output phase per GEMM; packs only)
+    M_TCONV_PAIRS = 2,   // transposed convolution, all phases: 9 (phase, neighbour) weight blocks
+    M_TCONV_MERGED = 3   // transposed convolution, all phases: rows = (phase, channel), K = (neighbour, channel)
+};
+
+// The 9 (output phase, input neighbour) pairs of a stride-2 transposed 3x3
+// convolution. Phase p = 2 py + px is output (2a+py, 2b+px); neighbour
+// nb = 2 di + dj is input (a+di, b+dj). Row tap kh = 1 for py = 0, and for
+// py = 1 kh = 0 with di = 1 or kh = 2 with di = 0; columns likewise.
+__host__ __device__ constexpr int pair_phase(int q) { return q == 0 ? 0 : (q <= 2 ? 1 : (q <= 4 ? 2 : 3)); }
+__host__ __device__ constexpr int pair_nb(int q) {
+    return q == 0 ? 0 : (q == 1 ? 0 : (q == 2 ? 1 : (q == 3 ? 0 : (q == 4 ? 2 : q - 5))));
+}
+__host__ __device__ constexpr bool phase_uses(int ph, int nb) {
+    return ((ph >> 1) || !(nb >> 1)) && ((ph & 1) || !(nb & 1));
+}
+__host__ __device__ constexpr int tap_kh(int ph, int nb) { return (ph >> 1) ? ((nb >> 1) ? 0 : 2) : 1; }
+__host__ __device__ constexpr int tap_kw(int ph, int nb) { return (ph & 1) ? ((nb & 1) ? 0 : 2) : 1; }
 
 // One source of input channels; a channel concatenation is two sources.
 struct Src {
@@ -208,6 +227,79 @@ __device__ __forceinline__ void store_seg(const Seg& s, long doff, long opix, in
 // 16 bytes so that the 16 rows read by one MFMA fragment hit distinct banks).
 __host__ __device__ constexpr int wlds_row_bytes(int kstride, int esize) { return kstride * esize + 16; }
 
+// Input neighbour nb (= 2 di + dj) of a transposed-convolution GEMM pixel
+// (a, b): the lane's VW channels [c, c+VW) of input pixel (a+di, b+dj).
+template <int P, int C0>
+__device__ __forceinline__ typename Traits<P>::V gather_nb(const ClassGeom& G, const PixState& ps, int nb, int c,
+                                                           long rowd0, long rowd1) {
+    typedef typename Traits<P>::T T;
+    typedef typename Traits<P>::V V;
+    const int di = nb >> 1, dj = nb & 1;
+    if (!ps.v || (di && !ps.down) || (dj && !ps.right)) return vzero<V>();
+    const T* src = (c < C0) ? (const T*)G.s0.p + ps.off0 + di * rowd0 + dj * G.s0.ld + c
+                            : (const T*)G.s1.p + ps.off1 + di * rowd1 + dj * G.s1.ld + (c - C0);
+    return *(const V*)src;
+}
+
+// Per-pixel setup shared by the kernels: map, base input position, border
+// flags, input offsets and the output pixel of the GEMM pixel.
+template <int MODE, bool RAW>
+__device__ __forceinline__ void pix_setup(const ClassGeom& G, long pix, long t0, long t1, PixState& ps) {
+    ps.v = pix < t1;
+    if (!ps.v) pix = t0;
+    const int hw = G.Hg * G.Wg;
+    const int n = (int)(pix / hw);
+    const int rem = (int)(pix - (long)n * hw);
+    const int P_ = rem / G.Wg, Q_ = rem - P_ * G.Wg;
+    const int bi = (MODE == M_CONV) ? 2 * P_ : P_;
+    const int bj = (MODE == M_CONV) ? 2 * Q_ : Q_;
+    ps.n = n;
+    ps.up = bi > 0;
+    ps.left = bj > 0;
+    ps.down = bi + 1 < G.Hin;
+    ps.right = bj + 1 < G.Win;
+    const long ploc = (long)bi * G.Win + bj;
+    if constexpr (RAW) {
+        const long base = G.in_off ? G.in_off[n] : (long)n * G.Hin * G.Win * G.s0.ld;
+        ps.off0 = base + ploc * G.s0.ld;
+        ps.off1 = 0;
+    } else {
+        const long pl = (long)n * G.Hin * G.Win + ploc;
+        ps.off0 = pl * G.s0.ld;
+        ps.off1 = pl * G.s1.ld;
+    }
+    // conv: output (P_, Q_); transposed conv: phase-0 output (2a, 2b)
+    const int oi = (MODE == M_CONV) ? P_ : 2 * P_;
+    const int oj = (MODE == M_CONV) ? Q_ : 2 * Q_;
+    ps.oloc = (long)oi * G.Wout + oj;
+    ps.opix = (long)n * G.Hout * G.Wout + ps.oloc;
+}
+
+// Finds the resolution class of a work item and its pixel range.
+__device__ __forceinline__ const ClassGeom& item_class(const LayerArgs& a, long item, long& t0, long& t1) {
+    int c = 0;
+#pragma unroll
+    for (int k = 1; k < kMaxClasses; ++k)
+        if (k < a.nclass && item >= a.cls[k].item0) c = k;
+    const ClassGeom& G = a.cls[c];
+    const long npix = (long)G.nmaps * G.Hg * G.Wg;
+    t0 = (item - G.item0) * G.tile_px;
+    t1 = min(npix, t0 + G.tile_px);
+    return G;
+}
+
+// Stages rows x klen of a weight pack into LDS (16 bytes per thread step).
+template <int ES>
+__device__ __forceinline__ void stage_weights(char* smem, const void* w, int rows, int kstride, int klen, int rowb) {
+    const int chunks_per_row = klen * ES / 16;
+    for (int e = threadIdx.x; e < rows * chunks_per_row; e += 256) {
+        const int row = e / chunks_per_row, ch = e - row * chunks_per_row;
+        *(uint4*)(smem + row * rowb + ch * 16) =
+            *(const uint4*)((const char*)w + (size_t)row * kstride * ES + ch * 16);
+    }
+    __syncthreads();
+}
+
 // Gathers the lane's VW K elements [kk, kk+VW) of one GEMM pixel.
 // C0: channels of source 0 (the rest come from source 1).
 template <int P, int MODE, int PHASE, int CIN, int C0, bool RAW>
@@ -246,7 +338,7 @@ __device__ __forceinline__ typename Traits<P>::V gather(const ClassGeom& G, int 
             const float* src = (const float*)G.s0.p + ps.off0 + di * rowd0 + dj * G.s0.ld;
 #pragma unroll
             for (int e = 0; e < SUB; ++e)
-                if (c + e < raw_c) tmp[s * SUB + e] = TR::from_f32(src[c + e], raw_qscale);
+                if (c + e < raw_c) tmp[s * SUB + e] = to_store<P>(src[c + e], raw_qscale);
         } else {
             const T* src = (c < C0) ? (const T*)G.s0.p + ps.off0 + di * rowd0 + dj * G.s0.ld + c
                                     : (const T*)G.s1.p + ps.off1 + di * rowd1 + dj * G.s1.ld + (c - C0);
@@ -286,11 +378,8 @@ __device__ __forceinline__ void conv_layer_phase(const LayerArgs& a, const char*
         for (int e = 0; e < 4; ++e) bias[m][e] = 0.0f;
 
     for (long item = blockIdx.x; item < a.total_items; item += gridDim.x) {
-        int c = 0;
-#pragma unroll
-        for (int k = 1; k < kMaxClasses; ++k)
-            if (k < a.nclass && item >= a.cls[k].item0) c = k;
-        const ClassGeom& G = a.cls[c];
+        long t0, t1;
+        const ClassGeom& G = item_class(a, item, t0, t1);
         if (a.bias) {
             const int nb = G.seg0.c + G.seg1.c;
 #pragma unroll
@@ -301,44 +390,12 @@ __device__ __forceinline__ void conv_layer_phase(const LayerArgs& a, const char*
                     bias[m][e] = ch < nb ? a.bias[ch] : 0.0f;
                 }
         }
-        const int hw = G.Hg * G.Wg;
-        const long npix = (long)G.nmaps * hw;
-        const long t0 = (item - G.item0) * G.tile_px;
-        const long t1 = min(npix, t0 + G.tile_px);
         const long rowd0 = (long)G.Win * G.s0.ld, rowd1 = (long)G.Win * G.s1.ld;
 
         for (long pix0 = t0 + (long)wave * (NPW * 16); pix0 < t1; pix0 += 4L * NPW * 16) {
             PixState ps[NPW];
 #pragma unroll
-            for (int p = 0; p < NPW; ++p) {
-                long pix = pix0 + p * 16 + r16;
-                ps[p].v = pix < t1;
-                if (!ps[p].v) pix = t0;
-                const int n = (int)(pix / hw);
-                const int rem = (int)(pix - (long)n * hw);
-                const int P_ = rem / G.Wg, Q_ = rem - P_ * G.Wg;
-                const int bi = (MODE == M_CONV) ? 2 * P_ : P_;
-                const int bj = (MODE == M_CONV) ? 2 * Q_ : Q_;
-                ps[p].n = n;
-                ps[p].up = bi > 0;
-                ps[p].left = bj > 0;
-                ps[p].down = bi + 1 < G.Hin;
-                ps[p].right = bj + 1 < G.Win;
-                const long ploc = (long)bi * G.Win + bj;
-                if constexpr (RAW) {
-                    const long base = G.in_off ? G.in_off[n] : (long)n * G.Hin * G.Win * G.s0.ld;
-                    ps[p].off0 = base + ploc * G.s0.ld;
-                    ps[p].off1 = 0;
-                } else {
-                    const long pl = (long)n * G.Hin * G.Win + ploc;
-                    ps[p].off0 = pl * G.s0.ld;
-                    ps[p].off1 = pl * G.s1.ld;
-                }
-                const int oi = (MODE == M_CONV) ? P_ : 2 * P_ + (PHASE >> 1);
-                const int oj = (MODE == M_CONV) ? Q_ : 2 * Q_ + (PHASE & 1);
-                ps[p].oloc = (long)oi * G.Wout + oj;
-                ps[p].opix = (long)n * G.Hout * G.Wout + ps[p].oloc;
-            }
+            for (int p = 0; p < NPW; ++p) pix_setup<MODE, RAW>(G, pix0 + p * 16 + r16, t0, t1, ps[p]);
 
             f4 acc[MT][NPW];
 #pragma unroll
@@ -396,37 +453,215 @@ __device__ __forceinline__ void conv_layer_phase(const LayerArgs& a, const char*
     }
 }
 
-// Persistent layer kernel. For transposed convolutions grid.y selects the
-// output phase, each compiled with its own tap table.
+// Persistent stride-2 convolution kernel.
 template <int P, int MODE, int CIN, int C0, int COUT_PAD, int NPW, bool RAW, bool OUT_F32, bool WLDS>
 __global__ __launch_bounds__(256) void conv_layer_kernel(const LayerArgs a) {
+    static_assert(MODE == M_CONV, "transposed convolutions use tconv_pairs_kernel / tconv_merged_kernel");
     typedef typename Traits<P>::T T;
     constexpr int ES = (int)sizeof(T);
     constexpr int KS = Traits<P>::KS;
     extern __shared__ __align__(16) char smem[];
-    const int phase = (MODE == M_TCONV) ? (int)blockIdx.y : 0;
-    const int ntaps = MODE == M_CONV ? 9 : ((phase >> 1) ? 2 : 1) * ((phase & 1) ? 2 : 1);
-    const int klen = (ntaps * CIN + KS - 1) / KS * KS;
     const int rowb = wlds_row_bytes(a.kstride, ES);
-    if constexpr (WLDS) {
-        // stage rows [0, COUT_PAD) x [0, klen) of this phase's pack, 16 bytes per thread step
-        const T* wglob = (const T*)a.wpack + (size_t)phase * COUT_PAD * a.kstride;
-        const int chunks_per_row = klen * ES / 16;
-        for (int e = threadIdx.x; e < COUT_PAD * chunks_per_row; e += 256) {
-            const int row = e / chunks_per_row, ch = e - row * chunks_per_row;
-            *(uint4*)(smem + row * rowb + ch * 16) =
-                *(const uint4*)((const char*)(wglob + (size_t)row * a.kstride) + ch * 16);
+    if constexpr (WLDS) stage_weights<ES>(smem, a.wpack, COUT_PAD, a.kstride, (9 * CIN + KS - 1) / KS * KS, rowb);
+    conv_layer_phase<P, MODE, 0, CIN, C0, COUT_PAD, NPW, RAW, OUT_F32, WLDS>(a, smem, rowb);
+}
+
+// Persistent stride-2 transposed convolution over all four output phases.
+// Each GEMM pixel (a, b) gathers its 4 input neighbours once per K step and
+// feeds them to the 9 (phase, neighbour) weight blocks; weight pack
+// [pair q][COUT_PAD][kstride].
+template <int P, int CIN, int C0, int COUT_PAD, int NPW, bool OUT_F32, bool WLDS>
+__global__ __launch_bounds__(256) void tconv_pairs_kernel(const LayerArgs a) {
+    typedef Traits<P> TR;
+    typedef typename TR::T T;
+    typedef typename TR::V V;
+    constexpr int KS = TR::KS, VW = TR::VW;
+    constexpr int ES = (int)sizeof(T);
+    constexpr int MT = COUT_PAD / 16;
+    static_assert(CIN % KS == 0, "one neighbour per K step");
+    constexpr int KSN = CIN / KS;
+    extern __shared__ __align__(16) char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int rowb = wlds_row_bytes(a.kstride, ES);
+    if constexpr (WLDS) stage_weights<ES>(smem, a.wpack, 9 * COUT_PAD, a.kstride, CIN, rowb);
+    const T* wglob = (const T*)a.wpack;
+
+    float bias[MT][4];
+    for (long item = blockIdx.x; item < a.total_items; item += gridDim.x) {
+        long t0, t1;
+        const ClassGeom& G = item_class(a, item, t0, t1);
+        const int nb_out = G.seg0.c + G.seg1.c;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ch = m * 16 + g * 4 + e;
+                bias[m][e] = (a.bias && ch < nb_out) ? a.bias[ch] : 0.0f;
+            }
+        const long rowd0 = (long)G.Win * G.s0.ld, rowd1 = (long)G.Win * G.s1.ld;
+        for (long pix0 = t0 + (long)wave * (NPW * 16); pix0 < t1; pix0 += 4L * NPW * 16) {
+            PixState ps[NPW];
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) pix_setup<M_TCONV, false>(G, pix0 + p * 16 + r16, t0, t1, ps[p]);
+            f4 acc[4][MT][NPW];
+#pragma unroll
+            for (int ph = 0; ph < 4; ++ph)
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int p = 0; p < NPW; ++p) acc[ph][m][p] = f4{0.f, 0.f, 0.f, 0.f};
+            V bv[2][4][NPW];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+                for (int p = 0; p < NPW; ++p) bv[0][nb][p] = gather_nb<P, C0>(G, ps[p], nb, g * VW, rowd0, rowd1);
+#pragma unroll
+            for (int ks = 0; ks < KSN; ++ks) {
+                const int cur = ks & 1;
+                if (ks + 1 < KSN) {
+#pragma unroll
+                    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+                        for (int p = 0; p < NPW; ++p)
+                            bv[cur ^ 1][nb][p] = gather_nb<P, C0>(G, ps[p], nb, (ks + 1) * KS + g * VW, rowd0, rowd1);
+                }
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    const int ph = pair_phase(q), nb = pair_nb(q);
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) {
+                        const int row = (q * COUT_PAD + m * 16 + r16);
+                        V av;
+                        if constexpr (WLDS)
+                            av = *(const V*)(smem + row * rowb + (ks * KS + g * VW) * ES);
+                        else
+                            av = *(const V*)(wglob + (size_t)row * a.kstride + ks * KS + g * VW);
+#pragma unroll
+                        for (int p = 0; p < NPW; ++p) TR::mma(acc[ph][m][p], av, bv[cur][nb][p]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int ph = 0; ph < 4; ++ph)
+#pragma unroll
+                for (int p = 0; p < NPW; ++p) {
+                    if (!ps[p].v) continue;
+                    const long dpix = (long)(ph >> 1) * G.Wout + (ph & 1);
+                    const long opix = ps[p].opix + dpix;
+                    long doff0 = opix * G.seg0.ld;
+                    if constexpr (OUT_F32)
+                        if (G.out_off) doff0 = G.out_off[ps[p].n] + (ps[p].oloc + dpix) * G.seg0.ld;
+                    const long doff1 = opix * G.seg1.ld;
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) {
+                        const int ch = m * 16 + g * 4;
+                        float val[4] = {acc[ph][m][p].x * a.acc_scale + bias[m][0], acc[ph][m][p].y * a.acc_scale + bias[m][1],
+                                        acc[ph][m][p].z * a.acc_scale + bias[m][2], acc[ph][m][p].w * a.acc_scale + bias[m][3]};
+                        if (ch < G.seg0.c)
+                            store_seg<P, OUT_F32>(G.seg0, doff0, opix, ch, val);
+                        else if (ch - G.seg0.c < G.seg1.c)
+                            store_seg<P, OUT_F32>(G.seg1, doff1, opix, ch - G.seg0.c, val);
+                    }
+                }
         }
-        __syncthreads();
     }
-    if constexpr (MODE == M_CONV) {
-        conv_layer_phase<P, MODE, 0, CIN, C0, COUT_PAD, NPW, RAW, OUT_F32, WLDS>(a, smem, rowb);
-    } else {
-        switch (phase) {
-            case 0: conv_layer_phase<P, MODE, 0, CIN, C0, COUT_PAD, NPW, RAW, OUT_F32, WLDS>(a, smem, rowb); break;
-            case 1: conv_layer_phase<P, MODE, 1, CIN, C0, COUT_PAD, NPW, RAW, OUT_F32, WLDS>(a, smem, rowb); break;
-            case 2: conv_layer_phase<P, MODE, 2, CIN, C0, COUT_PAD, NPW, RAW, OUT_F32, WLDS>(a, smem, rowb); break;
-            default: conv_layer_phase<P, MODE, 3, CIN, C0, COUT_PAD, NPW, RAW, OUT_F32, WLDS>(a, smem, rowb); break;
+}
+
+// Transposed convolution with few output channels (Cout < 16): the four
+// phases share one block of rows r = phase * COUT + co, and K runs over
+// (neighbour, channel): pack [R][kstride], zero where a phase does not use a
+// neighbour. One gather per neighbour feeds all phases.
+template <int P, int CIN, int C0, int COUT, int R, int NPW, bool OUT_F32, bool WLDS>
+__global__ __launch_bounds__(256) void tconv_merged_kernel(const LayerArgs a) {
+    typedef Traits<P> TR;
+    typedef typename TR::T T;
+    typedef typename TR::V V;
+    constexpr int KS = TR::KS, VW = TR::VW;
+    constexpr int ES = (int)sizeof(T);
+    constexpr int MT = R / 16;
+    constexpr int KSTEPS = (4 * CIN + KS - 1) / KS;
+    static_assert(CIN % VW == 0, "a lane's K elements stay inside one neighbour");
+    extern __shared__ __align__(16) char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int rowb = wlds_row_bytes(a.kstride, ES);
+    if constexpr (WLDS) stage_weights<ES>(smem, a.wpack, R, a.kstride, KSTEPS * KS, rowb);
+    const T* wglob = (const T*)a.wpack;
+
+    float bias[MT][4];
+    int rph[MT][4], rco[MT][4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = m * 16 + g * 4 + e;
+            rph[m][e] = r / COUT;
+            rco[m][e] = r - (r / COUT) * COUT;
+            bias[m][e] = (a.bias && r < 4 * COUT) ? a.bias[rco[m][e]] : 0.0f;
+        }
+    for (long item = blockIdx.x; item < a.total_items; item += gridDim.x) {
+        long t0, t1;
+        const ClassGeom& G = item_class(a, item, t0, t1);
+        const long rowd0 = (long)G.Win * G.s0.ld, rowd1 = (long)G.Win * G.s1.ld;
+        for (long pix0 = t0 + (long)wave * (NPW * 16); pix0 < t1; pix0 += 4L * NPW * 16) {
+            PixState ps[NPW];
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) pix_setup<M_TCONV, false>(G, pix0 + p * 16 + r16, t0, t1, ps[p]);
+            f4 acc[MT][NPW];
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int p = 0; p < NPW; ++p) acc[m][p] = f4{0.f, 0.f, 0.f, 0.f};
+            V bv[2][NPW];
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) {
+                const int k = g * VW;
+                bv[0][p] = k < 4 * CIN ? gather_nb<P, C0>(G, ps[p], k / CIN, k % CIN, rowd0, rowd1) : vzero<V>();
+            }
+#pragma unroll
+            for (int ks = 0; ks < KSTEPS; ++ks) {
+                const int cur = ks & 1;
+                if (ks + 1 < KSTEPS) {
+                    const int k = (ks + 1) * KS + g * VW;
+#pragma unroll
+                    for (int p = 0; p < NPW; ++p)
+                        bv[cur ^ 1][p] = k < 4 * CIN ? gather_nb<P, C0>(G, ps[p], k / CIN, k % CIN, rowd0, rowd1)
+                                                     : vzero<V>();
+                }
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    V av;
+                    if constexpr (WLDS)
+                        av = *(const V*)(smem + (m * 16 + r16) * rowb + (ks * KS + g * VW) * ES);
+                    else
+                        av = *(const V*)(wglob + (size_t)(m * 16 + r16) * a.kstride + ks * KS + g * VW);
+#pragma unroll
+                    for (int p = 0; p < NPW; ++p) TR::mma(acc[m][p], av, bv[cur][p]);
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) {
+                if (!ps[p].v) continue;
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (m * 16 + g * 4 + e >= 4 * COUT) continue;
+                        const int ph = rph[m][e], co = rco[m][e];
+                        const long dpix = (long)(ph >> 1) * G.Wout + (ph & 1);
+                        const long opix = ps[p].opix + dpix;
+                        long doff = opix * G.seg0.ld;
+                        if constexpr (OUT_F32)
+                            if (G.out_off) doff = G.out_off[ps[p].n] + (ps[p].oloc + dpix) * G.seg0.ld;
+                        float v = acc[m][p][e] * a.acc_scale + bias[m][e];
+                        if (G.seg0.relu) v = (v < 0.0f) ? 0.0f : v;
+                        if constexpr (OUT_F32)
+                            ((float*)G.seg0.dst)[doff + co] = v;
+                        else
+                            ((T*)G.seg0.dst)[doff + co] = to_store<P>(v, G.seg0.qscale);
+                    }
+            }
         }
     }
 }

@@ -67,22 +67,41 @@ int prec_esize(int prec) { return prec == P_F32 ? 4 : (prec == P_BF16 ? 2 : 1); 
 static int rup(int v, int m) { return (v + m - 1) / m * m; }
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Forward / backward-data GEMM geometry of layer l.
+// Forward / backward-data GEMM geometry of layer l. Transposed
+// convolutions run all four output phases in one GEMM: with per-pair weight
+// blocks when the output has 16 or more channels, else with the phases
+// merged into one block of rows.
 GemmGeom gemm_geom(int l, bool backward, int prec) {
     const LayerDef& L = kLayers[l];
     GemmGeom g;
+    bool tconv;
     if (!backward) {
-        g.mode = L.tconv ? M_TCONV : M_CONV;
+        tconv = L.tconv;
         g.cin_eff = (l == 0) ? 8 : L.cin;
         g.rows = L.cout;
     } else {
-        g.mode = L.tconv ? M_CONV : M_TCONV;
+        tconv = !L.tconv;
         g.cin_eff = (l == 5) ? (prec == P_F32 ? 4 : 8) : L.cout;
         g.rows = L.cin;
     }
-    g.rows_pad = rup(g.rows, 16);
-    g.nphase = g.mode == M_TCONV ? 4 : 1;
-    g.kstride = rup((g.mode == M_TCONV ? 4 : 9) * g.cin_eff, prec_ks(prec));
+    const int ks = prec_ks(prec);
+    if (!tconv) {
+        g.mode = M_CONV;
+        g.rows_pad = rup(g.rows, 16);
+        g.nblk = 1;
+        g.kstride = rup(9 * g.cin_eff, ks);
+    } else if (g.rows >= 16) {
+        g.mode = M_TCONV_PAIRS;
+        g.rows_pad = rup(g.rows, 16);
+        g.nblk = 9;
+        g.kstride = rup(g.cin_eff, ks);
+    } else {
+        g.mode = M_TCONV_MERGED;
+        g.rows_pad = rup(4 * g.rows, 16);
+        g.nblk = 1;
+        g.kstride = rup(4 * g.cin_eff, ks);
+    }
+    g.nphase = g.nblk;
     return g;
 }
 
@@ -128,16 +147,16 @@ extern "C" drc_status drc_cae_create(const drc_cae_desc* desc, drc_cae** out) {
     bool ok = true;
     for (int l = 0; l < 6 && ok; ++l) {
         GemmGeom gf = gemm_geom(l, false, h->prec);
-        h->wf_bytes[l] = (size_t)gf.nphase * gf.rows_pad * gf.kstride * prec_esize(h->prec);
+        h->wf_bytes[l] = (size_t)gf.nblk * gf.rows_pad * gf.kstride * prec_esize(h->prec);
         ok = alloc(&h->wf[l], h->wf_bytes[l]);
         if (ok && h->prec != P_FP8) {
             GemmGeom gb = gemm_geom(l, true, h->prec);
-            h->wb_bytes[l] = (size_t)gb.nphase * gb.rows_pad * gb.kstride * prec_esize(h->prec);
+            h->wb_bytes[l] = (size_t)gb.nblk * gb.rows_pad * gb.kstride * prec_esize(h->prec);
             ok = alloc(&h->wb[l], h->wb_bytes[l]);
         }
         if (ok && h->prec == P_FP8) {  // float32 packs for the calibration forward
             GemmGeom gc = gemm_geom(l, false, P_F32);
-            ok = alloc(&h->wcal[l], (size_t)gc.nphase * gc.rows_pad * gc.kstride * 4);
+            ok = alloc(&h->wcal[l], (size_t)gc.nblk * gc.rows_pad * gc.kstride * 4);
         }
     }
     ok = ok && alloc((void**)&h->bias, 512 * sizeof(float));
@@ -439,11 +458,11 @@ static drc_status pack_all(drc_cae* h, const float* d_params, hipStream_t s) {
             a.cin_eff = g.cin_eff;
             a.rows_pad = g.rows_pad;
             a.kstride = g.kstride;
-            a.nphase = g.nphase;
+            a.nblk = g.nblk;
             a.prec = prec;
             a.scale = prec == P_FP8 ? h->scales + l : nullptr;
             a.dst = dst;
-            const long total = (long)g.nphase * g.rows_pad * g.kstride;
+            const long total = (long)g.nblk * g.rows_pad * g.kstride;
             const int blocks = (int)std::min(1024L, (total + 255) / 256);
             hipLaunchKernelGGL(pack_weights_kernel, dim3(blocks), dim3(256), 0, s, a);
         }

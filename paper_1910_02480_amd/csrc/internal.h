@@ -18,11 +18,12 @@ extern const LayerDef kLayers[6];
 
 // Geometry of one layer GEMM (forward or backward-data).
 struct GemmGeom {
-    int mode;      // drc::M_CONV / drc::M_TCONV
-    int cin_eff;   // K elements per tap
-    int rows;      // GEMM rows (output channels)
-    int rows_pad;  // rows padded to 16
-    int nphase;    // 1 or 4
+    int mode;      // drc::M_CONV / M_TCONV_PAIRS / M_TCONV_MERGED
+    int cin_eff;   // K elements per tap or neighbour
+    int rows;      // output channels of the GEMM
+    int rows_pad;  // packed rows per block (merged: 4 * rows), padded to 16
+    int nblk;      // weight blocks: 1, or 9 (phase, neighbour) pairs
+    int nphase;    // same as nblk (kept for the pack launch)
     int kstride;   // K elements per packed row (padded to the MFMA K step)
 };
 

@@ -28,20 +28,23 @@ using namespace drc;
     } while (0)
 
 // ------------------------------------------------------------------ tile shapes
-static int rows_pad_of(int layer, bool backward) {
-    const int rows = backward ? kLayers[layer].cin : kLayers[layer].cout;
-    return (rows + 15) / 16 * 16;
+// MFMA accumulator blocks (16 rows) a wave holds per 16-pixel block.
+static int acc_blocks(int prec, int layer, bool backward) {
+    const GemmGeom g = gemm_geom(layer, backward, prec);
+    if (g.mode == M_TCONV_PAIRS) return 4 * g.rows_pad / 16;
+    return g.rows_pad / 16;
 }
 
 bool npw_supported(int prec, int layer, bool backward, int npw) {
     if (npw != 1 && npw != 2 && npw != 4 && npw != 8) return false;
     if (backward && prec == P_FP8) return false;
-    return (rows_pad_of(layer, backward) / 16) * npw <= 16;
+    return acc_blocks(prec, layer, backward) * npw <= 16;
 }
 
 int default_npw(int prec, int layer, bool backward) {
-    const int mt = rows_pad_of(layer, backward) / 16;
-    const int npw = mt >= 8 ? 2 : (mt >= 4 ? 4 : (mt >= 2 ? 4 : 8));
+    const int mt = acc_blocks(prec, layer, backward);
+    int npw = mt >= 8 ? 2 : 4;
+    if (mt * npw > 16) npw = std::max(1, 16 / mt);
     // FP8 operands are 32 bytes per lane: halve the tile to stay out of scratch
     return prec == P_FP8 ? std::max(1, npw / 2) : npw;
 }
