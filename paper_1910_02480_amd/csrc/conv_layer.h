@@ -355,19 +355,24 @@ __device__ __forceinline__ typename Traits<P>::V gather(const ClassGeom& G, int 
 }
 
 // One phase's worth of the persistent layer kernel (PHASE = 0 for conv).
-template <int P, int MODE, int PHASE, int CIN, int C0, int COUT_PAD, int NPW, bool RAW, bool OUT_F32, bool WLDS>
+template <int P, int MODE, int PHASE, int CIN, int C0, int COUT_PAD, int NPW, bool RAW, bool OUT_F32, bool WLDS,
+          int WM>
 __device__ __forceinline__ void conv_layer_phase(const LayerArgs& a, const char* smem, int rowb) {
     typedef Traits<P> TR;
     typedef typename TR::T T;
     typedef typename TR::V V;
     constexpr int KS = TR::KS, VW = TR::VW;
-    constexpr int MT = COUT_PAD / 16;
+    // WM waves share a pixel tile, each owning every WM-th block of 16 rows
+    constexpr int MT = COUT_PAD / 16 / WM;
+    constexpr int WP = 4 / WM;
+    static_assert(COUT_PAD / 16 % WM == 0, "row blocks split evenly over waves");
     constexpr int ES = (int)sizeof(T);
     constexpr int NT = ntaps_of<MODE, PHASE>();
     constexpr int KSTEPS = (NT * CIN + KS - 1) / KS;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r16 = lane & 15;
+    const int wm = wave % WM, wp = wave / WM;
     const T* wglob = (const T*)a.wpack + (size_t)PHASE * COUT_PAD * a.kstride;
 
     // biases of this lane's output channels, loaded once
@@ -386,13 +391,13 @@ __device__ __forceinline__ void conv_layer_phase(const LayerArgs& a, const char*
             for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int ch = m * 16 + g * 4 + e;
+                    const int ch = (wm + WM * m) * 16 + g * 4 + e;
                     bias[m][e] = ch < nb ? a.bias[ch] : 0.0f;
                 }
         }
         const long rowd0 = (long)G.Win * G.s0.ld, rowd1 = (long)G.Win * G.s1.ld;
 
-        for (long pix0 = t0 + (long)wave * (NPW * 16); pix0 < t1; pix0 += 4L * NPW * 16) {
+        for (long pix0 = t0 + (long)wp * (NPW * 16); pix0 < t1; pix0 += (long)WP * NPW * 16) {
             PixState ps[NPW];
 #pragma unroll
             for (int p = 0; p < NPW; ++p) pix_setup<MODE, RAW>(G, pix0 + p * 16 + r16, t0, t1, ps[p]);
@@ -419,10 +424,11 @@ __device__ __forceinline__ void conv_layer_phase(const LayerArgs& a, const char*
                 V av[MT];
 #pragma unroll
                 for (int m = 0; m < MT; ++m) {
+                    const int row = (wm + WM * m) * 16 + r16;
                     if constexpr (WLDS)
-                        av[m] = *(const V*)(smem + (m * 16 + r16) * rowb + (ks * KS + g * VW) * ES);
+                        av[m] = *(const V*)(smem + row * rowb + (ks * KS + g * VW) * ES);
                     else
-                        av[m] = *(const V*)(wglob + (size_t)(m * 16 + r16) * a.kstride + ks * KS + g * VW);
+                        av[m] = *(const V*)(wglob + (size_t)row * a.kstride + ks * KS + g * VW);
                 }
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
@@ -440,7 +446,7 @@ __device__ __forceinline__ void conv_layer_phase(const LayerArgs& a, const char*
                 const long doff1 = ps[p].opix * G.seg1.ld;
 #pragma unroll
                 for (int m = 0; m < MT; ++m) {
-                    const int ch = m * 16 + g * 4;
+                    const int ch = (wm + WM * m) * 16 + g * 4;
                     float val[4] = {acc[m][p].x * a.acc_scale + bias[m][0], acc[m][p].y * a.acc_scale + bias[m][1],
                                     acc[m][p].z * a.acc_scale + bias[m][2], acc[m][p].w * a.acc_scale + bias[m][3]};
                     if (ch < G.seg0.c)
@@ -454,7 +460,7 @@ __device__ __forceinline__ void conv_layer_phase(const LayerArgs& a, const char*
 }
 
 // Persistent stride-2 convolution kernel.
-template <int P, int MODE, int CIN, int C0, int COUT_PAD, int NPW, bool RAW, bool OUT_F32, bool WLDS>
+template <int P, int MODE, int CIN, int C0, int COUT_PAD, int NPW, bool RAW, bool OUT_F32, bool WLDS, int WM>
 __global__ __launch_bounds__(256) void conv_layer_kernel(const LayerArgs a) {
     static_assert(MODE == M_CONV, "transposed convolutions use tconv_pairs_kernel / tconv_merged_kernel");
     typedef typename Traits<P>::T T;
@@ -463,26 +469,30 @@ __global__ __launch_bounds__(256) void conv_layer_kernel(const LayerArgs a) {
     extern __shared__ __align__(16) char smem[];
     const int rowb = wlds_row_bytes(a.kstride, ES);
     if constexpr (WLDS) stage_weights<ES>(smem, a.wpack, COUT_PAD, a.kstride, (9 * CIN + KS - 1) / KS * KS, rowb);
-    conv_layer_phase<P, MODE, 0, CIN, C0, COUT_PAD, NPW, RAW, OUT_F32, WLDS>(a, smem, rowb);
+    conv_layer_phase<P, MODE, 0, CIN, C0, COUT_PAD, NPW, RAW, OUT_F32, WLDS, WM>(a, smem, rowb);
 }
 
 // Persistent stride-2 transposed convolution over all four output phases.
 // Each GEMM pixel (a, b) gathers its 4 input neighbours once per K step and
 // feeds them to the 9 (phase, neighbour) weight blocks; weight pack
 // [pair q][COUT_PAD][kstride].
-template <int P, int CIN, int C0, int COUT_PAD, int NPW, bool OUT_F32, bool WLDS>
+template <int P, int CIN, int C0, int COUT_PAD, int NPW, bool OUT_F32, bool WLDS, int WM>
 __global__ __launch_bounds__(256) void tconv_pairs_kernel(const LayerArgs a) {
     typedef Traits<P> TR;
     typedef typename TR::T T;
     typedef typename TR::V V;
     constexpr int KS = TR::KS, VW = TR::VW;
     constexpr int ES = (int)sizeof(T);
-    constexpr int MT = COUT_PAD / 16;
+    // WM waves share a pixel tile, each owning every WM-th block of 16 rows
+    constexpr int MT = COUT_PAD / 16 / WM;
+    constexpr int WP = 4 / WM;
+    static_assert(COUT_PAD / 16 % WM == 0, "row blocks split evenly over waves");
     static_assert(CIN % KS == 0, "one neighbour per K step");
     constexpr int KSN = CIN / KS;
     extern __shared__ __align__(16) char smem[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r16 = lane & 15;
+    const int wm = wave % WM, wp = wave / WM;
     const int rowb = wlds_row_bytes(a.kstride, ES);
     if constexpr (WLDS) stage_weights<ES>(smem, a.wpack, 9 * COUT_PAD, a.kstride, CIN, rowb);
     const T* wglob = (const T*)a.wpack;
@@ -496,11 +506,11 @@ __global__ __launch_bounds__(256) void tconv_pairs_kernel(const LayerArgs a) {
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int ch = m * 16 + g * 4 + e;
+                const int ch = (wm + WM * m) * 16 + g * 4 + e;
                 bias[m][e] = (a.bias && ch < nb_out) ? a.bias[ch] : 0.0f;
             }
         const long rowd0 = (long)G.Win * G.s0.ld, rowd1 = (long)G.Win * G.s1.ld;
-        for (long pix0 = t0 + (long)wave * (NPW * 16); pix0 < t1; pix0 += 4L * NPW * 16) {
+        for (long pix0 = t0 + (long)wp * (NPW * 16); pix0 < t1; pix0 += (long)WP * NPW * 16) {
             PixState ps[NPW];
 #pragma unroll
             for (int p = 0; p < NPW; ++p) pix_setup<M_TCONV, false>(G, pix0 + p * 16 + r16, t0, t1, ps[p]);
@@ -531,7 +541,7 @@ __global__ __launch_bounds__(256) void tconv_pairs_kernel(const LayerArgs a) {
                     const int ph = pair_phase(q), nb = pair_nb(q);
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
-                        const int row = (q * COUT_PAD + m * 16 + r16);
+                        const int row = q * COUT_PAD + (wm + WM * m) * 16 + r16;
                         V av;
                         if constexpr (WLDS)
                             av = *(const V*)(smem + row * rowb + (ks * KS + g * VW) * ES);
@@ -555,7 +565,7 @@ __global__ __launch_bounds__(256) void tconv_pairs_kernel(const LayerArgs a) {
                     const long doff1 = opix * G.seg1.ld;
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
-                        const int ch = m * 16 + g * 4;
+                        const int ch = (wm + WM * m) * 16 + g * 4;
                         float val[4] = {acc[ph][m][p].x * a.acc_scale + bias[m][0], acc[ph][m][p].y * a.acc_scale + bias[m][1],
                                         acc[ph][m][p].z * a.acc_scale + bias[m][2], acc[ph][m][p].w * a.acc_scale + bias[m][3]};
                         if (ch < G.seg0.c)

@@ -29,7 +29,11 @@ struct GemmCfg {
     static constexpr int WROWS = MODE == M_CONV ? RUP : (MODE == M_TCONV_PAIRS ? 9 * RUP : MROWS);
     static constexpr int LDS = WROWS * wlds_row_bytes(KSTRIDE, ES);
     static constexpr bool WLDS = LDS <= 80 * 1024;
-    static constexpr int MT = MODE == M_CONV ? RUP / 16 : (MODE == M_TCONV_PAIRS ? 4 * RUP / 16 : MROWS / 16);
+    // weights read from L2: split the row blocks over up to 4 waves for reuse
+    static constexpr int RB = MODE == M_TCONV_MERGED ? MROWS / 16 : RUP / 16;
+    static constexpr int WM = (WLDS || MODE == M_TCONV_MERGED) ? 1 : (RB % 4 == 0 ? 4 : (RB % 2 == 0 ? 2 : 1));
+    // accumulator blocks per wave and 16-pixel block
+    static constexpr int MT = MODE == M_TCONV_PAIRS ? 4 * RB / WM : RB / WM;
 };
 
 template <typename K>
@@ -48,9 +52,9 @@ static drc_status launch_one(const LayerArgs& a, dim3 grid, hipStream_t s) {
     typedef GemmCfg<P, MODE, CIN, ROWS> C;
     const int lds = C::WLDS ? C::LDS : 0;
     if constexpr (MODE == M_CONV)
-        return launch_kernel(conv_layer_kernel<P, MODE, CIN, C0, C::RUP, NPW, RAW, OF32, C::WLDS>, a, grid, lds, s);
+        return launch_kernel(conv_layer_kernel<P, MODE, CIN, C0, C::RUP, NPW, RAW, OF32, C::WLDS, C::WM>, a, grid, lds, s);
     else if constexpr (MODE == M_TCONV_PAIRS)
-        return launch_kernel(tconv_pairs_kernel<P, CIN, C0, C::RUP, NPW, OF32, C::WLDS>, a, grid, lds, s);
+        return launch_kernel(tconv_pairs_kernel<P, CIN, C0, C::RUP, NPW, OF32, C::WLDS, C::WM>, a, grid, lds, s);
     else
         return launch_kernel(tconv_merged_kernel<P, CIN, C0, ROWS, C::MROWS, NPW, OF32, C::WLDS>, a, grid, lds, s);
 }
