@@ -347,6 +347,163 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
                     }
 }
 
+// BF16 weight gradient (same D[j][cp] as wgrad_kernel) with both operands
+// staged in LDS so that the reduction runs on v_mfma_f32_16x16x32_bf16,
+// whose operands need 8 consecutive reduction pixels per lane.
+// A workgroup walks strips of R rows x Wr columns of reduction pixels of one
+// map (Wr a multiple of 8, R*Wr a multiple of 32). Per strip:
+// * the gathered operand's rows 2u0-1 .. 2u0+2R-1 are staged as
+//   Qs[c][row][kw][v] = Q[2u0-1+row][2v+kw-1][c] (zero outside), i.e. three
+//   column views, one per kernel column kw, so that tap (kh, kw) of pixels
+//   (u, v..v+7) is one aligned 16-byte read at row 2(u-u0)+kh;
+// * the plain operand's channel tile [cp0, cp0+16 PB) is staged transposed,
+//   Pt[cp][k], k = (u-u0)*Wr + v.
+// Wave w owns the (tap, channel) row blocks w, w+4, ... and all PB column
+// blocks, accumulating over the workgroup's strips; each workgroup writes
+// its own partial tile (summed later in a fixed order).
+struct WgradBArgs {
+    const void* p; const void* p2;  // plain operand (bf16), channels [0, pc0) from p, the rest from p2
+    int pc, pc0, pld, p2ld;
+    const void* q;                  // gathered operand: bf16, or float32 when q_raw
+    int q_raw, qc, qld;
+    int nmaps, Hr, Wr, Hq, Wq;
+    int R, strips_per_map, total_strips, strips_per_chunk;
+    int qcs;                        // LDS elements per staged channel (padded)
+    float* partial;                 // [chunk][9*qc][pc]
+};
+
+template <int JBW, int PB, int QCP>
+__global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradBArgs a) {
+    extern __shared__ __align__(16) char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int Wr = a.Wr, R = a.R, K = R * Wr;
+    const int qrows = 2 * R + 1;
+    uint16_t* Qs = (uint16_t*)smem;
+    uint16_t* Pt = Qs + (size_t)QCP * a.qcs;
+    const int ptld = K + 8;
+    const int cp0 = blockIdx.y * PB * 16;
+    const int J = 9 * a.qc;
+
+    // this lane's (tap, channel) row per owned row block
+    int jc[JBW], jrow[JBW], jview[JBW];
+    bool jv[JBW];
+#pragma unroll
+    for (int i = 0; i < JBW; ++i) {
+        const int j = (wave + 4 * i) * 16 + r16;
+        jv[i] = j < J;
+        const int t = jv[i] ? j / a.qc : 0;
+        jc[i] = jv[i] ? j - t * a.qc : 0;
+        jrow[i] = t / 3;           // kh
+        jview[i] = t - 3 * (t / 3); // kw
+    }
+    f4 acc[JBW][PB];
+#pragma unroll
+    for (int i = 0; i < JBW; ++i)
+#pragma unroll
+        for (int b = 0; b < PB; ++b) acc[i][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+    const int s_begin = blockIdx.x * a.strips_per_chunk;
+    const int s_end = min(a.total_strips, s_begin + a.strips_per_chunk);
+    for (int s = s_begin; s < s_end; ++s) {
+        const int n = s / a.strips_per_map;
+        const int u0 = (s - n * a.strips_per_map) * R;
+        __syncthreads();  // the previous strip's LDS reads are done
+        // ---- stage the gathered operand (three column views)
+        const int ncols = 2 * Wr + 1;  // columns -1 .. 2 Wr - 1
+        constexpr int CG = QCP / 8;
+        for (int e = threadIdx.x; e < qrows * ncols * CG; e += 256) {
+            const int cg = e % CG;
+            const int rest = e / CG;
+            const int colp = rest % ncols, row = rest / ncols;
+            const int qi = 2 * u0 - 1 + row, qj = colp - 1;
+            float v8[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v8[k] = 0.0f;
+            if ((unsigned)qi < (unsigned)a.Hq && (unsigned)qj < (unsigned)a.Wq) {
+                const long base = (((long)n * a.Hq + qi) * a.Wq + qj) * a.qld + cg * 8;
+                if (a.q_raw) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if (cg * 8 + k < a.qc) v8[k] = ((const float*)a.q)[base + k];
+                } else {
+                    const uint4 w = *(const uint4*)((const uint16_t*)a.q + base);
+                    const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        v8[2 * k] = bf16_to_f32((uint16_t)(ww[k] & 0xffffu));
+                        v8[2 * k + 1] = bf16_to_f32((uint16_t)(ww[k] >> 16));
+                    }
+                }
+            }
+            // column qj feeds view kw at v = (qj + 1 - kw) / 2 when that is an integer in [0, Wr)
+#pragma unroll
+            for (int kw = 0; kw < 3; ++kw) {
+                const int t2 = qj + 1 - kw;
+                if (t2 < 0 || (t2 & 1)) continue;
+                const int v = t2 >> 1;
+                if (v >= Wr) continue;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const __bf16 b = (__bf16)v8[k];
+                    Qs[(size_t)(cg * 8 + k) * a.qcs + (row * 3 + kw) * Wr + v] = __builtin_bit_cast(uint16_t, b);
+                }
+            }
+        }
+        // ---- stage the plain operand, transposed
+        for (int e = threadIdx.x; e < K * PB * 2; e += 256) {
+            const int cg = e % (PB * 2);
+            const int k = e / (PB * 2);
+            const int u = u0 + k / Wr, v = k % Wr;
+            const int c = cp0 + cg * 8;
+            uint4 w = make_uint4(0, 0, 0, 0);
+            if (u < a.Hr && c < a.pc) {
+                const long pix = ((long)n * a.Hr + u) * a.Wr + v;
+                w = (c < a.pc0) ? *(const uint4*)((const uint16_t*)a.p + pix * a.pld + c)
+                                : *(const uint4*)((const uint16_t*)a.p2 + pix * a.p2ld + (c - a.pc0));
+            }
+            const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) {
+                Pt[(size_t)(cg * 8 + 2 * k2) * ptld + k] = (uint16_t)(ww[k2] & 0xffffu);
+                Pt[(size_t)(cg * 8 + 2 * k2 + 1) * ptld + k] = (uint16_t)(ww[k2] >> 16);
+            }
+        }
+        __syncthreads();
+        // ---- MFMAs over the strip
+        for (int ks = 0; ks < K / 32; ++ks) {
+            const int k0 = ks * 32 + 8 * g;
+            const int ul = k0 / Wr, v0 = k0 - (k0 / Wr) * Wr;
+            uint4 bfr[PB];
+#pragma unroll
+            for (int b = 0; b < PB; ++b) bfr[b] = *(const uint4*)(Pt + (size_t)(b * 16 + r16) * ptld + k0);
+#pragma unroll
+            for (int i = 0; i < JBW; ++i) {
+                uint4 afr = make_uint4(0, 0, 0, 0);
+                if (jv[i])
+                    afr = *(const uint4*)(Qs + (size_t)jc[i] * a.qcs + ((2 * ul + jrow[i]) * 3 + jview[i]) * Wr + v0);
+#pragma unroll
+                for (int b = 0; b < PB; ++b)
+                    acc[i][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, afr),
+                                                                      __builtin_bit_cast(bf16x8, bfr[b]), acc[i][b],
+                                                                      0, 0, 0);
+            }
+        }
+    }
+    // ---- partial tile: lane holds rows 4*g + r of row block (wave + 4 i), column r16 of block b
+    float* out = a.partial + (long)blockIdx.x * J * a.pc;
+#pragma unroll
+    for (int i = 0; i < JBW; ++i)
+#pragma unroll
+        for (int b = 0; b < PB; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = (wave + 4 * i) * 16 + 4 * g + r;
+                const int cp = cp0 + b * 16 + r16;
+                if (j < J && cp < a.pc) out[(long)j * a.pc + cp] = acc[i][b][r];
+            }
+}
+
 // dW in the parameter layout from partial[chunk][j][cp] (fixed-order sum).
 // q_is_cout: 1 for transposed-convolution layers (j = t*Cout + co, cp = ci),
 // 0 for convolution layers (j = t*Cin + ci, cp = co).

@@ -293,7 +293,7 @@ extern "C" drc_status drc_cae_saved_size(const drc_cae* h, int n, int H, int W, 
 
 // Weight-gradient work split for layer l (see wgrad_kernel): MFMA tile
 // blocks, reduction pixels per workgroup and number of reduction chunks.
-WgradPlan wgrad_plan(int l, int n, int H, int W) {
+WgradPlan wgrad_plan(int l, int n, int H, int W, int prec) {
     const LayerDef& L = kLayers[l];
     int hin, win, hout, wout;
     layer_io(l, H, W, &hin, &win, &hout, &wout);
@@ -318,6 +318,42 @@ WgradPlan wgrad_plan(int l, int n, int H, int W) {
     w.per_block = pb;
     w.nchunks = (int)((K + pb - 1) / pb);
     w.partial_floats = (size_t)w.nchunks * per_chunk_floats;  // 4 wave slots per chunk
+
+    // BF16: LDS-staged operands on bf16 MFMA when a row holds whole groups of 8 pixels
+    w.bf16 = 0;
+    if (prec == P_BF16 && w.Wr % 8 == 0) {
+        w.QCP = (w.qc + 7) / 8 * 8;
+        const int jb = (9 * w.qc + 15) / 16;
+        w.JBW = (jb + 3) / 4;
+        w.BPB = (w.pc >= 64) ? 4 : 2;
+        w.bptiles = (w.pc + 16 * w.BPB - 1) / (16 * w.BPB);
+        const bool inst = (w.JBW == 1 && (w.BPB == 2 || w.BPB == 4) && w.QCP == 8) ||
+                          (w.JBW == 5 && w.BPB == 4 && w.QCP == 32) || (w.JBW == 9 && w.BPB == 4 && w.QCP == 64);
+        for (int R = std::max(1, 128 / w.Wr); R >= 1 && inst; R /= 2) {
+            if ((R * w.Wr) % 32) continue;
+            int qcs = (2 * R + 1) * 3 * w.Wr;
+            qcs = (qcs + 7) / 8 * 8;
+            if ((qcs / 8) % 2 == 0) qcs += 8;
+            const int lds = w.QCP * qcs * 2 + 16 * w.BPB * (R * w.Wr + 8) * 2;
+            if (lds > 64 * 1024) continue;
+            w.bf16 = 1;
+            w.R = R;
+            w.qcs = qcs;
+            w.lds = lds;
+            break;
+        }
+        if (w.bf16) {
+            w.strips_per_map = (w.Hr + w.R - 1) / w.R;
+            w.total_strips = n * w.strips_per_map;
+            const long per_chunk = 9L * w.qc * w.pc;
+            long chunks = std::max(1L, 2048L / w.bptiles);
+            chunks = std::min(chunks, std::max(1L, (16L << 20) / per_chunk));
+            chunks = std::min<long>(chunks, w.total_strips);
+            w.strips_per_chunk = (int)((w.total_strips + chunks - 1) / chunks);
+            w.bchunks = (w.total_strips + w.strips_per_chunk - 1) / w.strips_per_chunk;
+            w.partial_floats = std::max(w.partial_floats, (size_t)w.bchunks * per_chunk);
+        }
+    }
     return w;
 }
 
@@ -360,7 +396,7 @@ BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed) {
     b.dz_h1 = cur; cur += align256(a.p1 * 32 * es);
     size_t wp = 0, bp = 0;
     for (int l = 0; l < 6; ++l) {
-        wp = std::max(wp, wgrad_plan(l, n, H, W).partial_floats * sizeof(float));
+        wp = std::max(wp, wgrad_plan(l, n, H, W, prec).partial_floats * sizeof(float));
         int hin, win, hout, wout;
         layer_io(l, H, W, &hin, &win, &hout, &wout);
         int nb;

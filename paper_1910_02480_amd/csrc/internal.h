@@ -99,8 +99,10 @@ struct WgradPlan {
     int qc, pc, Hr, Wr, JB, PB, VEC, jtiles, ptiles, nchunks;
     long per_block;
     size_t partial_floats;
+    // BF16 path with LDS-staged operands (bf16 = 1 when it applies)
+    int bf16, QCP, JBW, BPB, R, strips_per_map, total_strips, strips_per_chunk, bchunks, bptiles, qcs, lds;
 };
-WgradPlan wgrad_plan(int l, int n, int H, int W);
+WgradPlan wgrad_plan(int l, int n, int H, int W, int prec);
 void colsum_split(long npix, int* nblocks, long* per_block);
 BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed);
 StepLayout step_layout(int prec, int n, int H, int W, int recompute);

@@ -290,9 +290,42 @@ template <typename T>
 static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_raw, Src s0, Src s1,
                               int a_raw_c, float* partial, float* out, float scale, hipStream_t s) {
     const LayerDef& L = kLayers[l];
-    const WgradPlan wp = wgrad_plan(l, n, H, W);
+    const WgradPlan wp = wgrad_plan(l, n, H, W, sizeof(T) == 2 ? P_BF16 : P_F32);
     int hin, win, hout, wout;
     layer_io(l, H, W, &hin, &win, &hout, &wout);
+    if (wp.bf16) {
+        WgradBArgs b;
+        memset(&b, 0, sizeof b);
+        if (!L.tconv) {
+            b.p = g; b.pc = L.cout; b.pc0 = L.cout; b.pld = L.cout;
+            b.q = s0.p; b.q_raw = a_raw_c > 0; b.qc = L.cin; b.qld = s0.ld; b.Hq = hin; b.Wq = win;
+        } else {
+            b.p = s0.p; b.p2 = s1.p; b.pc = L.cin; b.pc0 = s0.c; b.pld = s0.ld; b.p2ld = s1.ld;
+            b.q = g; b.q_raw = g_raw; b.qc = L.cout; b.qld = L.cout; b.Hq = hout; b.Wq = wout;
+        }
+        b.nmaps = n;
+        b.Hr = wp.Hr;
+        b.Wr = wp.Wr;
+        b.R = wp.R;
+        b.strips_per_map = wp.strips_per_map;
+        b.total_strips = wp.total_strips;
+        b.strips_per_chunk = wp.strips_per_chunk;
+        b.qcs = wp.qcs;
+        b.partial = partial;
+        dim3 grid(wp.bchunks, wp.bptiles);
+        if (wp.JBW == 1 && wp.BPB == 2)
+            hipLaunchKernelGGL((wgrad_bf16_kernel<1, 2, 8>), grid, dim3(256), wp.lds, s, b);
+        else if (wp.JBW == 1)
+            hipLaunchKernelGGL((wgrad_bf16_kernel<1, 4, 8>), grid, dim3(256), wp.lds, s, b);
+        else if (wp.JBW == 5)
+            hipLaunchKernelGGL((wgrad_bf16_kernel<5, 4, 32>), grid, dim3(256), wp.lds, s, b);
+        else
+            hipLaunchKernelGGL((wgrad_bf16_kernel<9, 4, 64>), grid, dim3(256), wp.lds, s, b);
+        const long count = 9L * wp.qc * wp.pc;
+        hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)std::min(2048L, (count + 255) / 256)), dim3(256), 0, s,
+                           (const float*)partial, wp.bchunks, wp.qc, wp.pc, (int)L.tconv, scale, out);
+        return check_launch("weight_grad");
+    }
     WgradArgs a;
     memset(&a, 0, sizeof a);
     if (!L.tconv) {  // plain = output gradient, gathered = layer input
