@@ -297,6 +297,15 @@ def main():
             tt = timed(lambda: tr.step(xt, tg), args.steps, args.warmup)
             legs[f"{comp}_train_step"] = {"maps_per_s": nt / tt, "ms": tt * 1e3, "batch": nt,
                                           "recompute": True}
+            B.drc_cae_profile(tr.cae.h, 1)
+            B.drc_cae_profile_read(tr.cae.h)
+            tr.step(xt, tg)
+            ms_s, calls_s = B.drc_cae_profile_read(tr.cae.h)
+            B.drc_cae_profile(tr.cae.h, 0)
+            names = [f"fwd {LAYERS[l][0]}" for l in range(6)] + [f"dgrad {LAYERS[l][0]}" for l in range(6)] + \
+                    [f"wgrad {LAYERS[l][0]}" for l in range(6)] + ["bias grads", "loss", "adam+repack"]
+            legs[f"{comp}_train_step"]["breakdown_ms"] = {names[k]: round(ms_s[k], 4) for k in range(21)
+                                                          if calls_s[k]}
             log(f"{comp} train step (batch {nt}): {nt / tt:,.0f} maps/s, {tt * 1e3:.3f} ms")
         # ---------------- mixed-resolution frame: one graph replay per frame
         legs["bf16_mixed_frame"] = mixed_frame_leg(cae, tune_path, args)

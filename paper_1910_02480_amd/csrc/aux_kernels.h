@@ -141,34 +141,70 @@ static __global__ void l1_final_kernel(const double* partial, int nparts, long c
 }
 
 // ------------------------------------------------------------------ bias gradient
-// Column sums of a [npix][C] tensor in two fixed-order stages:
-// colsum_partial: block b sums rows [b*per, (b+1)*per) into partial[b][c];
-// colsum_final: one workgroup per column adds the partials (strided per
-// thread, then a tree in LDS) and scales.
-template <typename TG>
-__global__ __launch_bounds__(256) void colsum_partial_kernel(const TG* g, int C, int cpow2, int ld, long npix,
-                                                             long per_block, float* partial) {
-    __shared__ float red[256];
-    const int c = threadIdx.x % cpow2, po = threadIdx.x / cpow2, stride = 256 / cpow2;
-    const long b0 = blockIdx.x * per_block, b1 = min(npix, b0 + per_block);
-    float s = 0.0f;
-    if (c < C)
-        for (long p = b0 + po; p < b1; p += stride) s += to_float<TG>(g[p * ld + c]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = stride >> 1; o > 0; o >>= 1) {
-        if (po < o) red[threadIdx.x] += red[threadIdx.x + o * cpow2];
-        __syncthreads();
+// Column sums of a contiguous [npix][C] tensor (bias gradients), in two
+// fixed-order stages. Stage 1 views the tensor as a flat array read with
+// VW-element vector loads; the grid stride (in elements) is a multiple of C,
+// so every lane of a thread always adds the same channel. The workgroup then
+// folds its 256 x VW lane sums into C channel sums through LDS (first S =
+// 256 / C interleaved subsets per channel, then the S subset sums) and
+// writes partial[block][C]. Stage 2 adds the block rows per channel.
+template <typename TG, int VW>
+__global__ __launch_bounds__(256) void colsum_partial_kernel(const TG* g, long nelem, int C, float* partial) {
+    __shared__ float red[256 * VW];
+    __shared__ float red2[256];
+    float acc[VW];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) acc[k] = 0.0f;
+    const long tid = blockIdx.x * 256L + threadIdx.x;
+    const long stride = (long)gridDim.x * 256 * VW;
+    for (long e = tid * VW; e < nelem; e += stride) {
+        if (e + VW <= nelem) {
+            if constexpr (sizeof(TG) == 4) {
+                const float4 v = *(const float4*)((const float*)g + e);
+                acc[0] += v.x; acc[1] += v.y; acc[2] += v.z; acc[3] += v.w;
+            } else {
+                const uint4 v = *(const uint4*)((const uint16_t*)g + e);
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    acc[2 * k] += bf16_to_f32((uint16_t)(w[k] & 0xffffu));
+                    acc[2 * k + 1] += bf16_to_f32((uint16_t)(w[k] >> 16));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < VW; ++k)
+                if (e + k < nelem) acc[k] += to_float<TG>(g[e + k]);
+        }
     }
-    if (po == 0 && c < C) partial[(long)blockIdx.x * C + c] = red[threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) red[threadIdx.x * VW + k] = acc[k];
+    __syncthreads();
+    // flat LDS index f holds channel (base + f) % C
+    const int S = 256 / C;
+    const int base_mod = (int)(((long)blockIdx.x * 256 * VW) % C);
+    const int t = threadIdx.x;
+    if (t < S * C) {
+        const int c = t % C, j = t / C;
+        const int f0 = (c - base_mod + C) % C;
+        float v = 0.0f;
+        for (int f = f0 + C * j; f < 256 * VW; f += C * S) v += red[f];
+        red2[t] = v;
+    }
+    __syncthreads();
+    if (t < C) {
+        float v = 0.0f;
+        for (int j = 0; j < S; ++j) v += red2[t + C * j];
+        partial[(long)blockIdx.x * C + t] = v;
+    }
 }
 
-static __global__ __launch_bounds__(256) void colsum_final_kernel(const float* partial, int nblocks, int C,
+static __global__ __launch_bounds__(256) void colsum_final_kernel(const float* partial, int nrows, int C,
                                                                   float scale, float* out) {
     __shared__ float red[256];
     const int c = blockIdx.x;
     float s = 0.0f;
-    for (int b = threadIdx.x; b < nblocks; b += 256) s += partial[(long)b * C + c];
+    for (int r = threadIdx.x; r < nrows; r += 256) s += partial[(long)r * C + c];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -507,19 +543,36 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradBArgs a) {
 // dW in the parameter layout from partial[chunk][j][cp] (fixed-order sum).
 // q_is_cout: 1 for transposed-convolution layers (j = t*Cout + co, cp = ci),
 // 0 for convolution layers (j = t*Cin + ci, cp = co).
-static __global__ void wgrad_final_kernel(const float* partial, int nchunks, int qc, int pc, int q_is_cout,
-                                          float scale, float* dw) {
+static __global__ __launch_bounds__(1024) void wgrad_final_kernel(const float* partial, int nchunks, int qc,
+                                                                  int pc, int q_is_cout, float scale, float* dw) {
+    // 64 consecutive outputs per workgroup; wave w adds rows w, w + 16, ...
+    // (coalesced 256-byte row segments), then wave sums are added in order.
+    __shared__ float red[16][64];
     const long count = 9L * qc * pc;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count;
-         e += (long)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long e = blockIdx.x * 64L + lane;
+    float s = 0.0f;
+    if (e < count) {
+        int k = wv;
+        for (; k + 48 < nchunks; k += 64) {
+            const float a0 = partial[(long)k * count + e], a1 = partial[(long)(k + 16) * count + e];
+            const float a2 = partial[(long)(k + 32) * count + e], a3 = partial[(long)(k + 48) * count + e];
+            s += a0; s += a1; s += a2; s += a3;
+        }
+        for (; k < nchunks; k += 16) s += partial[(long)k * count + e];
+    }
+    red[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && e < count) {
+        float v = 0.0f;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) v += red[w][lane];
         const int cp = (int)(e % pc);
         const int j = (int)(e / pc);
-        const int t = j / qc, c = j - (j / qc) * qc;
-        float s = 0.0f;
-        for (int k = 0; k < nchunks; ++k) s += partial[(long)k * count + e];
+        const int t = j / qc, c = j - t * qc;
         const int co = q_is_cout ? c : cp, ci = q_is_cout ? cp : c;
         const int cin = q_is_cout ? pc : qc;
-        dw[((long)co * 9 + t) * cin + ci] = s * scale;
+        dw[((long)co * 9 + t) * cin + ci] = v * scale;
     }
 }
 

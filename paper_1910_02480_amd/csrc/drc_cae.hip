@@ -346,7 +346,7 @@ WgradPlan wgrad_plan(int l, int n, int H, int W, int prec) {
             w.strips_per_map = (w.Hr + w.R - 1) / w.R;
             w.total_strips = n * w.strips_per_map;
             const long per_chunk = 9L * w.qc * w.pc;
-            long chunks = std::max(1L, 2048L / w.bptiles);
+            long chunks = std::max(1L, 1024L / w.bptiles);
             chunks = std::min(chunks, std::max(1L, (16L << 20) / per_chunk));
             chunks = std::min<long>(chunks, w.total_strips);
             w.strips_per_chunk = (int)((w.total_strips + chunks - 1) / chunks);
@@ -368,11 +368,13 @@ void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout) {
 
 static const long kLossPerBlock = 16384;
 
-// Column-sum (bias gradient) split: at most 1024 fixed row ranges.
+// Column-sum (bias gradient) grid: a multiple of 3 blocks, so that the
+// element stride 256 * VW * blocks is a multiple of every channel count
+// (3, 32, 64, 128) with VW = 4 (float) or 8 (bf16).
 void colsum_split(long npix, int* nblocks, long* per_block) {
-    const long nb = std::max(1L, std::min(1024L, (npix + 255) / 256));
-    *per_block = (npix + nb - 1) / nb;
-    *nblocks = (int)((npix + *per_block - 1) / *per_block);
+    (void)npix;
+    *nblocks = 384;
+    *per_block = 0;
 }
 
 // Backward workspace: [recompute h3 u3 u2] [gradients] [wgrad partials] [bias partials]
@@ -402,7 +404,7 @@ BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed) {
         int nb;
         long per;
         colsum_split((long)n * hout * wout, &nb, &per);
-        bp = std::max(bp, (size_t)nb * kLayers[l].cout * sizeof(float));
+        bp = std::max(bp, (size_t)nb * 128 * sizeof(float));
     }
     b.wpart = cur; cur += align256(wp);
     b.bpart = cur; cur += align256(bp);

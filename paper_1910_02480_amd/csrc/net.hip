@@ -271,14 +271,13 @@ static drc_status bias_grad(const void* g, bool g_raw, int C, long npix, float* 
     int nb;
     long per;
     colsum_split(npix, &nb, &per);
-    int cp = 1;
-    while (cp < C) cp <<= 1;
-    if (g_raw)
-        hipLaunchKernelGGL(colsum_partial_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)g, C, cp, C,
-                           npix, per, partial);
+    const long nelem = npix * C;
+    if (g_raw || sizeof(T) == 4)
+        hipLaunchKernelGGL((colsum_partial_kernel<float, 4>), dim3(nb), dim3(256), 0, s, (const float*)g, nelem, C,
+                           partial);
     else
-        hipLaunchKernelGGL(colsum_partial_kernel<T>, dim3(nb), dim3(256), 0, s, (const T*)g, C, cp, C, npix,
-                           per, partial);
+        hipLaunchKernelGGL((colsum_partial_kernel<T, 8>), dim3(nb), dim3(256), 0, s, (const T*)g, nelem, C,
+                           partial);
     hipLaunchKernelGGL(colsum_final_kernel, dim3(C), dim3(256), 0, s, (const float*)partial, nb, C, scale, out);
     return check_launch("bias_grad");
 }
@@ -322,7 +321,7 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
         else
             hipLaunchKernelGGL((wgrad_bf16_kernel<9, 4, 64>), grid, dim3(256), wp.lds, s, b);
         const long count = 9L * wp.qc * wp.pc;
-        hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)std::min(2048L, (count + 255) / 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)((count + 63) / 64)), dim3(1024), 0, s,
                            (const float*)partial, wp.bchunks, wp.qc, wp.pc, (int)L.tconv, scale, out);
         return check_launch("weight_grad");
     }
@@ -371,7 +370,7 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
     else
         hipLaunchKernelGGL((wgrad_kernel<T, 2, 4, 1>), grid, dim3(256), 0, s, a);
     const long count = 9L * wp.qc * wp.pc;
-    hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)std::min(2048L, (count + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)((count + 63) / 64)), dim3(1024), 0, s,
                        (const float*)partial, 4 * wp.nchunks, wp.qc, wp.pc, (int)L.tconv, scale, out);
     return check_launch("weight_grad");
 }
