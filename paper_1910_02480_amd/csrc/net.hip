@@ -110,6 +110,19 @@ static LayerArgs layer_args(const void* wpack, int kstride) {
     return a;
 }
 
+// Halves the pixel blocks per wave until the launch has at least two work
+// items per compute unit (small batches), keeping every CU busy.
+static int fit_npw(int npw, long npix, int num_cu) {
+    while (npw > 1 && (npix + 64L * npw - 1) / (64L * npw) < 2L * num_cu) npw >>= 1;
+    return npw;
+}
+
+static long gemm_pixels(const LayerArgs& a) {
+    long p = 0;
+    for (int c = 0; c < a.nclass; ++c) p += (long)a.cls[c].nmaps * a.cls[c].Hg * a.cls[c].Wg;
+    return p;
+}
+
 int pick_npw(const drc_cae* h, int l, int H, int prec, bool bwd) {
     if (!bwd) {
         auto it = h->tile.find({l, H});
@@ -188,7 +201,16 @@ drc_status forward_classes(drc_cae* h, void* const* packs, const FwdClass* fc, i
                 if (it != h->tile_px.end()) a.cls[c].tile_px = it->second;
             }
         }
-        npw = fc[0].npw[l] > 0 ? fc[0].npw[l] : pick_npw(h, l, fc[0].H, P, false);
+        if (fc[0].npw[l] > 0) {
+            npw = fc[0].npw[l];
+        } else if (h->tile.count({l, fc[0].H})) {
+            npw = pick_npw(h, l, fc[0].H, P, false);
+        } else {
+            npw = default_npw(P, l, false);
+            bool fixed_px = false;
+            for (int c = 0; c < nclass; ++c) fixed_px |= a.cls[c].tile_px > 0;
+            if (!fixed_px) npw = fit_npw(npw, gemm_pixels(a), h->num_cu);
+        }
         const long tok = prof_begin(h, PROF_FWD + l, s);
         TRY(run_gemm<P>(l, false, a, npw, h->num_cu, s));
         prof_end(h, tok, s);
@@ -416,7 +438,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         G.seg0.ldm = 32;
         G.seg1 = seg_out(dh1s, 32, 0, 1.0f);
         { const long tok = prof_begin(h, PROF_BWD + 5, s);
-        TRY(run_gemm<P>(5, true, a, default_npw(P, 5, true), h->num_cu, s));
+        TRY(run_gemm<P>(5, true, a, fit_npw(default_npw(P, 5, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 5, s);
         TRY(weight_grad<T>(5, n, H, W, b.dy, true, Src{b.u2, 32, 32}, Src{b.h1, 32, 32}, 0, wpart,
@@ -438,7 +460,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         G.seg0.ldm = 64;
         G.seg1 = seg_out(dh2s, 64, 0, 1.0f);
         { const long tok = prof_begin(h, PROF_BWD + 4, s);
-        TRY(run_gemm<P>(4, true, a, default_npw(P, 4, true), h->num_cu, s));
+        TRY(run_gemm<P>(4, true, a, fit_npw(default_npw(P, 4, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 4, s);
         TRY(weight_grad<T>(4, n, H, W, dz_u2, false, Src{b.u3, 64, 64}, Src{b.h2, 64, 64}, 0, wpart,
@@ -459,7 +481,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         G.seg0.mask = b.h3;
         G.seg0.ldm = 128;
         { const long tok = prof_begin(h, PROF_BWD + 3, s);
-        TRY(run_gemm<P>(3, true, a, default_npw(P, 3, true), h->num_cu, s));
+        TRY(run_gemm<P>(3, true, a, fit_npw(default_npw(P, 3, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 3, s);
         TRY(weight_grad<T>(3, n, H, W, dz_u3, false, Src{b.h3, 128, 128}, Src{nullptr, 0, 0}, 0, wpart,
@@ -482,7 +504,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         G.seg0.mask = b.h2;
         G.seg0.ldm = 64;
         { const long tok = prof_begin(h, PROF_BWD + 2, s);
-        TRY(run_gemm<P>(2, true, a, default_npw(P, 2, true), h->num_cu, s));
+        TRY(run_gemm<P>(2, true, a, fit_npw(default_npw(P, 2, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 2, s);
         TRY(weight_grad<T>(2, n, H, W, dz_h3, false, Src{b.h2, 64, 64}, Src{nullptr, 0, 0}, 0, wpart,
@@ -505,7 +527,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         G.seg0.mask = b.h1;
         G.seg0.ldm = 32;
         { const long tok = prof_begin(h, PROF_BWD + 1, s);
-        TRY(run_gemm<P>(1, true, a, default_npw(P, 1, true), h->num_cu, s));
+        TRY(run_gemm<P>(1, true, a, fit_npw(default_npw(P, 1, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 1, s);
         TRY(weight_grad<T>(1, n, H, W, dz_h2, false, Src{b.h1, 32, 32}, Src{nullptr, 0, 0}, 0, wpart,
@@ -533,7 +555,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
             a.acc_scale = gscale;
             G.seg0 = seg_out(b.dx, 7, 0, 1.0f);
             { const long tok = prof_begin(h, PROF_BWD + 0, s);
-            TRY(run_gemm<P>(0, true, a, default_npw(P, 0, true), h->num_cu, s));
+            TRY(run_gemm<P>(0, true, a, fit_npw(default_npw(P, 0, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
             prof_end(h, tok, s); }
         }
     }
