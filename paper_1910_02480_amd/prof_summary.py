@@ -1,0 +1,177 @@
+"""Short text summaries of rocprofv3 output for the library's kernels.
+
+    python -m paper_1910_02480_amd.prof_summary stats <run_kernel_stats.csv> --cmd "..." --out X.md
+    python -m paper_1910_02480_amd.prof_summary traffic <fetch counter csv> <write counter csv> \
+        --cmd "..." --out X.md
+
+`stats` turns a `--kernel-trace --stats` kernel table into a markdown table
+with the layer each kernel instantiation serves. `traffic` turns two `--pmc`
+runs (FETCH_SIZE, then WRITE_SIZE; both in KiB per dispatch) into HBM bytes
+per launch, scaled by what the same counters read for a plain elementwise
+copy of known size run in the same process (torch.mul over 256 MiB): the
+scale factors are (true bytes) / (counted bytes) of that copy. The traffic
+file carries a hash of the kernel sources it was measured with, so that a
+reader can tell when the kernels have changed since.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 256 << 20  # one read and one write stream of this size
+
+# (regex on the demangled name, label); first match wins
+_LABELS = (
+    (r"conv_layer_kernel<1, 0, 8, 8, 32,", "forward E1"),
+    (r"conv_layer_kernel<1, 0, 32, 32, 64,", "forward E2"),
+    (r"conv_layer_kernel<1, 0, 64, 64, 128,", "forward E3"),
+    (r"tconv_pairs_kernel<1, 128, 128, 64,", "forward D3"),
+    (r"tconv_pairs_kernel<1, 128, 64, 32,", "forward D2"),
+    (r"tconv_merged_kernel<1, 64, 32, 3,", "forward D1"),
+    (r"cae_fused_forward_kernel", "forward fused"),
+    (r"pack_weights_kernel", "weight pack"),
+    (r"elementwise.*Mul|Mul.*elementwise", "copy (torch.mul, 256 MiB)"),
+)
+
+
+def label(name: str) -> str | None:
+    for pat, lab in _LABELS:
+        if re.search(pat, name):
+            return lab
+    return None
+
+
+def source_hash() -> str:
+    """Hash of the HIP sources and the public header the library is built from."""
+    h = hashlib.sha256()
+    files = []
+    csrc = os.path.join(_HERE, "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            files.append(os.path.join(csrc, f))
+    files.append(os.path.join(_HERE, "..", "include", "drc_cae.h"))
+    for p in files:
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _short(name: str, n: int = 90) -> str:
+    name = name.replace("(anonymous namespace)::", "")
+    return name if len(name) <= n else name[: n - 3] + "..."
+
+
+def stats(csv_path: str, cmd: str, title: str) -> str:
+    rows = list(csv.DictReader(open(csv_path)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows) or 1.0
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = [f"# {title}", "", "Command (run from /tmp with TMPDIR=/tmp; $R = repository root):", "",
+           f"    {cmd}", "", f"Source hash of the kernels: `{source_hash()}`", "",
+           "| Kernel | Serves | Calls | Avg (us) | Total (ms) | Share |", "|---|---|--:|--:|--:|--:|"]
+    for r in rows[:16]:
+        lab = label(r["Name"]) or ""
+        out.append(f"| `{_short(r['Name'])}` | {lab} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.3f} | {100 * float(r['TotalDurationNs']) / tot:.1f} % |")
+    return "\n".join(out) + "\n"
+
+
+def _per_dispatch(csv_path: str, counter: str):
+    """Mean counter value per dispatch of every labelled kernel instantiation."""
+    acc = collections.defaultdict(list)
+    for r in csv.DictReader(open(csv_path)):
+        if r["Counter_Name"] != counter:
+            continue
+        lab = label(r["Kernel_Name"])
+        if lab:
+            acc[(lab, r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def traffic(fetch_csv: str, write_csv: str, cmd_fetch: str, cmd_write: str, title: str) -> str:
+    f = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    w = _per_dispatch(write_csv, "WRITE_SIZE")
+    copy = "copy (torch.mul, 256 MiB)"
+    fc = [v[0] for (lab, _), v in f.items() if lab == copy]
+    wc = [v[0] for (lab, _), v in w.items() if lab == copy]
+    if not fc or not wc:
+        raise SystemExit("the copy kernel is missing from the counter files (run with --copy-calib)")
+    kf = COPY_BYTES / (fc[0] * 1024.0)
+    kw = COPY_BYTES / (wc[0] * 1024.0)
+    rows = []
+    kernels = {}
+    for key in sorted(set(f) & set(w)):
+        lab, name = key
+        if lab == copy:
+            continue
+        fk, nf = f[key]
+        wk, nw = w[key]
+        d = {"name": name, "fetch_kib": fk, "write_kib": wk, "dispatches": min(nf, nw),
+             "bytes_per_launch": fk * 1024.0 * kf + wk * 1024.0 * kw}
+        rows.append((lab, d))
+        # a label's figure: its most dispatched instantiation (the one the timed loop runs)
+        if lab not in kernels or d["dispatches"] > kernels[lab]["dispatches"]:
+            kernels[lab] = d
+    doc = {"source_hash": source_hash(), "fetch_scale": kf, "write_scale": kw,
+           "copy_fetch_kib": fc[0], "copy_write_kib": wc[0], "kernels": kernels}
+    out = [f"# {title}", "", "Commands (run from /tmp with TMPDIR=/tmp; $R = repository root):", "",
+           f"    {cmd_fetch}", f"    {cmd_write}", "",
+           f"Calibration: the 256 MiB elementwise copy reads {fc[0]:.0f} KiB (FETCH_SIZE) and writes "
+           f"{wc[0]:.0f} KiB (WRITE_SIZE) per dispatch, so counted FETCH is scaled by {kf:.3f} and "
+           f"WRITE by {kw:.3f}. Source hash of the kernels: `{doc['source_hash']}`.", "",
+           "| Kernel | Serves | Dispatches | FETCH (KiB) | WRITE (KiB) | HBM bytes per launch (scaled) |",
+           "|---|---|--:|--:|--:|--:|"]
+    for lab, d in rows:
+        out.append(f"| `{_short(d['name'])}` | {lab} | {d['dispatches']} | {d['fetch_kib']:.0f} | "
+                   f"{d['write_kib']:.0f} | {d['bytes_per_launch'] / 1e6:.1f} MB |")
+    out += ["", "Machine-readable copy (per layer: its most dispatched instantiation):", "", "```json",
+            json.dumps(doc, indent=1), "```", ""]
+    return "\n".join(out)
+
+
+def read_traffic(md_path: str):
+    """The json block of a traffic summary, or None when absent or stale."""
+    try:
+        text = open(md_path).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    doc = json.loads(m.group(1))
+    return doc if doc.get("source_hash") == source_hash() else None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--cmd", required=True)
+    s.add_argument("--title", default="Kernel trace")
+    s.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_csv")
+    t.add_argument("write_csv")
+    t.add_argument("--cmd-fetch", required=True)
+    t.add_argument("--cmd-write", required=True)
+    t.add_argument("--title", default="HBM traffic")
+    t.add_argument("--out", required=True)
+    a = ap.parse_args()
+    if a.cmd_name == "stats":
+        text = stats(a.csv, a.cmd, a.title)
+    else:
+        text = traffic(a.fetch_csv, a.write_csv, a.cmd_fetch, a.cmd_write, a.title)
+    with open(a.out, "w") as fh:
+        fh.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()
