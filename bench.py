@@ -56,6 +56,18 @@ def layer_cost(l, n, H, compute):
     return flops, bytes_in + bytes_out + bytes_w
 
 
+FUSED_SLOT = 21  # timing slot of the whole-network kernel
+
+
+def fused_cost(n, H):
+    """Algorithmic FLOPs and HBM bytes of one whole-network forward launch:
+    all six layers' nominal FLOPs; bytes = float32 x in (7 ch), float32 y
+    out (3 ch) and the BF16 weight packs once (activations stay on chip)."""
+    flops = sum(layer_cost(l, n, H, "bf16")[0] for l in range(6))
+    w = sum(cout * 9 * cin * 2 for _, _, cin, cout in LAYERS)
+    return flops, n * H * H * (7 + 3) * 4 + w
+
+
 def gen_maps(n, H, chunk=512):
     import numpy as np
     import torch
@@ -225,13 +237,19 @@ def main():
     y_bf16 = y[:8].cpu().numpy()
     value = n / t
     kernels = []
+    tot_ms = max(sum(ms_l[:6]) + ms_l[FUSED_SLOT], 1e-30)
     for l in range(6):
         if calls_l[l] == 0:
             continue
         avg = ms_l[l] / calls_l[l] * 1e-3
         fl, by = layer_cost(l, n, H, "bf16")
-        kernels.append({"kernel": f"forward {LAYERS[l][0]}", "avg_ms": avg * 1e3,
-                        "share": ms_l[l] / max(sum(ms_l[:6]), 1e-30),
+        kernels.append({"kernel": f"forward {LAYERS[l][0]}", "avg_ms": avg * 1e3, "share": ms_l[l] / tot_ms,
+                        "GB/s": by / avg / 1e9, "TFLOP/s": fl / avg / 1e12,
+                        "alg_bytes": by, "alg_flops": fl})
+    if calls_l[FUSED_SLOT]:
+        avg = ms_l[FUSED_SLOT] / calls_l[FUSED_SLOT] * 1e-3
+        fl, by = fused_cost(n, H)
+        kernels.append({"kernel": "forward fused", "avg_ms": avg * 1e3, "share": ms_l[FUSED_SLOT] / tot_ms,
                         "GB/s": by / avg / 1e9, "TFLOP/s": fl / avg / 1e12,
                         "alg_bytes": by, "alg_flops": fl})
     dom = max(kernels, key=lambda k: k["avg_ms"] * 1.0)
@@ -259,6 +277,13 @@ def main():
     log(f"bf16 forward: {value:,.0f} maps/s ({t * 1e3:.3f} ms / {n} maps)")
 
     if not args.main_only:
+        # ---------------- the same BF16 forward, one kernel per layer (activations through HBM)
+        cae.set_fused(False)
+        tl = timed(fwd, args.steps, args.warmup)
+        legs["bf16_fwd_layer_by_layer"] = {"maps_per_s": n / tl, "ms": tl * 1e3,
+                                           "mfma_frac_flop_based": total_flops / tl / (PEAK_TFLOPS["bf16"] * 1e12)}
+        log(f"bf16 forward, layer by layer: {n / tl:,.0f} maps/s")
+        cae.set_fused(True)
         # ---------------- FP32 and FP8 forward
         for comp in ("f32", "fp8"):
             c = CAE(comp, params, device=dev)

@@ -53,6 +53,7 @@ _SIGS = {
     "drc_cae_num_params": (_SZ, [_VP]),
     "drc_cae_set_params": (_I, [_VP, _VP, _VP]),
     "drc_cae_set_recompute": (_I, [_VP, _I]),
+    "drc_cae_set_fused": (_I, [_VP, _I]),
     "drc_cae_saved_size": (_I, [_VP, _I, _I, _I, ctypes.POINTER(_SZ), ctypes.POINTER(ctypes.c_int64)]),
     "drc_cae_workspace_size": (_I, [_VP, _I, _I, _I, _I, ctypes.POINTER(_SZ)]),
     "drc_cae_forward": (_I, [_VP, _VP, _VP, _I, _I, _I, _VP, _VP, _SZ, _VP]),
@@ -153,6 +154,10 @@ def drc_cae_set_params(h, params, stream=None):
 
 def drc_cae_set_recompute(h, on):
     _check(lib().drc_cae_set_recompute(h, int(on)))
+
+
+def drc_cae_set_fused(h, on):
+    _check(lib().drc_cae_set_fused(h, int(on)))
 
 
 def drc_cae_saved_size(h, n, H, W):

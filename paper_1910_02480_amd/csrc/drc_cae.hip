@@ -194,6 +194,13 @@ extern "C" drc_status drc_cae_set_recompute(drc_cae* h, int on) {
     return DRC_OK;
 }
 
+extern "C" drc_status drc_cae_set_fused(drc_cae* h, int on) {
+    if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "set_fused: handle is NULL");
+    if (on != 0 && on != 1) return drc_fail(DRC_ERR_INVALID_ARG, "set_fused: on must be 0 or 1");
+    h->fused = on;
+    return DRC_OK;
+}
+
 extern "C" drc_status drc_cae_set_tile(drc_cae* h, int layer, int H, int npw) {
     if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "set_tile: handle is NULL");
     if (layer < 0 || layer > 5) return drc_fail(DRC_ERR_INVALID_ARG, "set_tile: layer %d", layer);

@@ -42,6 +42,7 @@ struct drc_cae {
     unsigned* amax = nullptr;  // scratch for amax reductions
     float host_scales[16];
     int recompute = 0;
+    int fused = 1;         // BF16 inference forward of 32x32 / 64x64 maps in one kernel
     bool params_set = false;
     bool calibrated = false;
     const float* packed_from = nullptr;
@@ -56,9 +57,9 @@ struct drc_cae {
 
 // Timing slots (drc_cae_profile_read): 0..5 forward GEMM of E1..D1,
 // 6..11 backward-data GEMM of E1..D1, 12..17 weight gradient of E1..D1,
-// 18 bias gradients, 19 L1 loss, 20 Adam and repack.
+// 18 bias gradients, 19 L1 loss, 20 Adam and repack, 21 fused forward.
 enum { PROF_FWD = 0, PROF_BWD = 6, PROF_WGRAD = 12, PROF_BIAS = 18, PROF_LOSS = 19, PROF_ADAM = 20,
-       PROF_SLOTS = 24 };
+       PROF_FUSED = 21, PROF_SLOTS = 24 };
 // Records the start event of a slot; returns a token for prof_end (or -1).
 long prof_begin(drc_cae* h, int slot, hipStream_t s);
 void prof_end(drc_cae* h, long token, hipStream_t s);
@@ -137,3 +138,10 @@ int pick_npw(const drc_cae* h, int l, int H, int prec, bool bwd);
 // Tile shapes: pixel blocks of 16 per wave built for each layer GEMM.
 bool npw_supported(int prec, int layer, bool backward, int npw);
 int default_npw(int prec, int layer, bool backward);
+
+// Whole-network BF16 forward with activations in LDS (fused_fwd.hip).
+bool fused_forward_size(int H, int W);
+int fused_forward_grid(const drc_cae* h, int n, int H, int W);
+size_t fused_forward_scratch(const drc_cae* h, int n, int H, int W);
+drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int W, const long* x_off,
+                         const long* y_off, void* scratch, size_t scratch_bytes, hipStream_t s);

@@ -267,6 +267,8 @@ extern "C" drc_status drc_cae_forward(drc_cae* h, const float* d_x, float* d_y, 
     TRY(drc_cae_workspace_size(h, n, H, W, DRC_WS_FORWARD, &need));
     if (ws_bytes < need)
         return drc_fail(DRC_ERR_WORKSPACE, "forward: workspace %zu < %zu bytes", ws_bytes, need);
+    if (h->fused && h->prec == P_BF16 && !d_saved && fused_forward_size(H, W))
+        return fused_forward(h, d_x, d_y, n, H, W, nullptr, nullptr, d_ws, ws_bytes, (hipStream_t)stream);
     ActSizes a = act_sizes(h->prec, n, H, W);
     char* ws = (char*)d_ws;
     void* act[5];
