@@ -10,14 +10,16 @@
 // through a per-workgroup slot that stays in the L2/last-level caches.
 //
 // LDS plan for an H x W map (bytes, BF16 NHWC, 16-byte channel chunks XOR-
-// swizzled per pixel against bank conflicts):
+// swizzled by column against bank conflicts):
 //   R0 [0, 16HW)           h1 (E1 -> E2), then u2 (D2 -> D1)
 //   R1 [16HW, 24HW)        h2 (E2 -> D2)
 //   R2 [24HW, 32HW)        u3 (D3 -> D2)
 //   R3 [32HW, 36HW)        h3 (E3 -> D3)
 //   R1+R2                  x as BF16, 8 channels (staging -> E1), and h1
 //                          again for D1 (reloaded from the workgroup's slot)
-// 36 HW bytes in all: 144 KB at 64x64 (one workgroup per CU), 36 KB at 32x32.
+//   [36HW, 36HW + 256)     zeros, read by taps that fall outside the map
+// 36 HW bytes + 256 in all: 144 KB at 64x64 (one workgroup per CU), 36 KB
+// at 32x32.
 //
 // Every GEMM uses the same weight packs, K order and epilogue arithmetic as
 // the layer kernels, so the two paths agree bit for bit.
@@ -35,6 +37,7 @@ namespace {
 
 constexpr int FT = 512;      // threads per workgroup
 constexpr int FW = FT / 64;  // waves
+constexpr int kZeroBytes = 256;  // zero block read by taps outside the map (any chunk XOR stays inside)
 
 struct FusedArgs {
     const float* x;      // [.., H, W, 7] float32
@@ -50,23 +53,29 @@ struct FusedArgs {
 
 __device__ __forceinline__ uint16_t bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 
-// Byte offset of 16-byte chunk `chunk` of pixel p in an LDS tensor of C
-// channels. The chunk index is XORed with bits of p so that 16 lanes reading
-// the same chunk of pixels 1 or 2 apart spread over the banks.
+// Byte offset of 16-byte chunk `chunk` of pixel (y, x) in an LDS tensor of C
+// channels and row length WI. The chunk index is XORed with bits of the
+// column x, so that the 16 lanes of an MFMA operand, which read the same
+// chunk of pixels 1 or 2 columns apart, spread over the LDS banks; since the
+// swizzle ignores the row, moving by whole rows is a constant byte offset.
 template <int C>
-__device__ __forceinline__ int loff(int p, int chunk) {
+__device__ __forceinline__ int swz(int x) {
     constexpr int CH = C / 8;
-    int sw;
-    if constexpr (CH == 1) sw = 0;
-    else if constexpr (CH == 4) sw = (p >> 2) & 3;
-    else if constexpr (CH == 8) sw = (p >> 1) & 7;
-    else sw = p & 15;
-    return p * (C * 2) + ((chunk ^ sw) & (CH - 1)) * 16;
+    if constexpr (CH == 1) return 0;
+    else if constexpr (CH == 4) return (x >> 2) & 3;
+    else if constexpr (CH == 8) return (x >> 1) & 7;
+    else return x & 15;
+}
+template <int C, int WI>
+__device__ __forceinline__ int loff(int y, int x, int chunk) {
+    constexpr int CH = C / 8;
+    return (y * WI + x) * (C * 2) + ((chunk ^ swz<C>(x)) & (CH - 1)) * 16;
 }
 
-// Stores channels [ch, ch+4) of pixel p (bias added, optional ReLU) as BF16.
-template <int C>
-__device__ __forceinline__ void lds_store4(char* t, int p, int ch, const f4& acc, const float* bias, bool relu) {
+// Stores channels [ch, ch+4) of pixel (y, x) (bias added, optional ReLU) as BF16.
+template <int C, int WI>
+__device__ __forceinline__ void lds_store4(char* smem, int region, int y, int x, int ch, const f4& acc,
+                                           const float* bias, bool relu) {
     float v[4] = {acc.x + bias[0], acc.y + bias[1], acc.z + bias[2], acc.w + bias[3]};
     if (relu) {
 #pragma unroll
@@ -75,81 +84,136 @@ __device__ __forceinline__ void lds_store4(char* t, int p, int ch, const f4& acc
     uint2 w;
     w.x = (uint32_t)bf16_bits(v[0]) | ((uint32_t)bf16_bits(v[1]) << 16);
     w.y = (uint32_t)bf16_bits(v[2]) | ((uint32_t)bf16_bits(v[3]) << 16);
-    *(uint2*)(t + loff<C>(p, ch >> 3) + ((ch >> 2) & 1) * 8) = w;
+    *(uint2*)(smem + region + loff<C, WI>(y, x, ch >> 3) + ((ch >> 2) & 1) * 8) = w;
 }
 
 __device__ __forceinline__ void mma(f4& acc, const uint4& a, const uint4& b) { Traits<P_BF16>::mma(acc, a, b); }
 
-// Hides a uniform pointer's value from the optimiser: weight loads are then
-// issued inside the tile loop instead of being hoisted out of the map loop
-// (where they would pin hundreds of registers across every layer).
+// Hides a value from the optimiser. Weight loads are then issued inside the
+// layer instead of being hoisted out of the map loop (where they would pin
+// hundreds of registers across every layer), and per-lane addresses are
+// recomputed per layer rather than kept live. Only an integer goes through
+// the asm statement, so pointers keep their global address space.
 template <typename T>
 __device__ __forceinline__ const T* opaque(const T* p) {
-    asm volatile("" : "+s"(p));
-    return p;
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return p + z;
 }
-// The same for the thread index: per-lane addresses of a layer are then
-// recomputed inside the map loop rather than kept live across all layers.
 __device__ __forceinline__ int opaque_tid() {
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
     return t;
 }
 
-// x (float32, 7 channels) -> LDS as BF16 with 8 channels (channel 7 = 0).
-// Flat float4 loads (coalesced), in groups of up to 8 per thread in flight.
+__device__ __forceinline__ uint4 lds16(const char* smem, int off) { return *(const uint4*)(smem + off); }
+
+// x (float32, 7 channels) -> LDS region xs as BF16 with 8 channels (channel
+// 7 = 0), 16 bytes per pixel. A thread converts 4 consecutive pixels (112
+// bytes of input = 7 float4, read together) per pass.
 template <int H, int W>
-__device__ __forceinline__ void stage_x(char* xs, const float* xm) {
-    constexpr int NF4 = H * W * 7 / 4;
-    constexpr int IT = (NF4 + FT - 1) / FT;
-    constexpr int GRP = IT < 8 ? IT : 8;
+__device__ __forceinline__ void stage_x(char* smem, int xs, const float* xm) {
+    constexpr int Q = H * W / 4;
+    constexpr int IT = (Q + FT - 1) / FT;
     const int tid = opaque_tid();
-    for (int p = tid; p < H * W; p += FT) *(uint16_t*)(xs + p * 16 + 14) = 0;
+    float4 v[IT][7];
 #pragma unroll
-    for (int g0 = 0; g0 < IT; g0 += GRP) {
-        float4 v[GRP];
+    for (int it = 0; it < IT; ++it) {
+        const int q = tid + it * FT;
+        if (Q % FT == 0 || q < Q)
 #pragma unroll
-        for (int it = 0; it < GRP; ++it) {
-            const int i = tid + (g0 + it) * FT;
-            if (g0 + it < IT && (NF4 % FT == 0 || i < NF4)) v[it] = ((const float4*)xm)[i];
-        }
+            for (int k = 0; k < 7; ++k) v[it][k] = ((const float4*)xm)[q * 7 + k];
+    }
 #pragma unroll
-        for (int it = 0; it < GRP; ++it) {
-            const int i = tid + (g0 + it) * FT;
-            if (g0 + it < IT && (NF4 % FT == 0 || i < NF4)) {
-                const float vv[4] = {v[it].x, v[it].y, v[it].z, v[it].w};
+    for (int it = 0; it < IT; ++it) {
+        const int q = tid + it * FT;
+        if (Q % FT == 0 || q < Q) {
+            const float* f = (const float*)v[it];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int f = 4 * i + k, p = f / 7, c = f - p * 7;
-                    *(uint16_t*)(xs + p * 16 + c * 2) = bf16_bits(vv[k]);
-                }
+            for (int px = 0; px < 4; ++px) {
+                uint4 o;
+                o.x = (uint32_t)bf16_bits(f[7 * px + 0]) | ((uint32_t)bf16_bits(f[7 * px + 1]) << 16);
+                o.y = (uint32_t)bf16_bits(f[7 * px + 2]) | ((uint32_t)bf16_bits(f[7 * px + 3]) << 16);
+                o.z = (uint32_t)bf16_bits(f[7 * px + 4]) | ((uint32_t)bf16_bits(f[7 * px + 5]) << 16);
+                o.w = (uint32_t)bf16_bits(f[7 * px + 6]);
+                *(uint4*)(smem + xs + (4 * q + px) * 16) = o;
             }
         }
     }
 }
 
 // Stride-2 3x3 convolution, LDS -> LDS, bias + ReLU (E1, E2, E3). Pack
-// [COUT][KSTEPS*32], k = tap * CIN + c. A wave owns tiles of MT row blocks
-// x NPW pixel blocks (16 consecutive output pixels each).
+// [COUT][KSTEPS*32], k = tap * CIN + c. Wave w owns the row blocks of group
+// w % TR for the whole layer and loads their weights (its A panel) into
+// registers once; it then walks the pixel tiles w / TR, w / TR + FW / TR, ...
+// (NPW blocks of 16 consecutive output pixels each). Taps that fall outside
+// the map read the zero block at zoff.
 template <int HI, int WI, int CIN, int COUT, int MT, int NPW>
-__device__ __forceinline__ void conv_phase(const char* in, char* out, const uint16_t* wp, const float* bias_g) {
+__device__ __forceinline__ void conv_phase(char* smem, int in, int out, int zoff, const uint16_t* wp,
+                                           const float* bias_g) {
     constexpr int HO = HI / 2, WO = WI / 2;
     constexpr int PB = HO * WO / 16, RB = COUT / 16;
     constexpr int KSTEPS = (9 * CIN + 31) / 32, KSTRIDE = KSTEPS * 32;
     constexpr int TR = RB / MT, TP = PB / NPW;
-    static_assert(RB % MT == 0 && PB % NPW == 0, "tiles cover the layer");
+    constexpr int ROW = WI * CIN * 2;  // bytes per input row
+    static_assert(RB % MT == 0 && PB % NPW == 0 && FW % TR == 0, "tiles cover the layer");
     const int tid = opaque_tid();
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, r16 = lane & 15;
-    for (int tile = wave; tile < TR * TP; tile += FW) {
-        const int tr = tile % TR, tp = tile / TR;
-        const uint16_t* w = opaque(wp);
+    const int tr = (wave + blockIdx.x) % TR;  // rotated by workgroup: CUs start on different weights
+    const uint16_t* w = opaque(wp);
+    uint4 A[KSTEPS][MT];
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS; ++ks)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            A[ks][m] = *(const uint4*)(w + (size_t)((tr * MT + m) * 16 + r16) * KSTRIDE + ks * 32 + g * 8);
+    const float* bg = opaque(bias_g);
+    float bias[MT][4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias[m][e] = bg[(tr * MT + m) * 16 + g * 4 + e];
+    // CIN == 8: the lane group g takes tap 4 ks + g of every K step
+    int dk[KSTEPS];
+    bool tv[KSTEPS], nt[KSTEPS], nl[KSTEPS];
+    if constexpr (CIN == 8) {
+#pragma unroll
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            const int t = ks * 4 + g, kh = t / 3, kw = t - (t / 3) * 3;
+            tv[ks] = t < 9;
+            nt[ks] = kh == 0;
+            nl[ks] = kw == 0;
+            dk[ks] = kh * ROW + kw * 16;
+        }
+    }
+    for (int tp = wave / TR; tp < TP; tp += FW / TR) {
         int oy[NPW], ox[NPW];
 #pragma unroll
         for (int p = 0; p < NPW; ++p) {
             const int pix = (tp * NPW + p) * 16 + r16;
             oy[p] = pix / WO;
             ox[p] = pix % WO;
+        }
+        // byte offsets of the 9 taps (CIN >= 32) or of the lane's tap per K step (CIN == 8)
+        int off[NPW][CIN == 8 ? KSTEPS : 9];
+#pragma unroll
+        for (int p = 0; p < NPW; ++p) {
+            const bool top = oy[p] > 0, left = ox[p] > 0;
+            if constexpr (CIN == 8) {
+                const int base = in + ((2 * oy[p] - 1) * WI + 2 * ox[p] - 1) * 16;
+#pragma unroll
+                for (int ks = 0; ks < KSTEPS; ++ks)
+                    off[p][ks] = (tv[ks] && (top || !nt[ks]) && (left || !nl[ks])) ? base + dk[ks] : zoff;
+            } else {
+#pragma unroll
+                for (int kw = 0; kw < 3; ++kw) {
+                    const int b = in + loff<CIN, WI>(2 * oy[p] - 1, 2 * ox[p] + kw - 1, g);
+#pragma unroll
+                    for (int kh = 0; kh < 3; ++kh)
+                        off[p][kh * 3 + kw] = ((kh == 0 && !top) || (kw == 0 && !left)) ? zoff : b + kh * ROW;
+                }
+            }
         }
         f4 acc[MT][NPW];
 #pragma unroll
@@ -158,127 +222,156 @@ __device__ __forceinline__ void conv_phase(const char* in, char* out, const uint
             for (int p = 0; p < NPW; ++p) acc[m][p] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KSTEPS; ++ks) {
-            int t, chunk;
-            if constexpr (CIN >= 32) {
-                t = ks * 32 / CIN;
-                chunk = (ks * 32 % CIN) / 8 + g;
-            } else {  // CIN == 8: one tap per lane group
-                t = ks * 4 + g;
-                chunk = 0;
-            }
-            uint4 a[MT];
-#pragma unroll
-            for (int m = 0; m < MT; ++m)
-                a[m] = *(const uint4*)(w + (size_t)((tr * MT + m) * 16 + r16) * KSTRIDE + ks * 32 + g * 8);
-            const int kh = t / 3, kw = t - (t / 3) * 3;
             uint4 b[NPW];
 #pragma unroll
             for (int p = 0; p < NPW; ++p) {
-                const int iy = 2 * oy[p] + kh - 1, ix = 2 * ox[p] + kw - 1;
-                const bool ok = t < 9 && iy >= 0 && ix >= 0;
-                b[p] = ok ? *(const uint4*)(in + loff<CIN>(iy * WI + ix, chunk)) : uint4{0u, 0u, 0u, 0u};
+                if constexpr (CIN == 8) {
+                    b[p] = lds16(smem, off[p][ks]);
+                } else {
+                    // K step ks covers channels [(ks*32) % CIN, +32) of tap (ks*32) / CIN;
+                    // chunk (c0 / 8 + g) ^ swz = (g ^ swz) ^ (c0 / 8): an XOR of the byte offset
+                    const int t = ks * 32 / CIN, c0 = ks * 32 % CIN;
+                    b[p] = lds16(smem, off[p][t] ^ (c0 / 8 * 16));
+                }
             }
 #pragma unroll
             for (int m = 0; m < MT; ++m)
 #pragma unroll
-                for (int p = 0; p < NPW; ++p) mma(acc[m][p], a[m], b[p]);
+                for (int p = 0; p < NPW; ++p) mma(acc[m][p], A[ks][m], b[p]);
         }
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             const int ch = (tr * MT + m) * 16 + g * 4;
-            const float* bg = opaque(bias_g);
-            const float bias[4] = {bg[ch], bg[ch + 1], bg[ch + 2], bg[ch + 3]};
 #pragma unroll
-            for (int p = 0; p < NPW; ++p) lds_store4<COUT>(out, oy[p] * WO + ox[p], ch, acc[m][p], bias, true);
+            for (int p = 0; p < NPW; ++p)
+                lds_store4<COUT, WO>(smem, out, oy[p], ox[p], ch, acc[m][p], bias[m], true);
         }
     }
 }
 
 // Stride-2 3x3 transposed convolution over all four output phases, LDS ->
 // LDS, bias + ReLU (D3, D2). Input = [in0 (C0 ch) | in1 (C1 ch)] at HI x WI;
-// GEMM pixel (a, b) gathers its neighbours (a + di, b + dj) and feeds the 9
-// (phase, neighbour) weight blocks, pack [q][COUT][C0 + C1].
-template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW>
-__device__ __forceinline__ void pairs_phase(const char* in0, const char* in1, char* out, const uint16_t* wp,
-                                            const float* bias_g) {
-    constexpr int CIN = C0 + C1, PB = HI * WI / 16, RB = COUT / 16, KSN = CIN / 32;
+// GEMM pixel (a, b) gathers its neighbours (a + di, b + dj) and feeds the
+// (phase, neighbour) weight blocks, pack [q][COUT][C0 + C1]. The 9 blocks
+// are split into two sets of whole phases, SET 0 = phases 0-2 (blocks
+// 0-4) and SET 1 = phase 3 (blocks 5-8), so that a wave loads only the
+// weights of its set and of its row blocks into registers (the weights are
+// read from L2 and their bandwidth bounds these layers). Within a phase the
+// accumulation order is the layer kernel's: K step, then block.
+template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW, int SET>
+__device__ __forceinline__ void pairs_set(char* smem, int in0, int in1, int out, int zoff, const uint16_t* wp,
+                                          const float* bias_g, int tr, int tp0, int tp_step) {
+    constexpr int CIN = C0 + C1, PB = HI * WI / 16, KSN = CIN / 32;
     constexpr int WO = 2 * WI;
-    constexpr int TR = RB / MT, TP = PB / NPW;
-    static_assert(RB % MT == 0 && PB % NPW == 0 && C0 % 32 == 0 && C1 % 32 == 0, "tiles cover the layer");
-    static_assert(C1 == 0 || C1 == C0, "both sources share one LDS layout");
-    const int tid = opaque_tid();
-    const int lane = tid & 63, wave = tid >> 6;
+    constexpr int TP = PB / NPW;
+    constexpr int ROW = WI * C0 * 2;
+    constexpr int NSRC = C1 > 0 ? 2 : 1;
+    constexpr int Q0 = SET ? 5 : 0, NQ = SET ? 4 : 5;   // weight blocks of the set
+    constexpr int PH0 = SET ? 3 : 0, NPH = SET ? 1 : 3; // its phases
+    constexpr int NNB = SET ? 4 : 3;                    // neighbours it reads
+    const int lane = opaque_tid() & 63;
     const int g = lane >> 4, r16 = lane & 15;
-    for (int tile = wave; tile < TR * TP; tile += FW) {
-        const int tr = tile % TR, tp = tile / TR;
-        const uint16_t* w = opaque(wp);
+    const uint16_t* w = opaque(wp);
+    uint4 A[KSN][NQ][MT];
+#pragma unroll
+    for (int ks = 0; ks < KSN; ++ks)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                A[ks][q][m] =
+                    *(const uint4*)(w + (size_t)((Q0 + q) * COUT + (tr * MT + m) * 16 + r16) * CIN + ks * 32 + g * 8);
+    const float* bg = opaque(bias_g);
+    float bias[MT][4];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias[m][e] = bg[(tr * MT + m) * 16 + g * 4 + e];
+    for (int tp = tp0; tp < TP; tp += tp_step) {
         int ia[NPW], ib[NPW];
+        int off[NPW][NSRC][4];
 #pragma unroll
         for (int p = 0; p < NPW; ++p) {
             const int pix = (tp * NPW + p) * 16 + r16;
             ia[p] = pix / WI;
             ib[p] = pix % WI;
-        }
-        f4 acc[4][MT][NPW];
+            const bool down = ia[p] + 1 < HI, right = ib[p] + 1 < WI;
 #pragma unroll
-        for (int ph = 0; ph < 4; ++ph)
+            for (int s = 0; s < NSRC; ++s)
+#pragma unroll
+                for (int dj = 0; dj < 2; ++dj) {
+                    const int b = (s ? in1 : in0) + loff<C0, WI>(ia[p], ib[p] + dj, g);
+                    off[p][s][dj] = (dj && !right) ? zoff : b;
+                    off[p][s][2 + dj] = ((dj && !right) || !down) ? zoff : b + ROW;
+                }
+        }
+        f4 acc[NPH][MT][NPW];
+#pragma unroll
+        for (int ph = 0; ph < NPH; ++ph)
 #pragma unroll
             for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int p = 0; p < NPW; ++p) acc[ph][m][p] = f4{0.f, 0.f, 0.f, 0.f};
-        // K steps stay rolled: unrolled, the 9 weight loads of every step are
-        // hoisted together and overflow the register file
-#pragma unroll 1
+#pragma unroll
         for (int ks = 0; ks < KSN; ++ks) {
-            const bool second = ks * 32 >= C0;
-            const char* src0 = second ? in1 : in0;
-            const int chunk = (second ? (ks * 32 - C0) / 8 : ks * 4) + g;
-            uint4 bv[4][NPW];
+            const int s = ks * 32 >= C0 ? 1 : 0;
+            const int c0 = ks * 32 - s * C0;  // first channel of the step within its source
+            uint4 bv[NNB][NPW];
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) {
-                const int di = nb >> 1, dj = nb & 1;
+            for (int nb = 0; nb < NNB; ++nb)
 #pragma unroll
-                for (int p = 0; p < NPW; ++p) {
-                    const int y = ia[p] + di, x = ib[p] + dj;
-                    const bool ok = y < HI && x < WI;
-                    bv[nb][p] = ok ? *(const uint4*)(src0 + loff<C0>(y * WI + x, chunk)) : uint4{0u, 0u, 0u, 0u};
-                }
-            }
+                for (int p = 0; p < NPW; ++p) bv[nb][p] = lds16(smem, off[p][s][nb] ^ (c0 / 8 * 16));
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                const int ph = pair_phase(q), nb = pair_nb(q);
+            for (int q = 0; q < NQ; ++q) {
+                const int ph = pair_phase(Q0 + q) - PH0, nb = pair_nb(Q0 + q);
 #pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    const int row = q * COUT + (tr * MT + m) * 16 + r16;
-                    const uint4 a = *(const uint4*)(w + (size_t)row * CIN + ks * 32 + g * 8);
+                for (int m = 0; m < MT; ++m)
 #pragma unroll
-                    for (int p = 0; p < NPW; ++p) mma(acc[ph][m][p], a, bv[nb][p]);
-                }
+                    for (int p = 0; p < NPW; ++p) mma(acc[ph][m][p], A[ks][q][m], bv[nb][p]);
             }
         }
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             const int ch = (tr * MT + m) * 16 + g * 4;
-            const float* bg = opaque(bias_g);
-            const float bias[4] = {bg[ch], bg[ch + 1], bg[ch + 2], bg[ch + 3]};
 #pragma unroll
-            for (int ph = 0; ph < 4; ++ph)
+            for (int ph = 0; ph < NPH; ++ph)
 #pragma unroll
                 for (int p = 0; p < NPW; ++p) {
-                    const int opix = (2 * ia[p] + (ph >> 1)) * WO + 2 * ib[p] + (ph & 1);
-                    lds_store4<COUT>(out, opix, ch, acc[ph][m][p], bias, true);
+                    const int P = PH0 + ph;
+                    lds_store4<COUT, WO>(smem, out, 2 * ia[p] + (P >> 1), 2 * ib[p] + (P & 1), ch, acc[ph][m][p],
+                                         bias[m], true);
                 }
         }
     }
+}
+
+// Work split of a transposed-convolution layer: 2 * TR groups (row-block
+// group x set), rotated by workgroup so that CUs start on different weights.
+template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW>
+__device__ __forceinline__ void pairs_phase(char* smem, int in0, int in1, int out, int zoff, const uint16_t* wp,
+                                            const float* bias_g) {
+    constexpr int PB = HI * WI / 16, RB = COUT / 16, TR = RB / MT, NG = 2 * TR;
+    static_assert(RB % MT == 0 && PB % NPW == 0 && FW % NG == 0 && C0 % 32 == 0 && C1 % 32 == 0,
+                  "tiles cover the layer");
+    static_assert(C1 == 0 || C1 == C0, "both sources share one LDS layout");
+    const int wave = opaque_tid() >> 6;
+    const int gid = (wave + blockIdx.x) % NG;
+    const int tr = gid >> 1, set = gid & 1;
+    const int tp0 = wave / NG, step = FW / NG;
+    if (set == 0)
+        pairs_set<HI, WI, C0, C1, COUT, MT, NPW, 0>(smem, in0, in1, out, zoff, wp, bias_g, tr, tp0, step);
+    else
+        pairs_set<HI, WI, C0, C1, COUT, MT, NPW, 1>(smem, in0, in1, out, zoff, wp, bias_g, tr, tp0, step);
 }
 
 // D1: transposed convolution [u2 | h1] (32 + 32 channels at HI x WI) -> 3
 // channels, linear, float32 to global. Merged rows r = phase * 3 + co (12 of
 // 16 used), K = neighbour * 64 + c, pack [16][256].
 template <int HI, int WI, int NPW>
-__device__ __forceinline__ void d1_phase(const char* u2, const char* h1, float* ym, const uint16_t* wp,
+__device__ __forceinline__ void d1_phase(char* smem, int u2, int h1, int zoff, float* ym, const uint16_t* wp,
                                          const float* bias_g, bool relu) {
     constexpr int PB = HI * WI / 16, WO = 2 * WI, TP = PB / NPW;
+    constexpr int ROW = WI * 64;
     static_assert(PB % NPW == 0, "tiles cover the layer");
     const int tid = opaque_tid();
     const int lane = tid & 63, wave = tid >> 6;
@@ -287,6 +380,7 @@ __device__ __forceinline__ void d1_phase(const char* u2, const char* h1, float* 
     const uint16_t* w = opaque(wp);
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) a[ks] = *(const uint4*)(w + (size_t)r16 * 256 + ks * 32 + g * 8);
+    const float* bg = opaque(bias_g);
     float bias[4];
     int rph[4], rco[4];
 #pragma unroll
@@ -294,29 +388,35 @@ __device__ __forceinline__ void d1_phase(const char* u2, const char* h1, float* 
         const int r = g * 4 + e;
         rph[e] = r / 3;
         rco[e] = r - (r / 3) * 3;
-        bias[e] = r < 12 ? bias_g[rco[e]] : 0.0f;
+        bias[e] = r < 12 ? bg[rco[e]] : 0.0f;
     }
     for (int tp = wave; tp < TP; tp += FW) {
         int ia[NPW], ib[NPW];
+        int off[NPW][4];  // neighbours of the pixel in u2; h1 is at h1 - u2 further on
 #pragma unroll
         for (int p = 0; p < NPW; ++p) {
             const int pix = (tp * NPW + p) * 16 + r16;
             ia[p] = pix / WI;
             ib[p] = pix % WI;
+            const bool down = ia[p] + 1 < HI, right = ib[p] + 1 < WI;
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj) {
+                const int b = loff<32, WI>(ia[p], ib[p] + dj, g);
+                off[p][dj] = (dj && !right) ? -1 : b;
+                off[p][2 + dj] = ((dj && !right) || !down) ? -1 : b + ROW;
+            }
         }
         f4 acc[NPW];
 #pragma unroll
         for (int p = 0; p < NPW; ++p) acc[p] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) {
-            const int nb = ks >> 1, di = nb >> 1, dj = nb & 1;
-            const char* src = (ks & 1) ? h1 : u2;
+            const int nb = ks >> 1;
+            const int src = (ks & 1) ? h1 : u2;
 #pragma unroll
             for (int p = 0; p < NPW; ++p) {
-                const int y = ia[p] + di, x = ib[p] + dj;
-                const bool ok = y < HI && x < WI;
-                const uint4 b = ok ? *(const uint4*)(src + loff<32>(y * WI + x, g)) : uint4{0u, 0u, 0u, 0u};
-                mma(acc[p], a[ks], b);
+                const int o = off[p][nb];
+                mma(acc[p], a[ks], lds16(smem, o < 0 ? zoff : src + o));
             }
         }
 #pragma unroll
@@ -345,45 +445,45 @@ template <int H, int W>
 __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a) {
     extern __shared__ __align__(16) char smem[];
     constexpr int HW = H * W;
-    char* R0 = smem;
-    char* R1 = smem + 16 * HW;
-    char* R2 = smem + 24 * HW;
-    char* R3 = smem + 32 * HW;
+    constexpr int R0 = 0, R1 = 16 * HW, R2 = 24 * HW, R3 = 32 * HW, ZO = 36 * HW;
     char* slot = a.scratch + (size_t)blockIdx.x * (16 * HW);
     // pixel blocks per wave: enough tiles for 8 waves at both map sizes
-    constexpr int E1N = (HW / 64) >= 8 * 4 * 2 ? 4 : 2;     // E1: 2 row blocks x PB = HW/64
-    constexpr int E2N = (HW / 256) >= 4 * 4 ? 4 : 1;        // E2: 2 pairs of row blocks x PB = HW/256
-    constexpr int E3M = (HW / 1024) >= 4 ? 2 : 1;           // E3: 8 row blocks x PB = HW/1024
-    constexpr int E3N = (HW / 1024) >= 4 ? 2 : 1;
-    constexpr int D3N = (HW / 1024) >= 4 ? 2 : 1;           // D3: 4 row blocks x PB = HW/1024
-    constexpr int D2N = (HW / 256) >= 16 ? 4 : 1;           // D2: 2 row blocks x PB = HW/256
+    // tiles: a wave owns one group of row blocks (MT blocks of 16) per layer and
+    // walks pixel tiles of NPW blocks; chosen so that 8 waves have work and
+    // few waves load the same weights
+    constexpr int E1N = (HW / 64) >= 8 * 4 * 2 ? 4 : 2;     // E1: 2 row blocks (one group), PB = HW/64
+    constexpr int E2N = (HW / 256) >= 8 ? 4 : 1;            // E2: 4 groups of 1, PB = HW/256
+    constexpr int E3N = (HW / 1024) >= 4 ? 4 : 1;           // E3: 8 groups of 1, PB = HW/1024
+    constexpr int D3N = (HW / 1024) >= 4 ? 4 : 1;           // D3: 4 groups x 2 sets, PB = HW/1024
+    constexpr int D2N = (HW / 256) >= 16 ? 4 : 1;           // D2: 2 groups x 2 sets, PB = HW/256
     constexpr int D1N = (HW / 64) >= 8 * 4 ? 4 : 2;         // D1: PB = HW/64
+    if (threadIdx.x < kZeroBytes / 16) *(uint4*)(smem + ZO + 16 * threadIdx.x) = uint4{0u, 0u, 0u, 0u};
     for (int m = blockIdx.x; m < a.nmaps; m += gridDim.x) {
         const float* xm = a.x + (a.x_off ? a.x_off[m] : (long)m * HW * 7);
         float* ym = a.y + (a.y_off ? a.y_off[m] : (long)m * HW * 3);
-        stage_x<H, W>(R1, xm);
+        stage_x<H, W>(smem, R1, xm);
         __syncthreads();
-        conv_phase<H, W, 8, 32, 2, E1N>(R1, R0, a.w[0], a.b[0]);
+        conv_phase<H, W, 8, 32, 2, E1N>(smem, R1, R0, ZO, a.w[0], a.b[0]);
         __syncthreads();
-        copy_out(slot, R0, 16 * HW);
-        conv_phase<H / 2, W / 2, 32, 64, 2, E2N>(R0, R1, a.w[1], a.b[1]);
+        copy_out(slot, smem + R0, 16 * HW);
+        conv_phase<H / 2, W / 2, 32, 64, 1, E2N>(smem, R0, R1, ZO, a.w[1], a.b[1]);
         __syncthreads();
-        conv_phase<H / 4, W / 4, 64, 128, E3M, E3N>(R1, R3, a.w[2], a.b[2]);
+        conv_phase<H / 4, W / 4, 64, 128, 1, E3N>(smem, R1, R3, ZO, a.w[2], a.b[2]);
         __syncthreads();
-        pairs_phase<H / 8, W / 8, 128, 0, 64, 1, D3N>(R3, nullptr, R2, a.w[3], a.b[3]);
+        pairs_phase<H / 8, W / 8, 128, 0, 64, 1, D3N>(smem, R3, R3, R2, ZO, a.w[3], a.b[3]);
         __syncthreads();
-        pairs_phase<H / 4, W / 4, 64, 64, 32, 1, D2N>(R2, R1, R0, a.w[4], a.b[4]);
+        pairs_phase<H / 4, W / 4, 64, 64, 32, 1, D2N>(smem, R2, R1, R0, ZO, a.w[4], a.b[4]);
         __syncthreads();
-        copy_in(R1, slot, 16 * HW);
+        copy_in(smem + R1, slot, 16 * HW);
         __syncthreads();
-        d1_phase<H / 2, W / 2, D1N>(R0, R1, ym, a.w[5], a.b[5], a.final_relu != 0);
+        d1_phase<H / 2, W / 2, D1N>(smem, R0, R1, ZO, ym, a.w[5], a.b[5], a.final_relu != 0);
         __syncthreads();
     }
 }
 
 template <int H, int W>
 drc_status launch_fused(const FusedArgs& a, int grid, hipStream_t s) {
-    const int lds = 36 * H * W;
+    const int lds = 36 * H * W + kZeroBytes;
     auto kern = cae_fused_forward_kernel<H, W>;
     if (lds > 64 * 1024) {
         if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
