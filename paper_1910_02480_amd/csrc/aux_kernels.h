@@ -140,6 +140,22 @@ static __global__ void l1_final_kernel(const double* partial, int nparts, long c
     if (threadIdx.x == 0) loss[0] = (float)(red[0] / (double)count);
 }
 
+// Reorders a BF16 weight pack [rows][ksteps * 32] into MFMA fragment order:
+// fragment (row block rb, K step ks) is 64 lanes x 16 bytes, lane g * 16 + r
+// holding row 16 rb + r, K elements [32 ks + 8 g, +8). One wave then loads a
+// whole fragment as 1 KB of contiguous memory.
+static __global__ void frag_order_kernel(const uint4* src, uint4* dst, int rows, int ksteps) {
+    const long total = (long)rows * ksteps * 4;
+    for (long u = blockIdx.x * (long)blockDim.x + threadIdx.x; u < total; u += (long)gridDim.x * blockDim.x) {
+        const int lane = (int)(u & 63);
+        const long f = u >> 6;
+        const int ks = (int)(f % ksteps);
+        const long rb = f / ksteps;
+        const int g = lane >> 4, r = lane & 15;
+        dst[u] = src[(rb * 16 + r) * (ksteps * 4) + ks * 4 + g];
+    }
+}
+
 // ------------------------------------------------------------------ bias gradient
 // Column sums of a contiguous [npix][C] tensor (bias gradients), in two
 // fixed-order stages. Stage 1 views the tensor as a flat array read with

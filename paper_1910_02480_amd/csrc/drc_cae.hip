@@ -154,6 +154,7 @@ extern "C" drc_status drc_cae_create(const drc_cae_desc* desc, drc_cae** out) {
             h->wb_bytes[l] = (size_t)gb.nblk * gb.rows_pad * gb.kstride * prec_esize(h->prec);
             ok = alloc(&h->wb[l], h->wb_bytes[l]);
         }
+        if (ok && h->prec == P_BF16) ok = alloc(&h->wfrag[l], h->wf_bytes[l]);
         if (ok && h->prec == P_FP8) {  // float32 packs for the calibration forward
             GemmGeom gc = gemm_geom(l, false, P_F32);
             ok = alloc(&h->wcal[l], (size_t)gc.nblk * gc.rows_pad * gc.kstride * 4);
@@ -178,6 +179,7 @@ extern "C" void drc_cae_destroy(drc_cae* h) {
         if (h->wf[l]) (void)hipFree(h->wf[l]);
         if (h->wb[l]) (void)hipFree(h->wb[l]);
         if (h->wcal[l]) (void)hipFree(h->wcal[l]);
+        if (h->wfrag[l]) (void)hipFree(h->wfrag[l]);
     }
     if (h->bias) (void)hipFree(h->bias);
     if (h->scales) (void)hipFree(h->scales);
@@ -510,6 +512,15 @@ static drc_status pack_all(drc_cae* h, const float* d_params, hipStream_t s) {
             const long total = (long)g.nblk * g.rows_pad * g.kstride;
             const int blocks = (int)std::min(1024L, (total + 255) / 256);
             hipLaunchKernelGGL(pack_weights_kernel, dim3(blocks), dim3(256), 0, s, a);
+        }
+    }
+    if (h->prec == P_BF16) {
+        for (int l = 0; l < 6; ++l) {
+            GemmGeom g = gemm_geom(l, false, P_BF16);
+            const int rows = g.nblk * g.rows_pad, ksteps = g.kstride / 32;
+            const long units = (long)rows * ksteps * 4;
+            hipLaunchKernelGGL(frag_order_kernel, dim3((int)std::min(1024L, (units + 255) / 256)), dim3(256), 0, s,
+                               (const uint4*)h->wf[l], (uint4*)h->wfrag[l], rows, ksteps);
         }
     }
     TRY(check_launch("set_params/pack"));

@@ -45,7 +45,7 @@ struct FusedArgs {
     int nmaps;
     const long* x_off;   // element offset of each map (null: packed)
     const long* y_off;
-    const uint16_t* w[6];  // forward packs (layer path layout)
+    const uint16_t* w[6];  // forward packs in MFMA fragment order
     const float* b[6];
     char* scratch;       // one h1 slot of 16 H W bytes per workgroup
     int final_relu;
@@ -142,8 +142,8 @@ __device__ __forceinline__ void stage_x(char* smem, int xs, const float* xm) {
     }
 }
 
-// Stride-2 3x3 convolution, LDS -> LDS, bias + ReLU (E1, E2, E3). Pack
-// [COUT][KSTEPS*32], k = tap * CIN + c. Wave w owns the row blocks of group
+// Stride-2 3x3 convolution, LDS -> LDS, bias + ReLU (E1, E2, E3). Weights:
+// the layer pack [COUT][KSTEPS*32] (k = tap * CIN + c) in fragment order. Wave w owns the row blocks of group
 // w % TR for the whole layer and loads their weights (its A panel) into
 // registers once; it then walks the pixel tiles w / TR, w / TR + FW / TR, ...
 // (NPW blocks of 16 consecutive output pixels each). Taps that fall outside
@@ -153,7 +153,7 @@ __device__ __forceinline__ void conv_phase(char* smem, int in, int out, int zoff
                                            const float* bias_g) {
     constexpr int HO = HI / 2, WO = WI / 2;
     constexpr int PB = HO * WO / 16, RB = COUT / 16;
-    constexpr int KSTEPS = (9 * CIN + 31) / 32, KSTRIDE = KSTEPS * 32;
+    constexpr int KSTEPS = (9 * CIN + 31) / 32;
     constexpr int TR = RB / MT, TP = PB / NPW;
     constexpr int ROW = WI * CIN * 2;  // bytes per input row
     static_assert(RB % MT == 0 && PB % NPW == 0 && FW % TR == 0, "tiles cover the layer");
@@ -167,7 +167,7 @@ __device__ __forceinline__ void conv_phase(char* smem, int in, int out, int zoff
     for (int ks = 0; ks < KSTEPS; ++ks)
 #pragma unroll
         for (int m = 0; m < MT; ++m)
-            A[ks][m] = *(const uint4*)(w + (size_t)((tr * MT + m) * 16 + r16) * KSTRIDE + ks * 32 + g * 8);
+            A[ks][m] = *(const uint4*)(w + ((size_t)((tr * MT + m) * KSTEPS + ks) * 64 + lane) * 8);
     const float* bg = opaque(bias_g);
     float bias[MT][4];
 #pragma unroll
@@ -252,7 +252,8 @@ __device__ __forceinline__ void conv_phase(char* smem, int in, int out, int zoff
 // Stride-2 3x3 transposed convolution over all four output phases, LDS ->
 // LDS, bias + ReLU (D3, D2). Input = [in0 (C0 ch) | in1 (C1 ch)] at HI x WI;
 // GEMM pixel (a, b) gathers its neighbours (a + di, b + dj) and feeds the
-// (phase, neighbour) weight blocks, pack [q][COUT][C0 + C1]. The 9 blocks
+// (phase, neighbour) weight blocks (pack [q][COUT][C0 + C1], fragment
+// order). The 9 blocks
 // are split into two sets of whole phases, SET 0 = phases 0-2 (blocks
 // 0-4) and SET 1 = phase 3 (blocks 5-8), so that a wave loads only the
 // weights of its set and of its row blocks into registers (the weights are
@@ -280,7 +281,7 @@ __device__ __forceinline__ void pairs_set(char* smem, int in0, int in1, int out,
 #pragma unroll
             for (int m = 0; m < MT; ++m)
                 A[ks][q][m] =
-                    *(const uint4*)(w + (size_t)((Q0 + q) * COUT + (tr * MT + m) * 16 + r16) * CIN + ks * 32 + g * 8);
+                    *(const uint4*)(w + ((size_t)(((Q0 + q) * (COUT / 16) + tr * MT + m) * KSN + ks) * 64 + lane) * 8);
     const float* bg = opaque(bias_g);
     float bias[MT][4];
 #pragma unroll
@@ -366,7 +367,7 @@ __device__ __forceinline__ void pairs_phase(char* smem, int in0, int in1, int ou
 
 // D1: transposed convolution [u2 | h1] (32 + 32 channels at HI x WI) -> 3
 // channels, linear, float32 to global. Merged rows r = phase * 3 + co (12 of
-// 16 used), K = neighbour * 64 + c, pack [16][256].
+// 16 used), K = neighbour * 64 + c, pack [16][256] in fragment order.
 template <int HI, int WI, int NPW>
 __device__ __forceinline__ void d1_phase(char* smem, int u2, int h1, int zoff, float* ym, const uint16_t* wp,
                                          const float* bias_g, bool relu) {
@@ -379,7 +380,7 @@ __device__ __forceinline__ void d1_phase(char* smem, int u2, int h1, int zoff, f
     uint4 a[8];
     const uint16_t* w = opaque(wp);
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) a[ks] = *(const uint4*)(w + (size_t)r16 * 256 + ks * 32 + g * 8);
+    for (int ks = 0; ks < 8; ++ks) a[ks] = *(const uint4*)(w + ((size_t)ks * 64 + lane) * 8);
     const float* bg = opaque(bias_g);
     float bias[4];
     int rph[4], rco[4];
@@ -525,7 +526,7 @@ drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int
     a.x_off = x_off;
     a.y_off = y_off;
     for (int l = 0; l < 6; ++l) {
-        a.w[l] = (const uint16_t*)h->wf[l];
+        a.w[l] = (const uint16_t*)h->wfrag[l];
         a.b[l] = h->bias + bias_slot(l);
     }
     a.scratch = (char*)scratch;

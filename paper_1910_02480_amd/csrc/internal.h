@@ -36,6 +36,7 @@ struct drc_cae {
     void* wf[6] = {};      // forward packs
     void* wb[6] = {};      // backward-data (transposed) packs
     void* wcal[6] = {};    // float32 forward packs of FP8 handles (calibration)
+    void* wfrag[6] = {};   // BF16 handles: forward packs in MFMA fragment order (fused forward)
     size_t wf_bytes[6] = {}, wb_bytes[6] = {};
     float* bias = nullptr; // float32 biases, layer l at bias_slot(l)
     float* scales = nullptr;   // [0..5] weight scales, [6..9] activation scales (FP8)
