@@ -207,12 +207,24 @@ extern "C" void drc_cae_plan_destroy(drc_plan* p) {
 // Enqueue the six persistent layer launches of a frame.
 static drc_status plan_enqueue(drc_plan* p, const float* x, float* y, char* ws, hipStream_t s) {
     drc_cae* h = p->h;
-    std::vector<FwdClass> fc(p->cls.size());
-    long best = -1;
-    int big = 0;
-    for (size_t c = 0; c < p->cls.size(); ++c) {
+    const bool prof = h->prof;
+    h->prof = false;
+    // BF16 classes the whole-network kernel is built for run through it, one
+    // launch per class; the rest share one persistent launch per layer.
+    std::vector<FwdClass> fc;
+    std::vector<int> from;
+    drc_status st = DRC_OK;
+    for (size_t c = 0; c < p->cls.size() && st == DRC_OK; ++c) {
         const PlanClass& pc = p->cls[c];
-        FwdClass& f = fc[c];
+        const long* xo = (const long*)(p->d_tables + pc.dev_xoff);
+        const long* yo = (const long*)(p->d_tables + pc.dev_yoff);
+        if (h->fused && h->prec == P_BF16 && fused_forward_size(pc.H, pc.W)) {
+            // the class's h1 region (n maps) holds the per-workgroup slots
+            st = fused_forward(h, x, y, pc.n, pc.H, pc.W, xo, yo, ws + pc.act[0],
+                               (size_t)pc.n * 16 * pc.H * pc.W, s);
+            continue;
+        }
+        FwdClass f;
         memset(&f, 0, sizeof f);
         f.b.x = x;
         f.b.y = y;
@@ -221,27 +233,31 @@ static drc_status plan_enqueue(drc_plan* p, const float* x, float* y, char* ws, 
         f.b.h3 = ws + pc.act[2];
         f.b.u3 = ws + pc.act[3];
         f.b.u2 = ws + pc.act[4];
-        f.b.x_off = (const long*)(p->d_tables + pc.dev_xoff);
-        f.b.y_off = (const long*)(p->d_tables + pc.dev_yoff);
+        f.b.x_off = xo;
+        f.b.y_off = yo;
         f.n = pc.n;
         f.H = pc.H;
         f.W = pc.W;
         for (int l = 0; l < 6; ++l) f.tile_px[l] = pc.tile_px[l];
-        if (pc.flops > best) {
-            best = pc.flops;
-            big = (int)c;
-        }
+        fc.push_back(f);
+        from.push_back((int)c);
     }
-    // The GEMM tile (NPW) is shared by the classes of a launch: take the
-    // tuned choice of the class with the most work.
-    for (int l = 0; l < 6; ++l) fc[0].npw[l] = p->cls[big].npw[l];
-    const bool prof = h->prof;
-    h->prof = false;
-    drc_status st = DRC_ERR_STATE;
-    const int nc = (int)fc.size();
-    if (h->prec == P_F32) st = forward_classes<P_F32>(h, h->wf, fc.data(), nc, 0, 5, s);
-    if (h->prec == P_BF16) st = forward_classes<P_BF16>(h, h->wf, fc.data(), nc, 0, 5, s);
-    if (h->prec == P_FP8) st = forward_classes<P_FP8>(h, h->wf, fc.data(), nc, 0, 5, s);
+    if (st == DRC_OK && !fc.empty()) {
+        // The GEMM tile (NPW) is shared by the classes of a launch: take the
+        // tuned choice of the class with the most work.
+        long best = -1;
+        int big = 0;
+        for (size_t k = 0; k < from.size(); ++k)
+            if (p->cls[from[k]].flops > best) {
+                best = p->cls[from[k]].flops;
+                big = from[k];
+            }
+        for (int l = 0; l < 6; ++l) fc[0].npw[l] = p->cls[big].npw[l];
+        const int nc = (int)fc.size();
+        if (h->prec == P_F32) st = forward_classes<P_F32>(h, h->wf, fc.data(), nc, 0, 5, s);
+        if (h->prec == P_BF16) st = forward_classes<P_BF16>(h, h->wf, fc.data(), nc, 0, 5, s);
+        if (h->prec == P_FP8) st = forward_classes<P_FP8>(h, h->wf, fc.data(), nc, 0, 5, s);
+    }
     h->prof = prof;
     return st;
 }
