@@ -136,14 +136,15 @@ drc_status drc_cae_set_recompute(drc_cae* h, int on);
 drc_status drc_cae_saved_size(const drc_cae* h, int n, int H, int W, size_t* bytes,
                               int64_t offsets[5]);
 
-/* Forward path for BF16 inference (d_saved == NULL) on 32x32 and 64x64
- * maps (default 1). 1: one kernel runs the whole network per map with its
- * activations in LDS (HBM traffic is the FP32 input and output plus a 64 KB
- * per-workgroup staging slot of h1 at 64x64); 0: one kernel per layer with
- * activations in HBM. Both give bitwise equal outputs (same packs, K order
- * and rounding). Other precisions, sizes and saving forwards always run
- * layer by layer. Errors: DRC_ERR_INVALID_ARG for a NULL handle or on not
- * in {0, 1}. */
+/* Forward path of BF16 handles on 32x32 and 64x64 maps (default 1).
+ * 1: one kernel runs the whole network per map with its activations in LDS
+ * (HBM traffic is the FP32 input and output, one 64 KB staging copy of h1
+ * at 64x64, and the activations a saving forward must keep); the
+ * recompute of a training backward (h2 -> h3, u3, u2) runs the same way.
+ * 0: one kernel per layer with activations in HBM. Both give bitwise equal
+ * outputs and saved activations (same packs, K order and rounding). Other
+ * precisions and sizes always run layer by layer. Errors:
+ * DRC_ERR_INVALID_ARG for a NULL handle or on not in {0, 1}. */
 drc_status drc_cae_set_fused(drc_cae* h, int on);
 
 enum { DRC_WS_FORWARD = 1, DRC_WS_BACKWARD = 2, DRC_WS_STEP = 4, DRC_WS_CALIBRATE = 8, DRC_WS_AUTOTUNE = 16 };

@@ -49,7 +49,7 @@ class CAE:
         B.drc_cae_set_recompute(self.h, int(on))
 
     def set_fused(self, on: bool):
-        """BF16 inference forward of 32x32 / 64x64 maps in one kernel (default) or layer by layer."""
+        """BF16 forward (and training recompute) of 32x32 / 64x64 maps in one kernel (default) or layer by layer."""
         B.drc_cae_set_fused(self.h, int(on))
         self._ws.clear()
 

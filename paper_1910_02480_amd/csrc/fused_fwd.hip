@@ -47,7 +47,8 @@ struct FusedArgs {
     const long* y_off;
     const uint16_t* w[6];  // forward packs in MFMA fragment order
     const float* b[6];
-    char* scratch;       // one h1 slot of 16 H W bytes per workgroup
+    char* scratch;       // one h1 slot of 16 H W bytes per workgroup (when h1 is not saved)
+    char* save[5];       // optional: h1 h2 h3 u3 u2 of every map, plain NHWC BF16 (null = not kept)
     int final_relu;
 };
 
@@ -434,64 +435,112 @@ __device__ __forceinline__ void d1_phase(char* smem, int u2, int h1, int zoff, f
     }
 }
 
-// 16-byte copies of `bytes` between LDS and global (both 16-byte aligned).
-__device__ __forceinline__ void copy_out(char* dst, const char* lds, int bytes) {
-    for (int i = threadIdx.x; i < bytes / 16; i += FT) ((uint4*)dst)[i] = ((const uint4*)lds)[i];
+// Copies an LDS tensor (C channels, HI x WI, column-swizzled chunks) to a
+// plain NHWC tensor in global memory and back, 16 bytes per thread step:
+// global chunks are consecutive, the LDS side undoes / applies the swizzle.
+template <int C, int HI, int WI>
+__device__ __forceinline__ void copy_out(char* dst, const char* smem, int region) {
+    constexpr int CH = C / 8, N = HI * WI * CH;
+    for (int i = threadIdx.x; i < N; i += FT) {
+        const int pix = i / CH, j = i - pix * CH;
+        ((uint4*)dst)[i] = *(const uint4*)(smem + region + loff<C, WI>(pix / WI, pix % WI, j));
+    }
 }
-__device__ __forceinline__ void copy_in(char* lds, const char* src, int bytes) {
-    for (int i = threadIdx.x; i < bytes / 16; i += FT) ((uint4*)lds)[i] = ((const uint4*)src)[i];
+template <int C, int HI, int WI>
+__device__ __forceinline__ void copy_in(char* smem, int region, const char* src) {
+    constexpr int CH = C / 8, N = HI * WI * CH;
+    for (int i = threadIdx.x; i < N; i += FT) {
+        const int pix = i / CH, j = i - pix * CH;
+        *(uint4*)(smem + region + loff<C, WI>(pix / WI, pix % WI, j)) = ((const uint4*)src)[i];
+    }
 }
 
-template <int H, int W>
+// MID = false: the whole network, x -> y (h1 kept in a per-workgroup slot
+// or in save[0]; every non-null save[k] receives that activation).
+// MID = true: the recompute of a training backward, h2 (read from save[1])
+// -> h3, u3, u2 (written to save[2..4]); E1, E2 and D1 are skipped.
+template <int H, int W, bool MID>
 __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a) {
     extern __shared__ __align__(16) char smem[];
     constexpr int HW = H * W;
     constexpr int R0 = 0, R1 = 16 * HW, R2 = 24 * HW, R3 = 32 * HW, ZO = 36 * HW;
-    char* slot = a.scratch + (size_t)blockIdx.x * (16 * HW);
-    // pixel blocks per wave: enough tiles for 8 waves at both map sizes
     // tiles: a wave owns one group of row blocks (MT blocks of 16) per layer and
     // walks pixel tiles of NPW blocks; chosen so that 8 waves have work and
     // few waves load the same weights
     constexpr int E1N = (HW / 64) >= 8 * 4 * 2 ? 4 : 2;     // E1: 2 row blocks (one group), PB = HW/64
     constexpr int E2N = (HW / 256) >= 8 ? 4 : 1;            // E2: 4 groups of 1, PB = HW/256
     constexpr int E3N = (HW / 1024) >= 4 ? 4 : 1;           // E3: 8 groups of 1, PB = HW/1024
-    constexpr int D3N = (HW / 1024) >= 4 ? 4 : 1;           // D3: 4 groups x 2 sets, PB = HW/1024
-    constexpr int D2N = (HW / 256) >= 16 ? 4 : 1;           // D2: 2 groups x 2 sets, PB = HW/256
+    constexpr int D3N = (HW / 1024) >= 4 ? 2 : 1;           // D3: 4 groups x 2 sets, PB = HW/1024
+    constexpr int D2N = (HW / 256) >= 16 ? 2 : 1;           // D2: 2 groups x 2 sets, PB = HW/256
     constexpr int D1N = (HW / 64) >= 8 * 4 ? 4 : 2;         // D1: PB = HW/64
+    // per-map bytes of h1 h2 h3 u3 u2
+    constexpr long B1 = 16L * HW, B2 = 8L * HW, B3 = 4L * HW, B4 = 8L * HW, B5 = 16L * HW;
     if (threadIdx.x < kZeroBytes / 16) *(uint4*)(smem + ZO + 16 * threadIdx.x) = uint4{0u, 0u, 0u, 0u};
     for (int m = blockIdx.x; m < a.nmaps; m += gridDim.x) {
-        const float* xm = a.x + (a.x_off ? a.x_off[m] : (long)m * HW * 7);
-        float* ym = a.y + (a.y_off ? a.y_off[m] : (long)m * HW * 3);
-        stage_x<H, W>(smem, R1, xm);
-        __syncthreads();
-        conv_phase<H, W, 8, 32, 2, E1N>(smem, R1, R0, ZO, a.w[0], a.b[0]);
-        __syncthreads();
-        copy_out(slot, smem + R0, 16 * HW);
-        conv_phase<H / 2, W / 2, 32, 64, 1, E2N>(smem, R0, R1, ZO, a.w[1], a.b[1]);
-        __syncthreads();
-        conv_phase<H / 4, W / 4, 64, 128, 1, E3N>(smem, R1, R3, ZO, a.w[2], a.b[2]);
-        __syncthreads();
-        pairs_phase<H / 8, W / 8, 128, 0, 64, 1, D3N>(smem, R3, R3, R2, ZO, a.w[3], a.b[3]);
-        __syncthreads();
-        pairs_phase<H / 4, W / 4, 64, 64, 32, 1, D2N>(smem, R2, R1, R0, ZO, a.w[4], a.b[4]);
-        __syncthreads();
-        copy_in(smem + R1, slot, 16 * HW);
-        __syncthreads();
-        d1_phase<H / 2, W / 2, D1N>(smem, R0, R1, ZO, ym, a.w[5], a.b[5], a.final_relu != 0);
-        __syncthreads();
+        if constexpr (!MID) {
+            const float* xm = a.x + (a.x_off ? a.x_off[m] : (long)m * HW * 7);
+            float* ym = a.y + (a.y_off ? a.y_off[m] : (long)m * HW * 3);
+            char* slot = a.save[0] ? a.save[0] + m * B1 : a.scratch + (size_t)blockIdx.x * B1;
+            stage_x<H, W>(smem, R1, xm);
+            __syncthreads();
+            conv_phase<H, W, 8, 32, 2, E1N>(smem, R1, R0, ZO, a.w[0], a.b[0]);
+            __syncthreads();
+            copy_out<32, H / 2, W / 2>(slot, smem, R0);
+            conv_phase<H / 2, W / 2, 32, 64, 1, E2N>(smem, R0, R1, ZO, a.w[1], a.b[1]);
+            __syncthreads();
+            if (a.save[1]) copy_out<64, H / 4, W / 4>(a.save[1] + m * B2, smem, R1);
+            conv_phase<H / 4, W / 4, 64, 128, 1, E3N>(smem, R1, R3, ZO, a.w[2], a.b[2]);
+            __syncthreads();
+            if (a.save[2]) copy_out<128, H / 8, W / 8>(a.save[2] + m * B3, smem, R3);
+            pairs_phase<H / 8, W / 8, 128, 0, 64, 1, D3N>(smem, R3, R3, R2, ZO, a.w[3], a.b[3]);
+            __syncthreads();
+            if (a.save[3]) copy_out<64, H / 4, W / 4>(a.save[3] + m * B4, smem, R2);
+            pairs_phase<H / 4, W / 4, 64, 64, 32, 1, D2N>(smem, R2, R1, R0, ZO, a.w[4], a.b[4]);
+            __syncthreads();
+            if (a.save[4]) copy_out<32, H / 2, W / 2>(a.save[4] + m * B5, smem, R0);
+            copy_in<32, H / 2, W / 2>(smem, R1, slot);
+            __syncthreads();
+            d1_phase<H / 2, W / 2, D1N>(smem, R0, R1, ZO, ym, a.w[5], a.b[5], a.final_relu != 0);
+            __syncthreads();
+        } else {
+            copy_in<64, H / 4, W / 4>(smem, R1, a.save[1] + m * B2);
+            __syncthreads();
+            conv_phase<H / 4, W / 4, 64, 128, 1, E3N>(smem, R1, R3, ZO, a.w[2], a.b[2]);
+            __syncthreads();
+            copy_out<128, H / 8, W / 8>(a.save[2] + m * B3, smem, R3);
+            pairs_phase<H / 8, W / 8, 128, 0, 64, 1, D3N>(smem, R3, R3, R2, ZO, a.w[3], a.b[3]);
+            __syncthreads();
+            copy_out<64, H / 4, W / 4>(a.save[3] + m * B4, smem, R2);
+            pairs_phase<H / 4, W / 4, 64, 64, 32, 1, D2N>(smem, R2, R1, R0, ZO, a.w[4], a.b[4]);
+            __syncthreads();
+            copy_out<32, H / 2, W / 2>(a.save[4] + m * B5, smem, R0);
+            __syncthreads();
+        }
     }
 }
 
-template <int H, int W>
+template <int H, int W, bool MID>
 drc_status launch_fused(const FusedArgs& a, int grid, hipStream_t s) {
     const int lds = 36 * H * W + kZeroBytes;
-    auto kern = cae_fused_forward_kernel<H, W>;
+    auto kern = cae_fused_forward_kernel<H, W, MID>;
     if (lds > 64 * 1024) {
         if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
             return drc_fail(DRC_ERR_HIP, "fused forward: cannot raise the LDS limit to %d bytes", lds);
     }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(FT), lds, s, a);
     return check_launch("fused forward");
+}
+
+FusedArgs fused_args(const drc_cae* h, int n) {
+    FusedArgs a;
+    memset(&a, 0, sizeof a);
+    a.nmaps = n;
+    for (int l = 0; l < 6; ++l) {
+        a.w[l] = (const uint16_t*)h->wfrag[l];
+        a.b[l] = h->bias + bias_slot(l);
+    }
+    a.final_relu = h->desc.final_relu;
+    return a;
 }
 
 }  // namespace
@@ -505,35 +554,48 @@ int fused_forward_grid(const drc_cae* h, int n, int H, int W) {
     return std::max(1, std::min(n, h->num_cu * per_cu));
 }
 
-// Scratch bytes of one fused launch (one h1 slot per workgroup).
+// Scratch bytes of one fused launch (one h1 slot per workgroup) when h1 is not saved.
 size_t fused_forward_scratch(const drc_cae* h, int n, int H, int W) {
     return (size_t)fused_forward_grid(h, n, H, W) * 16 * H * W;
 }
 
 drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int W, const long* x_off,
-                         const long* y_off, void* scratch, size_t scratch_bytes, hipStream_t s) {
+                         const long* y_off, void* scratch, size_t scratch_bytes, hipStream_t s,
+                         char* const* save) {
     if (h->prec != P_BF16 || !fused_forward_size(H, W))
         return drc_fail(DRC_ERR_UNSUPPORTED, "fused forward: BF16 maps of 32x32 or 64x64 only");
     if (n < 1) return DRC_OK;
-    if (scratch_bytes < fused_forward_scratch(h, n, H, W))
+    FusedArgs a = fused_args(h, n);
+    if (save)
+        for (int k = 0; k < 5; ++k) a.save[k] = save[k];
+    if (!a.save[0] && scratch_bytes < fused_forward_scratch(h, n, H, W))
         return drc_fail(DRC_ERR_WORKSPACE, "fused forward: scratch %zu < %zu bytes", scratch_bytes,
                         fused_forward_scratch(h, n, H, W));
-    FusedArgs a;
-    memset(&a, 0, sizeof a);
     a.x = x;
     a.y = y;
-    a.nmaps = n;
     a.x_off = x_off;
     a.y_off = y_off;
-    for (int l = 0; l < 6; ++l) {
-        a.w[l] = (const uint16_t*)h->wfrag[l];
-        a.b[l] = h->bias + bias_slot(l);
-    }
     a.scratch = (char*)scratch;
-    a.final_relu = h->desc.final_relu;
     const int grid = fused_forward_grid(h, n, H, W);
     const long tok = prof_begin(h, PROF_FUSED, s);
-    drc_status st = (H == 64) ? launch_fused<64, 64>(a, grid, s) : launch_fused<32, 32>(a, grid, s);
+    drc_status st = (H == 64) ? launch_fused<64, 64, false>(a, grid, s) : launch_fused<32, 32, false>(a, grid, s);
+    prof_end(h, tok, s);
+    return st;
+}
+
+drc_status fused_recompute(drc_cae* h, int n, int H, int W, const void* h2, void* h3, void* u3, void* u2,
+                           hipStream_t s) {
+    if (h->prec != P_BF16 || !fused_forward_size(H, W))
+        return drc_fail(DRC_ERR_UNSUPPORTED, "fused recompute: BF16 maps of 32x32 or 64x64 only");
+    if (n < 1) return DRC_OK;
+    FusedArgs a = fused_args(h, n);
+    a.save[1] = (char*)h2;
+    a.save[2] = (char*)h3;
+    a.save[3] = (char*)u3;
+    a.save[4] = (char*)u2;
+    const int grid = fused_forward_grid(h, n, H, W);
+    const long tok = prof_begin(h, PROF_FUSED, s);
+    drc_status st = (H == 64) ? launch_fused<64, 64, true>(a, grid, s) : launch_fused<32, 32, true>(a, grid, s);
     prof_end(h, tok, s);
     return st;
 }

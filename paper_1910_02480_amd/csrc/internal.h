@@ -144,5 +144,10 @@ int default_npw(int prec, int layer, bool backward);
 bool fused_forward_size(int H, int W);
 int fused_forward_grid(const drc_cae* h, int n, int H, int W);
 size_t fused_forward_scratch(const drc_cae* h, int n, int H, int W);
+// save: null, or h1 h2 h3 u3 u2 destinations (plain NHWC, null entries skipped).
 drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int W, const long* x_off,
-                         const long* y_off, void* scratch, size_t scratch_bytes, hipStream_t s);
+                         const long* y_off, void* scratch, size_t scratch_bytes, hipStream_t s,
+                         char* const* save = nullptr);
+// h2 -> h3, u3, u2 (the layers a recomputing backward rebuilds), all plain NHWC.
+drc_status fused_recompute(drc_cae* h, int n, int H, int W, const void* h2, void* h3, void* u3, void* u2,
+                           hipStream_t s);

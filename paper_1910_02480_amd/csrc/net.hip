@@ -267,8 +267,17 @@ extern "C" drc_status drc_cae_forward(drc_cae* h, const float* d_x, float* d_y, 
     TRY(drc_cae_workspace_size(h, n, H, W, DRC_WS_FORWARD, &need));
     if (ws_bytes < need)
         return drc_fail(DRC_ERR_WORKSPACE, "forward: workspace %zu < %zu bytes", ws_bytes, need);
-    if (h->fused && h->prec == P_BF16 && !d_saved && fused_forward_size(H, W))
-        return fused_forward(h, d_x, d_y, n, H, W, nullptr, nullptr, d_ws, ws_bytes, (hipStream_t)stream);
+    if (h->fused && h->prec == P_BF16 && fused_forward_size(H, W)) {
+        char* save[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+        if (d_saved) {
+            size_t sb;
+            int64_t off[5];
+            TRY(drc_cae_saved_size(h, n, H, W, &sb, off));
+            for (int k = 0; k < 5; ++k)
+                if (off[k] >= 0) save[k] = (char*)d_saved + off[k];
+        }
+        return fused_forward(h, d_x, d_y, n, H, W, nullptr, nullptr, d_ws, ws_bytes, (hipStream_t)stream, save);
+    }
     ActSizes a = act_sizes(h->prec, n, H, W);
     char* ws = (char*)d_ws;
     void* act[5];
@@ -568,7 +577,10 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
 static drc_status recompute_acts(drc_cae* h, BwdBufs& b, int n, int H, int W, hipStream_t s) {
     FwdBufs f{nullptr, nullptr, const_cast<void*>(b.h1), const_cast<void*>(b.h2), b.ws + b.L.recomp[0],
               b.ws + b.L.recomp[1], b.ws + b.L.recomp[2], nullptr, nullptr};
-    TRY(forward_dispatch(h, f, n, H, W, 2, 4, s));
+    if (h->fused && h->prec == P_BF16 && fused_forward_size(H, W))
+        TRY(fused_recompute(h, n, H, W, b.h2, f.h3, f.u3, f.u2, s));
+    else
+        TRY(forward_dispatch(h, f, n, H, W, 2, 4, s));
     b.h3 = f.h3;
     b.u3 = f.u3;
     b.u2 = f.u2;
@@ -671,7 +683,14 @@ extern "C" drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, floa
     float* y = (float*)(ws + S.y);
     float* dy = (float*)(ws + S.dy);
     FwdBufs fb{d_x, y, act[0], act[1], act[2], act[3], act[4], nullptr, nullptr};
-    TRY(forward_dispatch(h, fb, n, H, W, 0, 5, s));
+    if (h->fused && h->prec == P_BF16 && fused_forward_size(H, W)) {
+        // one kernel; it writes the activations the backward reads
+        char* save[5];
+        for (int k = 0; k < 5; ++k) save[k] = off[k] >= 0 ? (char*)act[k] : nullptr;
+        TRY(fused_forward(h, d_x, y, n, H, W, nullptr, nullptr, nullptr, 0, s, save));
+    } else {
+        TRY(forward_dispatch(h, fb, n, H, W, 0, 5, s));
+    }
 
     // L1 loss (mean) and dL/dy; dy is stored as sign(y - t) and the 1/M
     // factor is applied once, to the parameter gradients.

@@ -59,3 +59,45 @@ def test_fused_final_relu_and_repeat(params):
     np.testing.assert_array_equal(a, c)
     np.testing.assert_array_equal(b, c[:5])
     assert (a >= 0).all()
+
+
+@pytest.mark.parametrize("H,recompute", [(64, False), (64, True), (32, False), (32, True)])
+def test_fused_saving_forward_and_backward_bitwise(params, H, recompute):
+    """A saving forward writes the same activations, and a backward (with or
+    without recompute, which also runs fused) the same gradients, as the
+    layer path."""
+    from paper_1910_02480_amd.cae import CAE
+    print(f"[fused-save] H={H} recompute={recompute}", flush=True)
+    n = 40
+    x = torch.from_numpy(synth.radiance_maps(n, H, H, seed=14)).to(DEV)
+    dy = torch.from_numpy(np.random.default_rng(15).standard_normal((n, H, H, 3)).astype(np.float32)).to(DEV)
+    out = {}
+    for fused in (True, False):
+        cae = CAE("bf16", torch.from_numpy(params).to(DEV), device=DEV, recompute=recompute)
+        cae.set_fused(fused)
+        saved, offsets = cae.saved_buffer(n, H, H)
+        saved.zero_()
+        y = cae.forward(x, saved=saved)
+        dp, _ = cae.backward(x, dy, saved)
+        torch.cuda.synchronize()
+        out[fused] = (y.cpu().numpy(), saved.cpu().numpy(), dp.cpu().numpy(), offsets)
+    np.testing.assert_array_equal(out[True][0], out[False][0])
+    np.testing.assert_array_equal(out[True][1], out[False][1])
+    np.testing.assert_array_equal(out[True][2], out[False][2])
+
+
+def test_fused_training_step_matches_layer_path(params):
+    """drc_cae_step (forward, L1, recomputing backward, Adam) gives the same
+    loss and parameters through either forward path."""
+    from paper_1910_02480_amd.cae import CAE, Trainer
+    xt, tg = synth.training_batch(16, 64)
+    xt, tg = torch.from_numpy(xt).to(DEV), torch.from_numpy(tg).to(DEV)
+    res = {}
+    for fused in (True, False):
+        cae = CAE("bf16", device=DEV, recompute=True)
+        cae.set_fused(fused)
+        tr = Trainer(cae, torch.from_numpy(params).to(DEV).clone())
+        losses = [float(tr.step(xt, tg)) for _ in range(2)]
+        res[fused] = (losses, tr.params.cpu().numpy())
+    assert res[True][0] == res[False][0]
+    np.testing.assert_array_equal(res[True][1], res[False][1])
