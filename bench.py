@@ -320,8 +320,8 @@ def main():
             ms_s, calls_s = B.drc_cae_profile_read(c.h)
             B.drc_cae_profile(c.h, 0)
             names = [f"fwd {LAYERS[l][0]}" for l in range(6)] + [f"dgrad {LAYERS[l][0]}" for l in range(6)] + \
-                    [f"wgrad {LAYERS[l][0]}" for l in range(6)] + ["bias grads", "loss", "adam"]
-            legs[f"{comp}_fwd_bwd"]["breakdown_ms"] = {names[k]: round(ms_s[k], 4) for k in range(21)
+                    [f"wgrad {LAYERS[l][0]}" for l in range(6)] + ["bias grads", "loss", "adam", "fused forward"]
+            legs[f"{comp}_fwd_bwd"]["breakdown_ms"] = {names[k]: round(ms_s[k], 4) for k in range(22)
                                                        if calls_s[k]}
             log(f"{comp} forward+backward: {n / tt:,.0f} maps/s")
             del c, saved, dy, wf, wb
@@ -341,8 +341,9 @@ def main():
             ms_s, calls_s = B.drc_cae_profile_read(tr.cae.h)
             B.drc_cae_profile(tr.cae.h, 0)
             names = [f"fwd {LAYERS[l][0]}" for l in range(6)] + [f"dgrad {LAYERS[l][0]}" for l in range(6)] + \
-                    [f"wgrad {LAYERS[l][0]}" for l in range(6)] + ["bias grads", "loss", "adam+repack"]
-            legs[f"{comp}_train_step"]["breakdown_ms"] = {names[k]: round(ms_s[k], 4) for k in range(21)
+                    [f"wgrad {LAYERS[l][0]}" for l in range(6)] + ["bias grads", "loss", "adam+repack",
+                                                                   "fused forward / recompute"]
+            legs[f"{comp}_train_step"]["breakdown_ms"] = {names[k]: round(ms_s[k], 4) for k in range(22)
                                                           if calls_s[k]}
             log(f"{comp} train step (batch {nt}): {nt / tt:,.0f} maps/s, {tt * 1e3:.3f} ms")
         # ---------------- mixed-resolution frame: one graph replay per frame

@@ -34,7 +34,8 @@ _LABELS = (
     (r"tconv_pairs_kernel<1, 128, 128, 64,", "forward D3"),
     (r"tconv_pairs_kernel<1, 128, 64, 32,", "forward D2"),
     (r"tconv_merged_kernel<1, 64, 32, 3,", "forward D1"),
-    (r"cae_fused_forward_kernel", "forward fused"),
+    (r"cae_fused_forward_kernel<\d+, \d+, false>", "forward fused"),
+    (r"cae_fused_forward_kernel<\d+, \d+, true>", "recompute fused"),
     (r"pack_weights_kernel", "weight pack"),
     (r"elementwise.*Mul|Mul.*elementwise", "copy (torch.mul, 256 MiB)"),
 )
