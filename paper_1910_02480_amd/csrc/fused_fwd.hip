@@ -6,22 +6,20 @@
 //
 // The layer path moves every activation through HBM (about 690 KB per 64x64
 // map in BF16 with FP32 input and output); here a map costs its FP32 input
-// (7 channels) and output (3 channels) plus one 64 KB round trip of h1
-// through a per-workgroup slot that stays in the L2/last-level caches.
+// (7 channels) and output (3 channels), plus whatever activations a
+// training forward asks to keep.
 //
 // LDS plan for an H x W map (bytes, BF16 NHWC, 16-byte channel chunks XOR-
 // swizzled by column against bank conflicts):
-//   R0 [0, 16HW)           h1 (E1 -> E2), then u2 (D2 -> D1)
+//   R0 [0, 16HW)           h1 (E1 -> D1); u2 of the recompute kernel
 //   R1 [16HW, 24HW)        h2 (E2 -> D2)
 //   R2 [24HW, 32HW)        u3 (D3 -> D2)
-//   R3 [32HW, 36HW)        h3 (E3 -> D3)
-//   R1+R2                  x as BF16, 8 channels (staging -> E1), and h1
-//                          again for D1 (reloaded from the workgroup's slot)
-//   [36HW, 36HW + 256)     zeros, read by taps that fall outside the map
-// 36 HW bytes + 256 in all: 144 KB at 64x64 (one workgroup per CU), 36 KB
-// at 32x32.
+//   R3 [32HW, ...)         h3 (E3 -> D3), then a ring of 9 u2 rows (D2 -> D1)
+//   R1+R2                  x as BF16, 8 channels (staging -> E1)
+//   then 256 bytes of zeros, read by taps that fall outside the map.
+// 146 KB at 64x64 (one workgroup per CU), 41 KB at 32x32.
 //
-// Every GEMM uses the same weight packs, K order and epilogue arithmetic as
+// Every GEMM uses the same weight values, K order and epilogue arithmetic as
 // the layer kernels, so the two paths agree bit for bit.
 #include <hip/hip_runtime.h>
 #include <string.h>
@@ -47,7 +45,6 @@ struct FusedArgs {
     const long* y_off;
     const uint16_t* w[6];  // forward packs in MFMA fragment order
     const float* b[6];
-    char* scratch;       // one h1 slot of 16 H W bytes per workgroup (when h1 is not saved)
     char* save[5];       // optional: h1 h2 h3 u3 u2 of every map, plain NHWC BF16 (null = not kept)
     int final_relu;
 };
@@ -260,12 +257,44 @@ __device__ __forceinline__ void conv_phase(char* smem, int in, int out, int zoff
 // weights of its set and of its row blocks into registers (the weights are
 // read from L2 and their bandwidth bounds these layers). Within a phase the
 // accumulation order is the layer kernel's: K step, then block.
-template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW, int SET>
-__device__ __forceinline__ void pairs_set(char* smem, int in0, int in1, int out, int zoff, const uint16_t* wp,
-                                          const float* bias_g, int tr, int tp0, int tp_step) {
-    constexpr int CIN = C0 + C1, PB = HI * WI / 16, KSN = CIN / 32;
+// Weights and biases a wave keeps in registers for a transposed-convolution
+// layer: blocks of its set (5 or 4) for its MT row blocks, every K step.
+template <int KSN, int MT>
+struct PairsPanel {
+    uint4 A[KSN][5][MT];
+    float bias[MT][4];
+};
+
+template <int COUT, int CIN, int MT>
+__device__ __forceinline__ void pairs_panel_load(PairsPanel<CIN / 32, MT>& P, const uint16_t* wp,
+                                                 const float* bias_g, int tr, int set) {
+    constexpr int KSN = CIN / 32;
+    const int lane = opaque_tid() & 63;
+    const int g = lane >> 4;
+    const uint16_t* w = opaque(wp);
+    const int q0 = set ? 5 : 0, nq = set ? 4 : 5;
+#pragma unroll
+    for (int ks = 0; ks < KSN; ++ks)
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                if (q < nq)
+                    P.A[ks][q][m] =
+                        *(const uint4*)(w + ((size_t)(((q0 + q) * (COUT / 16) + tr * MT + m) * KSN + ks) * 64 + lane) * 8);
+    const float* bg = opaque(bias_g);
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) P.bias[m][e] = bg[(tr * MT + m) * 16 + g * 4 + e];
+}
+
+template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW, int SET, int NPB, int ORING>
+__device__ __forceinline__ void pairs_tiles(const PairsPanel<(C0 + C1) / 32, MT>& P, char* smem, int in0, int in1,
+                                            int out, int zoff, int tr, int tp0, int tp_step, int pix0) {
+    constexpr int CIN = C0 + C1, KSN = CIN / 32;
     constexpr int WO = 2 * WI;
-    constexpr int TP = PB / NPW;
+    constexpr int TP = NPB / NPW;
     constexpr int ROW = WI * C0 * 2;
     constexpr int NSRC = C1 > 0 ? 2 : 1;
     constexpr int Q0 = SET ? 5 : 0, NQ = SET ? 4 : 5;   // weight blocks of the set
@@ -273,28 +302,12 @@ __device__ __forceinline__ void pairs_set(char* smem, int in0, int in1, int out,
     constexpr int NNB = SET ? 4 : 3;                    // neighbours it reads
     const int lane = opaque_tid() & 63;
     const int g = lane >> 4, r16 = lane & 15;
-    const uint16_t* w = opaque(wp);
-    uint4 A[KSN][NQ][MT];
-#pragma unroll
-    for (int ks = 0; ks < KSN; ++ks)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-#pragma unroll
-            for (int m = 0; m < MT; ++m)
-                A[ks][q][m] =
-                    *(const uint4*)(w + ((size_t)(((Q0 + q) * (COUT / 16) + tr * MT + m) * KSN + ks) * 64 + lane) * 8);
-    const float* bg = opaque(bias_g);
-    float bias[MT][4];
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) bias[m][e] = bg[(tr * MT + m) * 16 + g * 4 + e];
     for (int tp = tp0; tp < TP; tp += tp_step) {
         int ia[NPW], ib[NPW];
         int off[NPW][NSRC][4];
 #pragma unroll
         for (int p = 0; p < NPW; ++p) {
-            const int pix = (tp * NPW + p) * 16 + r16;
+            const int pix = pix0 + (tp * NPW + p) * 16 + r16;
             ia[p] = pix / WI;
             ib[p] = pix % WI;
             const bool down = ia[p] + 1 < HI, right = ib[p] + 1 < WI;
@@ -329,7 +342,7 @@ __device__ __forceinline__ void pairs_set(char* smem, int in0, int in1, int out,
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
 #pragma unroll
-                    for (int p = 0; p < NPW; ++p) mma(acc[ph][m][p], A[ks][q][m], bv[nb][p]);
+                    for (int p = 0; p < NPW; ++p) mma(acc[ph][m][p], P.A[ks][q][m], bv[nb][p]);
             }
         }
 #pragma unroll
@@ -339,9 +352,10 @@ __device__ __forceinline__ void pairs_set(char* smem, int in0, int in1, int out,
             for (int ph = 0; ph < NPH; ++ph)
 #pragma unroll
                 for (int p = 0; p < NPW; ++p) {
-                    const int P = PH0 + ph;
-                    lds_store4<COUT, WO>(smem, out, 2 * ia[p] + (P >> 1), 2 * ib[p] + (P & 1), ch, acc[ph][m][p],
-                                         bias[m], true);
+                    const int PP = PH0 + ph;
+                    // output row, or its slot in a ring of ORING rows
+                    const int orow = ORING ? (2 * ia[p] + (PP >> 1)) % (ORING > 0 ? ORING : 1) : 2 * ia[p] + (PP >> 1);
+                    lds_store4<COUT, WO>(smem, out, orow, 2 * ib[p] + (PP & 1), ch, acc[ph][m][p], P.bias[m], true);
                 }
         }
     }
@@ -349,63 +363,80 @@ __device__ __forceinline__ void pairs_set(char* smem, int in0, int in1, int out,
 
 // Work split of a transposed-convolution layer: 2 * TR groups (row-block
 // group x set), rotated by workgroup so that CUs start on different weights.
-template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW>
+// The GEMM pixels are NPB blocks of 16 from pix0 on (a band of input rows, or
+// the whole layer); ORING > 0 stores output row r at row r % ORING.
+template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW, int NPB = HI * WI / 16, int ORING = 0>
 __device__ __forceinline__ void pairs_phase(char* smem, int in0, int in1, int out, int zoff, const uint16_t* wp,
-                                            const float* bias_g) {
-    constexpr int PB = HI * WI / 16, RB = COUT / 16, TR = RB / MT, NG = 2 * TR;
-    static_assert(RB % MT == 0 && PB % NPW == 0 && FW % NG == 0 && C0 % 32 == 0 && C1 % 32 == 0,
+                                            const float* bias_g, int pix0 = 0) {
+    constexpr int RB = COUT / 16, TR = RB / MT, NG = 2 * TR;
+    static_assert(RB % MT == 0 && NPB % NPW == 0 && FW % NG == 0 && C0 % 32 == 0 && C1 % 32 == 0,
                   "tiles cover the layer");
     static_assert(C1 == 0 || C1 == C0, "both sources share one LDS layout");
     const int wave = opaque_tid() >> 6;
     const int gid = (wave + blockIdx.x) % NG;
     const int tr = gid >> 1, set = gid & 1;
     const int tp0 = wave / NG, step = FW / NG;
+    PairsPanel<(C0 + C1) / 32, MT> P;
+    pairs_panel_load<COUT, C0 + C1, MT>(P, wp, bias_g, tr, set);
     if (set == 0)
-        pairs_set<HI, WI, C0, C1, COUT, MT, NPW, 0>(smem, in0, in1, out, zoff, wp, bias_g, tr, tp0, step);
+        pairs_tiles<HI, WI, C0, C1, COUT, MT, NPW, 0, NPB, ORING>(P, smem, in0, in1, out, zoff, tr, tp0, step, pix0);
     else
-        pairs_set<HI, WI, C0, C1, COUT, MT, NPW, 1>(smem, in0, in1, out, zoff, wp, bias_g, tr, tp0, step);
+        pairs_tiles<HI, WI, C0, C1, COUT, MT, NPW, 1, NPB, ORING>(P, smem, in0, in1, out, zoff, tr, tp0, step, pix0);
 }
 
 // D1: transposed convolution [u2 | h1] (32 + 32 channels at HI x WI) -> 3
-// channels, linear, float32 to global. Merged rows r = phase * 3 + co (12 of
-// 16 used), K = neighbour * 64 + c, pack [16][256] in fragment order.
-template <int HI, int WI, int NPW>
-__device__ __forceinline__ void d1_phase(char* smem, int u2, int h1, int zoff, float* ym, const uint16_t* wp,
-                                         const float* bias_g, bool relu) {
-    constexpr int PB = HI * WI / 16, WO = 2 * WI, TP = PB / NPW;
-    constexpr int ROW = WI * 64;
-    static_assert(PB % NPW == 0, "tiles cover the layer");
-    const int tid = opaque_tid();
-    const int lane = tid & 63, wave = tid >> 6;
-    const int g = lane >> 4, r16 = lane & 15;
+// channels, linear, float32 to global, for GEMM rows [row0, row0 + nrows).
+// u2 row r is at row r % RING of its region when RING > 0. Merged rows
+// r = phase * 3 + co (12 of 16 used), K = neighbour * 64 + c, pack [16][256]
+// in fragment order.
+struct D1Panel {
     uint4 a[8];
+    float bias[4];
+};
+
+__device__ __forceinline__ void d1_panel_load(D1Panel& P, const uint16_t* wp, const float* bias_g) {
+    const int lane = opaque_tid() & 63;
+    const int g = lane >> 4;
     const uint16_t* w = opaque(wp);
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) a[ks] = *(const uint4*)(w + ((size_t)ks * 64 + lane) * 8);
+    for (int ks = 0; ks < 8; ++ks) P.a[ks] = *(const uint4*)(w + ((size_t)ks * 64 + lane) * 8);
     const float* bg = opaque(bias_g);
-    float bias[4];
-    int rph[4], rco[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int r = g * 4 + e;
-        rph[e] = r / 3;
-        rco[e] = r - (r / 3) * 3;
-        bias[e] = r < 12 ? bg[rco[e]] : 0.0f;
+        P.bias[e] = r < 12 ? bg[r % 3] : 0.0f;
     }
+}
+
+template <int HI, int WI, int NPW, int RING>
+__device__ __forceinline__ void d1_phase(const D1Panel& P, char* smem, int u2, int h1, int zoff, float* ym,
+                                         bool relu, int row0, int nrows) {
+    constexpr int WO = 2 * WI, ROW = WI * 64;
+    static_assert((WI / 16) % NPW == 0 || NPW == 1, "tiles cover whole rows");
+    const int tid = opaque_tid();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int TP = nrows * WI / 16 / NPW;
     for (int tp = wave; tp < TP; tp += FW) {
         int ia[NPW], ib[NPW];
-        int off[NPW][4];  // neighbours of the pixel in u2; h1 is at h1 - u2 further on
+        int ou[NPW][4], oh[NPW][4];  // byte offsets of the 4 neighbours in u2 and in h1
 #pragma unroll
         for (int p = 0; p < NPW; ++p) {
-            const int pix = (tp * NPW + p) * 16 + r16;
+            const int pix = row0 * WI + (tp * NPW + p) * 16 + r16;
             ia[p] = pix / WI;
             ib[p] = pix % WI;
             const bool down = ia[p] + 1 < HI, right = ib[p] + 1 < WI;
+            const int ru0 = RING ? ia[p] % (RING > 0 ? RING : 1) : ia[p];
+            const int ru1 = RING ? (ia[p] + 1) % (RING > 0 ? RING : 1) : ia[p] + 1;
 #pragma unroll
             for (int dj = 0; dj < 2; ++dj) {
-                const int b = loff<32, WI>(ia[p], ib[p] + dj, g);
-                off[p][dj] = (dj && !right) ? -1 : b;
-                off[p][2 + dj] = ((dj && !right) || !down) ? -1 : b + ROW;
+                const bool okr = !dj || right;
+                const int cu = loff<32, WI>(0, ib[p] + dj, g);
+                const int ch = loff<32, WI>(ia[p], ib[p] + dj, g);
+                ou[p][dj] = okr ? u2 + ru0 * ROW + cu : zoff;
+                ou[p][2 + dj] = (okr && down) ? u2 + ru1 * ROW + cu : zoff;
+                oh[p][dj] = okr ? h1 + ch : zoff;
+                oh[p][2 + dj] = (okr && down) ? h1 + ch + ROW : zoff;
             }
         }
         f4 acc[NPW];
@@ -414,23 +445,21 @@ __device__ __forceinline__ void d1_phase(char* smem, int u2, int h1, int zoff, f
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) {
             const int nb = ks >> 1;
-            const int src = (ks & 1) ? h1 : u2;
 #pragma unroll
-            for (int p = 0; p < NPW; ++p) {
-                const int o = off[p][nb];
-                mma(acc[p], a[ks], lds16(smem, o < 0 ? zoff : src + o));
-            }
+            for (int p = 0; p < NPW; ++p)
+                mma(acc[p], P.a[ks], lds16(smem, (ks & 1) ? oh[p][nb] : ou[p][nb]));
         }
 #pragma unroll
         for (int p = 0; p < NPW; ++p)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                if (g * 4 + e >= 12) continue;
-                const int ph = rph[e];
+                const int r = g * 4 + e;
+                if (r >= 12) continue;
+                const int ph = r / 3;
                 const int opix = (2 * ia[p] + (ph >> 1)) * WO + 2 * ib[p] + (ph & 1);
-                float v = acc[p][e] + bias[e];
+                float v = acc[p][e] + P.bias[e];
                 if (relu) v = (v < 0.0f) ? 0.0f : v;
-                ym[opix * 3 + rco[e]] = v;
+                ym[opix * 3 + (r - ph * 3)] = v;
             }
     }
 }
@@ -446,6 +475,19 @@ __device__ __forceinline__ void copy_out(char* dst, const char* smem, int region
         ((uint4*)dst)[i] = *(const uint4*)(smem + region + loff<C, WI>(pix / WI, pix % WI, j));
     }
 }
+// Rows [row0, row0 + nrows) of a ring of RING rows (C channels, WI wide) to
+// a plain NHWC tensor (dst = its row 0).
+template <int C, int WI, int RING>
+__device__ __forceinline__ void copy_rows_out(char* dst, const char* smem, int region, int row0, int nrows) {
+    constexpr int CH = C / 8, PER_ROW = WI * CH;
+    const int N = nrows * PER_ROW;
+    for (int i = threadIdx.x; i < N; i += FT) {
+        const int r = row0 + i / PER_ROW, rem = i % PER_ROW;
+        const int x = rem / CH, j = rem - x * CH;
+        ((uint4*)dst)[(long)row0 * PER_ROW + i] =
+            *(const uint4*)(smem + region + (r % RING) * (WI * C * 2) + loff<C, WI>(0, x, j));
+    }
+}
 template <int C, int HI, int WI>
 __device__ __forceinline__ void copy_in(char* smem, int region, const char* src) {
     constexpr int CH = C / 8, N = HI * WI * CH;
@@ -455,15 +497,32 @@ __device__ __forceinline__ void copy_in(char* smem, int region, const char* src)
     }
 }
 
-// MID = false: the whole network, x -> y (h1 kept in a per-workgroup slot
-// or in save[0]; every non-null save[k] receives that activation).
+// LDS layout of an H x W map (byte offsets).
+template <int H, int W>
+struct FusedLds {
+    static constexpr int HW = H * W;
+    static constexpr int R0 = 0, R1 = 16 * HW, R2 = 24 * HW, R3 = 32 * HW;
+    static constexpr int BAND = 4;                      // input rows of D2 per band
+    static constexpr int RING = 2 * BAND + 1;           // u2 rows kept for D1
+    static constexpr int RING_BYTES = RING * (W / 2) * 64;
+    static constexpr int ZO = (R3 + (RING_BYTES > 4 * HW ? RING_BYTES : 4 * HW) + 255) / 256 * 256;
+    static constexpr int BYTES = ZO + kZeroBytes;
+};
+
+// MID = false: the whole network, x -> y. Every non-null save[k] receives
+// that activation. D2 and D1 run in bands of 4 D2 input rows: a band's 8 u2
+// rows go to a ring of 9 rows (in R3 after h3 is consumed) and D1 then
+// consumes all u2 rows of the band but the last, whose lower neighbour comes
+// with the next band (the last band takes all its rows); h1 stays in R0
+// throughout.
 // MID = true: the recompute of a training backward, h2 (read from save[1])
 // -> h3, u3, u2 (written to save[2..4]); E1, E2 and D1 are skipped.
 template <int H, int W, bool MID>
 __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a) {
     extern __shared__ __align__(16) char smem[];
+    typedef FusedLds<H, W> L;
     constexpr int HW = H * W;
-    constexpr int R0 = 0, R1 = 16 * HW, R2 = 24 * HW, R3 = 32 * HW, ZO = 36 * HW;
+    constexpr int R0 = L::R0, R1 = L::R1, R2 = L::R2, R3 = L::R3, ZO = L::ZO;
     // tiles: a wave owns one group of row blocks (MT blocks of 16) per layer and
     // walks pixel tiles of NPW blocks; chosen so that 8 waves have work and
     // few waves load the same weights
@@ -471,21 +530,25 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
     constexpr int E2N = (HW / 256) >= 8 ? 4 : 1;            // E2: 4 groups of 1, PB = HW/256
     constexpr int E3N = (HW / 1024) >= 4 ? 4 : 1;           // E3: 8 groups of 1, PB = HW/1024
     constexpr int D3N = (HW / 1024) >= 4 ? 2 : 1;           // D3: 4 groups x 2 sets, PB = HW/1024
-    constexpr int D2N = (HW / 256) >= 16 ? 2 : 1;           // D2: 2 groups x 2 sets, PB = HW/256
-    constexpr int D1N = (HW / 64) >= 8 * 4 ? 4 : 2;         // D1: PB = HW/64
+    constexpr int D2N = (HW / 256) >= 16 ? 2 : 1;           // D2 (whole layer): 2 groups x 2 sets, PB = HW/256
+    constexpr int D2BPB = L::BAND * (W / 4) / 16;           // D2 pixel blocks per band
+    constexpr int D2BN = D2BPB >= 4 ? 2 : 1;                // 2 waves per group share a band
+    constexpr int D1N = (W / 2) >= 32 ? 2 : 1;              // D1: pixel blocks per tile (whole rows)
+    constexpr int NBAND = (H / 4) / L::BAND;
+    constexpr int HU = H / 2, WU = W / 2;                   // u2 size
     // per-map bytes of h1 h2 h3 u3 u2
     constexpr long B1 = 16L * HW, B2 = 8L * HW, B3 = 4L * HW, B4 = 8L * HW, B5 = 16L * HW;
+    static_assert((H / 4) % L::BAND == 0, "whole bands");
     if (threadIdx.x < kZeroBytes / 16) *(uint4*)(smem + ZO + 16 * threadIdx.x) = uint4{0u, 0u, 0u, 0u};
     for (int m = blockIdx.x; m < a.nmaps; m += gridDim.x) {
         if constexpr (!MID) {
             const float* xm = a.x + (a.x_off ? a.x_off[m] : (long)m * HW * 7);
             float* ym = a.y + (a.y_off ? a.y_off[m] : (long)m * HW * 3);
-            char* slot = a.save[0] ? a.save[0] + m * B1 : a.scratch + (size_t)blockIdx.x * B1;
             stage_x<H, W>(smem, R1, xm);
             __syncthreads();
             conv_phase<H, W, 8, 32, 2, E1N>(smem, R1, R0, ZO, a.w[0], a.b[0]);
             __syncthreads();
-            copy_out<32, H / 2, W / 2>(slot, smem, R0);
+            if (a.save[0]) copy_out<32, H / 2, W / 2>(a.save[0] + m * B1, smem, R0);
             conv_phase<H / 2, W / 2, 32, 64, 1, E2N>(smem, R0, R1, ZO, a.w[1], a.b[1]);
             __syncthreads();
             if (a.save[1]) copy_out<64, H / 4, W / 4>(a.save[1] + m * B2, smem, R1);
@@ -495,13 +558,35 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
             pairs_phase<H / 8, W / 8, 128, 0, 64, 1, D3N>(smem, R3, R3, R2, ZO, a.w[3], a.b[3]);
             __syncthreads();
             if (a.save[3]) copy_out<64, H / 4, W / 4>(a.save[3] + m * B4, smem, R2);
-            pairs_phase<H / 4, W / 4, 64, 64, 32, 1, D2N>(smem, R2, R1, R0, ZO, a.w[4], a.b[4]);
-            __syncthreads();
-            if (a.save[4]) copy_out<32, H / 2, W / 2>(a.save[4] + m * B5, smem, R0);
-            copy_in<32, H / 2, W / 2>(smem, R1, slot);
-            __syncthreads();
-            d1_phase<H / 2, W / 2, D1N>(smem, R0, R1, ZO, ym, a.w[5], a.b[5], a.final_relu != 0);
-            __syncthreads();
+            {
+                // D2's and D1's weights stay in registers across the bands
+                constexpr int NG = 4;  // D2: 2 row blocks x 2 sets, one row block per group
+                const int wave = opaque_tid() >> 6;
+                const int gid = (wave + blockIdx.x) % NG;
+                const int tr = gid >> 1, set = gid & 1;
+                PairsPanel<4, 1> P2;
+                pairs_panel_load<32, 128, 1>(P2, a.w[4], a.b[4], tr, set);
+                D1Panel P1;
+                d1_panel_load(P1, a.w[5], a.b[5]);
+                for (int band = 0; band < NBAND; ++band) {
+                    const int pix0 = band * L::BAND * (W / 4);
+                    if (set == 0)
+                        pairs_tiles<H / 4, W / 4, 64, 64, 32, 1, D2BN, 0, D2BPB, L::RING>(
+                            P2, smem, R2, R1, R3, ZO, tr, wave / NG, FW / NG, pix0);
+                    else
+                        pairs_tiles<H / 4, W / 4, 64, 64, 32, 1, D2BN, 1, D2BPB, L::RING>(
+                            P2, smem, R2, R1, R3, ZO, tr, wave / NG, FW / NG, pix0);
+                    __syncthreads();
+                    const int u0 = 2 * L::BAND * band;  // first u2 row of the band
+                    if (a.save[4]) copy_rows_out<32, WU, L::RING>(a.save[4] + m * B5, smem, R3, u0, 2 * L::BAND);
+                    // u2 rows [r0, r1): all rows of the band whose lower neighbour is
+                    // known (the last band also takes the map's last row)
+                    const int r0 = band ? u0 - 1 : 0;
+                    const int r1 = band + 1 < NBAND ? u0 + 2 * L::BAND - 1 : HU;
+                    d1_phase<HU, WU, D1N, L::RING>(P1, smem, R3, R0, ZO, ym, a.final_relu != 0, r0, r1 - r0);
+                    __syncthreads();
+                }
+            }
         } else {
             copy_in<64, H / 4, W / 4>(smem, R1, a.save[1] + m * B2);
             __syncthreads();
@@ -521,7 +606,7 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
 
 template <int H, int W, bool MID>
 drc_status launch_fused(const FusedArgs& a, int grid, hipStream_t s) {
-    const int lds = 36 * H * W + kZeroBytes;
+    const int lds = FusedLds<H, W>::BYTES;
     auto kern = cae_fused_forward_kernel<H, W, MID>;
     if (lds > 64 * 1024) {
         if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
@@ -554,10 +639,9 @@ int fused_forward_grid(const drc_cae* h, int n, int H, int W) {
     return std::max(1, std::min(n, h->num_cu * per_cu));
 }
 
-// Scratch bytes of one fused launch (one h1 slot per workgroup) when h1 is not saved.
-size_t fused_forward_scratch(const drc_cae* h, int n, int H, int W) {
-    return (size_t)fused_forward_grid(h, n, H, W) * 16 * H * W;
-}
+// Scratch bytes of one fused launch: none (every activation stays on chip
+// unless saved).
+size_t fused_forward_scratch(const drc_cae*, int, int, int) { return 0; }
 
 drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int W, const long* x_off,
                          const long* y_off, void* scratch, size_t scratch_bytes, hipStream_t s,
@@ -568,14 +652,12 @@ drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int
     FusedArgs a = fused_args(h, n);
     if (save)
         for (int k = 0; k < 5; ++k) a.save[k] = save[k];
-    if (!a.save[0] && scratch_bytes < fused_forward_scratch(h, n, H, W))
-        return drc_fail(DRC_ERR_WORKSPACE, "fused forward: scratch %zu < %zu bytes", scratch_bytes,
-                        fused_forward_scratch(h, n, H, W));
+    (void)scratch_bytes;
     a.x = x;
     a.y = y;
     a.x_off = x_off;
     a.y_off = y_off;
-    a.scratch = (char*)scratch;
+    (void)scratch;
     const int grid = fused_forward_grid(h, n, H, W);
     const long tok = prof_begin(h, PROF_FUSED, s);
     drc_status st = (H == 64) ? launch_fused<64, 64, false>(a, grid, s) : launch_fused<32, 32, false>(a, grid, s);
