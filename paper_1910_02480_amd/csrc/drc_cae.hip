@@ -155,6 +155,7 @@ extern "C" drc_status drc_cae_create(const drc_cae_desc* desc, drc_cae** out) {
             ok = alloc(&h->wb[l], h->wb_bytes[l]);
         }
         if (ok && h->prec == P_BF16) ok = alloc(&h->wfrag[l], h->wf_bytes[l]);
+        if (ok && h->prec == P_BF16) ok = alloc(&h->wbfrag[l], h->wb_bytes[l]);
         if (ok && h->prec == P_FP8) {  // float32 packs for the calibration forward
             GemmGeom gc = gemm_geom(l, false, P_F32);
             ok = alloc(&h->wcal[l], (size_t)gc.nblk * gc.rows_pad * gc.kstride * 4);
@@ -180,6 +181,7 @@ extern "C" void drc_cae_destroy(drc_cae* h) {
         if (h->wb[l]) (void)hipFree(h->wb[l]);
         if (h->wcal[l]) (void)hipFree(h->wcal[l]);
         if (h->wfrag[l]) (void)hipFree(h->wfrag[l]);
+        if (h->wbfrag[l]) (void)hipFree(h->wbfrag[l]);
     }
     if (h->bias) (void)hipFree(h->bias);
     if (h->scales) (void)hipFree(h->scales);
@@ -515,13 +517,16 @@ static drc_status pack_all(drc_cae* h, const float* d_params, hipStream_t s) {
         }
     }
     if (h->prec == P_BF16) {
-        for (int l = 0; l < 6; ++l) {
-            GemmGeom g = gemm_geom(l, false, P_BF16);
-            const int rows = g.nblk * g.rows_pad, ksteps = g.kstride / 32;
-            const long units = (long)rows * ksteps * 4;
-            hipLaunchKernelGGL(frag_order_kernel, dim3((int)std::min(1024L, (units + 255) / 256)), dim3(256), 0, s,
-                               (const uint4*)h->wf[l], (uint4*)h->wfrag[l], rows, ksteps);
-        }
+        for (int l = 0; l < 6; ++l)
+            for (int dir = 0; dir < 2; ++dir) {
+                GemmGeom g = gemm_geom(l, dir == 1, P_BF16);
+                if (g.kstride % 32) continue;  // (not a fused-kernel operand)
+                const int rows = g.nblk * g.rows_pad, ksteps = g.kstride / 32;
+                const long units = (long)rows * ksteps * 4;
+                hipLaunchKernelGGL(frag_order_kernel, dim3((int)std::min(1024L, (units + 255) / 256)), dim3(256), 0,
+                                   s, (const uint4*)(dir ? h->wb[l] : h->wf[l]),
+                                   (uint4*)(dir ? h->wbfrag[l] : h->wfrag[l]), rows, ksteps);
+            }
     }
     TRY(check_launch("set_params/pack"));
     return DRC_OK;

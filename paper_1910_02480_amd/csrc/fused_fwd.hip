@@ -87,6 +87,16 @@ __device__ __forceinline__ void lds_store4(char* smem, int region, int y, int x,
 
 __device__ __forceinline__ void mma(f4& acc, const uint4& a, const uint4& b) { Traits<P_BF16>::mma(acc, a, b); }
 
+// Forward epilogue: bias + ReLU, BF16 into an LDS tensor of C channels, WO wide.
+template <int C, int WO>
+struct LdsOut {
+    char* smem;
+    int region;
+    __device__ __forceinline__ void operator()(int ch, int y, int x, const f4& acc, const float* bias) const {
+        lds_store4<C, WO>(smem, region, y, x, ch, acc, bias, true);
+    }
+};
+
 // Hides a value from the optimiser. Weight loads are then issued inside the
 // layer instead of being hoisted out of the map loop (where they would pin
 // hundreds of registers across every layer), and per-lane addresses are
@@ -146,9 +156,9 @@ __device__ __forceinline__ void stage_x(char* smem, int xs, const float* xm) {
 // registers once; it then walks the pixel tiles w / TR, w / TR + FW / TR, ...
 // (NPW blocks of 16 consecutive output pixels each). Taps that fall outside
 // the map read the zero block at zoff.
-template <int HI, int WI, int CIN, int COUT, int MT, int NPW>
-__device__ __forceinline__ void conv_phase(char* smem, int in, int out, int zoff, const uint16_t* wp,
-                                           const float* bias_g) {
+template <int HI, int WI, int CIN, int COUT, int MT, int NPW, class Epi>
+__device__ __forceinline__ void conv_phase(char* smem, int in, int zoff, const uint16_t* wp, const float* bias_g,
+                                           const Epi& epi) {
     constexpr int HO = HI / 2, WO = WI / 2;
     constexpr int PB = HO * WO / 16, RB = COUT / 16;
     constexpr int KSTEPS = (9 * CIN + 31) / 32;
@@ -171,7 +181,7 @@ __device__ __forceinline__ void conv_phase(char* smem, int in, int out, int zoff
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) bias[m][e] = bg[(tr * MT + m) * 16 + g * 4 + e];
+        for (int e = 0; e < 4; ++e) bias[m][e] = bias_g ? bg[(tr * MT + m) * 16 + g * 4 + e] : 0.0f;
     // CIN == 8: the lane group g takes tap 4 ks + g of every K step
     int dk[KSTEPS];
     bool tv[KSTEPS], nt[KSTEPS], nl[KSTEPS];
@@ -242,7 +252,7 @@ __device__ __forceinline__ void conv_phase(char* smem, int in, int out, int zoff
             const int ch = (tr * MT + m) * 16 + g * 4;
 #pragma unroll
             for (int p = 0; p < NPW; ++p)
-                lds_store4<COUT, WO>(smem, out, oy[p], ox[p], ch, acc[m][p], bias[m], true);
+                epi(ch, oy[p], ox[p], acc[m][p], bias[m]);
         }
     }
 }
@@ -286,12 +296,12 @@ __device__ __forceinline__ void pairs_panel_load(PairsPanel<CIN / 32, MT>& P, co
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) P.bias[m][e] = bg[(tr * MT + m) * 16 + g * 4 + e];
+        for (int e = 0; e < 4; ++e) P.bias[m][e] = bias_g ? bg[(tr * MT + m) * 16 + g * 4 + e] : 0.0f;
 }
 
-template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW, int SET, int NPB, int ORING>
+template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW, int SET, int NPB, int ORING, class Epi>
 __device__ __forceinline__ void pairs_tiles(const PairsPanel<(C0 + C1) / 32, MT>& P, char* smem, int in0, int in1,
-                                            int out, int zoff, int tr, int tp0, int tp_step, int pix0) {
+                                            int zoff, int tr, int tp0, int tp_step, int pix0, const Epi& epi) {
     constexpr int CIN = C0 + C1, KSN = CIN / 32;
     constexpr int WO = 2 * WI;
     constexpr int TP = NPB / NPW;
@@ -355,7 +365,7 @@ __device__ __forceinline__ void pairs_tiles(const PairsPanel<(C0 + C1) / 32, MT>
                     const int PP = PH0 + ph;
                     // output row, or its slot in a ring of ORING rows
                     const int orow = ORING ? (2 * ia[p] + (PP >> 1)) % (ORING > 0 ? ORING : 1) : 2 * ia[p] + (PP >> 1);
-                    lds_store4<COUT, WO>(smem, out, orow, 2 * ib[p] + (PP & 1), ch, acc[ph][m][p], P.bias[m], true);
+                    epi(ch, orow, 2 * ib[p] + (PP & 1), acc[ph][m][p], P.bias[m]);
                 }
         }
     }
@@ -363,11 +373,11 @@ __device__ __forceinline__ void pairs_tiles(const PairsPanel<(C0 + C1) / 32, MT>
 
 // Work split of a transposed-convolution layer: 2 * TR groups (row-block
 // group x set), rotated by workgroup so that CUs start on different weights.
-// The GEMM pixels are NPB blocks of 16 from pix0 on (a band of input rows, or
-// the whole layer); ORING > 0 stores output row r at row r % ORING.
-template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW, int NPB = HI * WI / 16, int ORING = 0>
-__device__ __forceinline__ void pairs_phase(char* smem, int in0, int in1, int out, int zoff, const uint16_t* wp,
-                                            const float* bias_g, int pix0 = 0) {
+template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW, class Epi>
+__device__ __forceinline__ void pairs_phase(char* smem, int in0, int in1, int zoff, const uint16_t* wp,
+                                            const float* bias_g, const Epi& epi) {
+    constexpr int NPB = HI * WI / 16, ORING = 0;
+    const int pix0 = 0;
     constexpr int RB = COUT / 16, TR = RB / MT, NG = 2 * TR;
     static_assert(RB % MT == 0 && NPB % NPW == 0 && FW % NG == 0 && C0 % 32 == 0 && C1 % 32 == 0,
                   "tiles cover the layer");
@@ -379,9 +389,9 @@ __device__ __forceinline__ void pairs_phase(char* smem, int in0, int in1, int ou
     PairsPanel<(C0 + C1) / 32, MT> P;
     pairs_panel_load<COUT, C0 + C1, MT>(P, wp, bias_g, tr, set);
     if (set == 0)
-        pairs_tiles<HI, WI, C0, C1, COUT, MT, NPW, 0, NPB, ORING>(P, smem, in0, in1, out, zoff, tr, tp0, step, pix0);
+        pairs_tiles<HI, WI, C0, C1, COUT, MT, NPW, 0, NPB, ORING>(P, smem, in0, in1, zoff, tr, tp0, step, pix0, epi);
     else
-        pairs_tiles<HI, WI, C0, C1, COUT, MT, NPW, 1, NPB, ORING>(P, smem, in0, in1, out, zoff, tr, tp0, step, pix0);
+        pairs_tiles<HI, WI, C0, C1, COUT, MT, NPW, 1, NPB, ORING>(P, smem, in0, in1, zoff, tr, tp0, step, pix0, epi);
 }
 
 // D1: transposed convolution [u2 | h1] (32 + 32 channels at HI x WI) -> 3
@@ -546,16 +556,16 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
             float* ym = a.y + (a.y_off ? a.y_off[m] : (long)m * HW * 3);
             stage_x<H, W>(smem, R1, xm);
             __syncthreads();
-            conv_phase<H, W, 8, 32, 2, E1N>(smem, R1, R0, ZO, a.w[0], a.b[0]);
+            conv_phase<H, W, 8, 32, 2, E1N>(smem, R1, ZO, a.w[0], a.b[0], LdsOut<32, W / 2>{smem, R0});
             __syncthreads();
             if (a.save[0]) copy_out<32, H / 2, W / 2>(a.save[0] + m * B1, smem, R0);
-            conv_phase<H / 2, W / 2, 32, 64, 1, E2N>(smem, R0, R1, ZO, a.w[1], a.b[1]);
+            conv_phase<H / 2, W / 2, 32, 64, 1, E2N>(smem, R0, ZO, a.w[1], a.b[1], LdsOut<64, W / 4>{smem, R1});
             __syncthreads();
             if (a.save[1]) copy_out<64, H / 4, W / 4>(a.save[1] + m * B2, smem, R1);
-            conv_phase<H / 4, W / 4, 64, 128, 1, E3N>(smem, R1, R3, ZO, a.w[2], a.b[2]);
+            conv_phase<H / 4, W / 4, 64, 128, 1, E3N>(smem, R1, ZO, a.w[2], a.b[2], LdsOut<128, W / 8>{smem, R3});
             __syncthreads();
             if (a.save[2]) copy_out<128, H / 8, W / 8>(a.save[2] + m * B3, smem, R3);
-            pairs_phase<H / 8, W / 8, 128, 0, 64, 1, D3N>(smem, R3, R3, R2, ZO, a.w[3], a.b[3]);
+            pairs_phase<H / 8, W / 8, 128, 0, 64, 1, D3N>(smem, R3, R3, ZO, a.w[3], a.b[3], LdsOut<64, W / 4>{smem, R2});
             __syncthreads();
             if (a.save[3]) copy_out<64, H / 4, W / 4>(a.save[3] + m * B4, smem, R2);
             {
@@ -570,12 +580,13 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
                 d1_panel_load(P1, a.w[5], a.b[5]);
                 for (int band = 0; band < NBAND; ++band) {
                     const int pix0 = band * L::BAND * (W / 4);
+                    const LdsOut<32, W / 2> ring{smem, R3};
                     if (set == 0)
                         pairs_tiles<H / 4, W / 4, 64, 64, 32, 1, D2BN, 0, D2BPB, L::RING>(
-                            P2, smem, R2, R1, R3, ZO, tr, wave / NG, FW / NG, pix0);
+                            P2, smem, R2, R1, ZO, tr, wave / NG, FW / NG, pix0, ring);
                     else
                         pairs_tiles<H / 4, W / 4, 64, 64, 32, 1, D2BN, 1, D2BPB, L::RING>(
-                            P2, smem, R2, R1, R3, ZO, tr, wave / NG, FW / NG, pix0);
+                            P2, smem, R2, R1, ZO, tr, wave / NG, FW / NG, pix0, ring);
                     __syncthreads();
                     const int u0 = 2 * L::BAND * band;  // first u2 row of the band
                     if (a.save[4]) copy_rows_out<32, WU, L::RING>(a.save[4] + m * B5, smem, R3, u0, 2 * L::BAND);
@@ -590,18 +601,179 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
         } else {
             copy_in<64, H / 4, W / 4>(smem, R1, a.save[1] + m * B2);
             __syncthreads();
-            conv_phase<H / 4, W / 4, 64, 128, 1, E3N>(smem, R1, R3, ZO, a.w[2], a.b[2]);
+            conv_phase<H / 4, W / 4, 64, 128, 1, E3N>(smem, R1, ZO, a.w[2], a.b[2], LdsOut<128, W / 8>{smem, R3});
             __syncthreads();
             copy_out<128, H / 8, W / 8>(a.save[2] + m * B3, smem, R3);
-            pairs_phase<H / 8, W / 8, 128, 0, 64, 1, D3N>(smem, R3, R3, R2, ZO, a.w[3], a.b[3]);
+            pairs_phase<H / 8, W / 8, 128, 0, 64, 1, D3N>(smem, R3, R3, ZO, a.w[3], a.b[3], LdsOut<64, W / 4>{smem, R2});
             __syncthreads();
             copy_out<64, H / 4, W / 4>(a.save[3] + m * B4, smem, R2);
-            pairs_phase<H / 4, W / 4, 64, 64, 32, 1, D2N>(smem, R2, R1, R0, ZO, a.w[4], a.b[4]);
+            pairs_phase<H / 4, W / 4, 64, 64, 32, 1, D2N>(smem, R2, R1, ZO, a.w[4], a.b[4], LdsOut<32, W / 2>{smem, R0});
             __syncthreads();
             copy_out<32, H / 2, W / 2>(a.save[4] + m * B5, smem, R0);
             __syncthreads();
         }
     }
+}
+
+// ======================================================================
+// Data-gradient chain of the training backward (Sec. 4.3), one map per
+// workgroup pass: dy -> D1^T -> D2^T
+// -> D3^T -> E3^T -> E2^T, each a stride-2 (transposed) convolution with the
+// layer's transposed weights, the ReLU masks of the saved activations and
+// the skip-gradient sums applied in the epilogues. Every output gradient the
+// weight gradients need (dz_u2, dz_u3, dz_h3, dz_h2, dz_h1) and the skip
+// gradient dh1s go to HBM; the chain's inputs stay in LDS:
+//   RA [0, 16HW): dy as BF16 (8 channels), then dz_u3 [0, 8HW) and dh2s [8HW, 16HW)
+//   RB [16HW, 32HW): dz_u2, then dz_h3 [16HW, 20HW) and dz_h2 [20HW, 28HW)
+//   zeros at 32HW.
+// K order, rounding and epilogue order (add, then mask) are the layer
+// kernels', so the results are bitwise equal to the layer path.
+struct GSeg {
+    int region;            // LDS tensor receiving the value (< 0: none)
+    uint16_t* gdst;        // global tensor of the map (plain NHWC; null: none)
+    const uint16_t* mask;  // ReLU output of the layer below (value kept where > 0; null: none)
+    const uint16_t* gadd;  // global tensor added first (null: none)
+    int ladd;              // LDS tensor added first (< 0: none)
+};
+
+constexpr GSeg kNoSeg = {-1, nullptr, nullptr, nullptr, -1};
+
+__device__ __forceinline__ void bf16x4_to_f32(uint2 w, float (&o)[4]) {
+    o[0] = bf16_to_f32((uint16_t)(w.x & 0xffffu));
+    o[1] = bf16_to_f32((uint16_t)(w.x >> 16));
+    o[2] = bf16_to_f32((uint16_t)(w.y & 0xffffu));
+    o[3] = bf16_to_f32((uint16_t)(w.y >> 16));
+}
+
+template <int C, int WO>
+__device__ __forceinline__ void grad_store(char* smem, const GSeg& sg, int lc, int y, int x, float (&v)[4]) {
+    const long pix = (long)y * WO + x;
+    const int loffs = loff<C, WO>(y, x, lc >> 3) + ((lc >> 2) & 1) * 8;
+    if (sg.gadd) {
+        float ad[4];
+        bf16x4_to_f32(*(const uint2*)(sg.gadd + pix * C + lc), ad);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] += ad[e];
+    }
+    if (sg.ladd >= 0) {
+        float ad[4];
+        bf16x4_to_f32(*(const uint2*)(smem + sg.ladd + loffs), ad);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] += ad[e];
+    }
+    if (sg.mask) {
+        float mk[4];
+        bf16x4_to_f32(*(const uint2*)(sg.mask + pix * C + lc), mk);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (mk[e] > 0.0f) ? v[e] : 0.0f;
+    }
+    uint2 w;
+    w.x = (uint32_t)bf16_bits(v[0]) | ((uint32_t)bf16_bits(v[1]) << 16);
+    w.y = (uint32_t)bf16_bits(v[2]) | ((uint32_t)bf16_bits(v[3]) << 16);
+    if (sg.region >= 0) *(uint2*)(smem + sg.region + loffs) = w;
+    if (sg.gdst) *(uint2*)(sg.gdst + pix * C + lc) = w;
+}
+
+// Epilogue of a data-gradient GEMM whose rows are [segment 0 (C0 channels) |
+// segment 1 (C1 channels)], WO pixels per output row.
+template <int C0, int C1, int WO>
+struct GradOut {
+    char* smem;
+    GSeg s0, s1;
+    __device__ __forceinline__ void operator()(int ch, int y, int x, const f4& acc, const float* bias) const {
+        float v[4] = {acc.x + bias[0], acc.y + bias[1], acc.z + bias[2], acc.w + bias[3]};
+        if (C1 == 0 || ch < C0)
+            grad_store<C0, WO>(smem, s0, ch, y, x, v);
+        else
+            grad_store<(C1 > 0 ? C1 : 8), WO>(smem, s1, ch - C0, y, x, v);
+    }
+};
+
+struct DgradArgs {
+    const float* dy;   // [n, H, W, 3] float32
+    int nmaps;
+    const uint16_t* w[6];  // backward-data packs in fragment order (layers 1..5 used)
+    const uint16_t *u2, *u3, *h3, *h2, *h1;              // saved activations (masks)
+    uint16_t *dz_u2, *dh1s, *dz_u3, *dz_h3, *dz_h2, *dz_h1;  // outputs
+};
+
+// dy (float32, 3 channels) -> LDS as BF16 with 8 channels (3..7 = 0).
+template <int H, int W>
+__device__ __forceinline__ void stage_dy(char* smem, int xs, const float* dm) {
+    constexpr int Q = H * W / 4;  // groups of 4 pixels = 12 floats = 3 float4
+    const int tid = opaque_tid();
+    for (int q = tid; q < Q; q += FT) {
+        float4 v[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[k] = ((const float4*)dm)[q * 3 + k];
+        const float* f = (const float*)v;
+#pragma unroll
+        for (int px = 0; px < 4; ++px) {
+            uint4 o;
+            o.x = (uint32_t)bf16_bits(f[3 * px + 0]) | ((uint32_t)bf16_bits(f[3 * px + 1]) << 16);
+            o.y = (uint32_t)bf16_bits(f[3 * px + 2]);
+            o.z = 0u;
+            o.w = 0u;
+            *(uint4*)(smem + xs + (4 * q + px) * 16) = o;
+        }
+    }
+}
+
+template <int H, int W>
+__global__ __launch_bounds__(FT) void cae_fused_dgrad_kernel(const DgradArgs a) {
+    extern __shared__ __align__(16) char smem[];
+    constexpr int HW = H * W;
+    constexpr int RA = 0, RB = 16 * HW, ZO = 32 * HW;
+    constexpr long S1 = 8L * HW, S2 = 4L * HW, S3 = 2L * HW;  // elements per map at H/2, H/4, H/8
+    constexpr int P3N = (HW / 256) >= 8 ? 4 : 2;
+    constexpr int P4N = (HW / 1024) >= 4 ? 4 : 1;
+    constexpr int P5N = (HW / 1024) >= 4 ? 2 : 1;
+    constexpr int P6N = (HW / 256) >= 16 ? 2 : 1;
+    if (threadIdx.x < kZeroBytes / 16) *(uint4*)(smem + ZO + 16 * threadIdx.x) = uint4{0u, 0u, 0u, 0u};
+    for (int m = blockIdx.x; m < a.nmaps; m += gridDim.x) {
+        stage_dy<H, W>(smem, RA, a.dy + (long)m * HW * 3);
+        __syncthreads();
+        {   // D1^T: dy -> [dz_u2 (masked by u2) | dh1s]
+            GradOut<32, 32, W / 2> e{smem, GSeg{RB, a.dz_u2 + m * S1, a.u2 + m * S1, nullptr, -1},
+                                     GSeg{-1, a.dh1s + m * S1, nullptr, nullptr, -1}};
+            conv_phase<H, W, 8, 64, 2, 4>(smem, RA, ZO, a.w[5], nullptr, e);
+        }
+        __syncthreads();
+        {   // D2^T: dz_u2 -> [dz_u3 (masked by u3) | dh2s]
+            GradOut<64, 64, W / 4> e{smem, GSeg{RA, a.dz_u3 + m * S2, a.u3 + m * S2, nullptr, -1},
+                                     GSeg{RA + 8 * HW, nullptr, nullptr, nullptr, -1}};
+            conv_phase<H / 2, W / 2, 32, 128, 2, P3N>(smem, RB, ZO, a.w[4], nullptr, e);
+        }
+        __syncthreads();
+        {   // D3^T: dz_u3 -> dz_h3 (masked by h3)
+            GradOut<128, 0, W / 8> e{smem, GSeg{RB, a.dz_h3 + m * S3, a.h3 + m * S3, nullptr, -1}, kNoSeg};
+            conv_phase<H / 4, W / 4, 64, 128, 1, P4N>(smem, RA, ZO, a.w[3], nullptr, e);
+        }
+        __syncthreads();
+        {   // E3^T: dz_h3 -> dz_h2 = (. + dh2s) masked by h2
+            GradOut<64, 0, W / 4> e{smem, GSeg{RB + 4 * HW, a.dz_h2 + m * S2, a.h2 + m * S2, nullptr, RA + 8 * HW},
+                                    kNoSeg};
+            pairs_phase<H / 8, W / 8, 128, 0, 64, 1, P5N>(smem, RB, RB, ZO, a.w[2], nullptr, e);
+        }
+        __syncthreads();
+        {   // E2^T: dz_h2 -> dz_h1 = (. + dh1s) masked by h1
+            GradOut<32, 0, W / 2> e{smem, GSeg{-1, a.dz_h1 + m * S1, a.h1 + m * S1, a.dh1s + m * S1, -1}, kNoSeg};
+            pairs_phase<H / 4, W / 4, 64, 0, 32, 1, P6N>(smem, RB + 4 * HW, RB + 4 * HW, ZO, a.w[1], nullptr, e);
+        }
+        __syncthreads();
+    }
+}
+
+template <int H, int W>
+drc_status launch_dgrad(const DgradArgs& a, int grid, hipStream_t s) {
+    const int lds = 32 * H * W + kZeroBytes;
+    auto kern = cae_fused_dgrad_kernel<H, W>;
+    if (lds > 64 * 1024) {
+        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+            return drc_fail(DRC_ERR_HIP, "fused dgrad: cannot raise the LDS limit to %d bytes", lds);
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(FT), lds, s, a);
+    return check_launch("fused dgrad");
 }
 
 template <int H, int W, bool MID>
@@ -678,6 +850,35 @@ drc_status fused_recompute(drc_cae* h, int n, int H, int W, const void* h2, void
     const int grid = fused_forward_grid(h, n, H, W);
     const long tok = prof_begin(h, PROF_FUSED, s);
     drc_status st = (H == 64) ? launch_fused<64, 64, true>(a, grid, s) : launch_fused<32, 32, true>(a, grid, s);
+    prof_end(h, tok, s);
+    return st;
+}
+
+drc_status fused_dgrad(drc_cae* h, int n, int H, int W, const float* dy, const void* u2, const void* u3,
+                       const void* h3, const void* h2, const void* h1, void* dz_u2, void* dh1s, void* dz_u3,
+                       void* dz_h3, void* dz_h2, void* dz_h1, hipStream_t s) {
+    if (h->prec != P_BF16 || !fused_forward_size(H, W))
+        return drc_fail(DRC_ERR_UNSUPPORTED, "fused dgrad: BF16 maps of 32x32 or 64x64 only");
+    if (n < 1) return DRC_OK;
+    DgradArgs a;
+    memset(&a, 0, sizeof a);
+    a.dy = dy;
+    a.nmaps = n;
+    for (int l = 1; l < 6; ++l) a.w[l] = (const uint16_t*)h->wbfrag[l];
+    a.u2 = (const uint16_t*)u2;
+    a.u3 = (const uint16_t*)u3;
+    a.h3 = (const uint16_t*)h3;
+    a.h2 = (const uint16_t*)h2;
+    a.h1 = (const uint16_t*)h1;
+    a.dz_u2 = (uint16_t*)dz_u2;
+    a.dh1s = (uint16_t*)dh1s;
+    a.dz_u3 = (uint16_t*)dz_u3;
+    a.dz_h3 = (uint16_t*)dz_h3;
+    a.dz_h2 = (uint16_t*)dz_h2;
+    a.dz_h1 = (uint16_t*)dz_h1;
+    const int grid = fused_forward_grid(h, n, H, W);
+    const long tok = prof_begin(h, PROF_FUSED_BWD, s);
+    drc_status st = (H == 64) ? launch_dgrad<64, 64>(a, grid, s) : launch_dgrad<32, 32>(a, grid, s);
     prof_end(h, tok, s);
     return st;
 }

@@ -37,6 +37,7 @@ struct drc_cae {
     void* wb[6] = {};      // backward-data (transposed) packs
     void* wcal[6] = {};    // float32 forward packs of FP8 handles (calibration)
     void* wfrag[6] = {};   // BF16 handles: forward packs in MFMA fragment order (fused forward)
+    void* wbfrag[6] = {};  // BF16 handles: backward-data packs in fragment order (fused data gradients)
     size_t wf_bytes[6] = {}, wb_bytes[6] = {};
     float* bias = nullptr; // float32 biases, layer l at bias_slot(l)
     float* scales = nullptr;   // [0..5] weight scales, [6..9] activation scales (FP8)
@@ -58,9 +59,10 @@ struct drc_cae {
 
 // Timing slots (drc_cae_profile_read): 0..5 forward GEMM of E1..D1,
 // 6..11 backward-data GEMM of E1..D1, 12..17 weight gradient of E1..D1,
-// 18 bias gradients, 19 L1 loss, 20 Adam and repack, 21 fused forward.
+// 18 bias gradients, 19 L1 loss, 20 Adam and repack, 21 fused forward, 22 fused
+// data-gradient chain.
 enum { PROF_FWD = 0, PROF_BWD = 6, PROF_WGRAD = 12, PROF_BIAS = 18, PROF_LOSS = 19, PROF_ADAM = 20,
-       PROF_FUSED = 21, PROF_SLOTS = 24 };
+       PROF_FUSED = 21, PROF_FUSED_BWD = 22, PROF_SLOTS = 24 };
 // Records the start event of a slot; returns a token for prof_end (or -1).
 long prof_begin(drc_cae* h, int slot, hipStream_t s);
 void prof_end(drc_cae* h, long token, hipStream_t s);
@@ -151,3 +153,8 @@ drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int
 // h2 -> h3, u3, u2 (the layers a recomputing backward rebuilds), all plain NHWC.
 drc_status fused_recompute(drc_cae* h, int n, int H, int W, const void* h2, void* h3, void* u3, void* u2,
                            hipStream_t s);
+// dy -> dz_u2, dh1s, dz_u3, dz_h3, dz_h2, dz_h1 (the data gradients of D1..E2)
+// in one kernel, from the saved activations u2 u3 h3 h2 h1 (plain NHWC BF16).
+drc_status fused_dgrad(drc_cae* h, int n, int H, int W, const float* dy, const void* u2, const void* u3,
+                       const void* h3, const void* h2, const void* h1, void* dz_u2, void* dh1s, void* dz_u3,
+                       void* dz_h3, void* dz_h2, void* dz_h1, hipStream_t s);

@@ -435,6 +435,10 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
     float* bpart = (float*)(ws + L.bpart);
     ActSizes as = act_sizes(P, n, H, W);
     float* dp = b.dparams;
+    // BF16 32x32 / 64x64: all data gradients of D1..E2 in one kernel first
+    const bool fdg = P == P_BF16 && h->fused && fused_forward_size(H, W);
+    if (fdg)
+        TRY(fused_dgrad(h, n, H, W, b.dy, b.u2, b.u3, b.h3, b.h2, b.h1, dz_u2, dh1s, dz_u3, dz_h3, dz_h2, dz_h1, s));
 
     // D1: y = tconv([u2|h1]); its data gradient is a stride-2 conv of dy.
     {
@@ -448,7 +452,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         G.seg0.mask = b.u2;
         G.seg0.ldm = 32;
         G.seg1 = seg_out(dh1s, 32, 0, 1.0f);
-        { const long tok = prof_begin(h, PROF_BWD + 5, s);
+        if (!fdg) { const long tok = prof_begin(h, PROF_BWD + 5, s);
         TRY(run_gemm<P>(5, true, a, fit_npw(default_npw(P, 5, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 5, s);
@@ -470,7 +474,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         G.seg0.mask = b.u3;
         G.seg0.ldm = 64;
         G.seg1 = seg_out(dh2s, 64, 0, 1.0f);
-        { const long tok = prof_begin(h, PROF_BWD + 4, s);
+        if (!fdg) { const long tok = prof_begin(h, PROF_BWD + 4, s);
         TRY(run_gemm<P>(4, true, a, fit_npw(default_npw(P, 4, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 4, s);
@@ -491,7 +495,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         G.seg0 = seg_out(dz_h3, 128, 0, 1.0f);
         G.seg0.mask = b.h3;
         G.seg0.ldm = 128;
-        { const long tok = prof_begin(h, PROF_BWD + 3, s);
+        if (!fdg) { const long tok = prof_begin(h, PROF_BWD + 3, s);
         TRY(run_gemm<P>(3, true, a, fit_npw(default_npw(P, 3, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 3, s);
@@ -514,7 +518,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         G.seg0.lda = 64;
         G.seg0.mask = b.h2;
         G.seg0.ldm = 64;
-        { const long tok = prof_begin(h, PROF_BWD + 2, s);
+        if (!fdg) { const long tok = prof_begin(h, PROF_BWD + 2, s);
         TRY(run_gemm<P>(2, true, a, fit_npw(default_npw(P, 2, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 2, s);
@@ -537,7 +541,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         G.seg0.lda = 32;
         G.seg0.mask = b.h1;
         G.seg0.ldm = 32;
-        { const long tok = prof_begin(h, PROF_BWD + 1, s);
+        if (!fdg) { const long tok = prof_begin(h, PROF_BWD + 1, s);
         TRY(run_gemm<P>(1, true, a, fit_npw(default_npw(P, 1, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
         { const long tok = prof_begin(h, PROF_WGRAD + 1, s);
