@@ -417,8 +417,11 @@ BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed) {
         colsum_split((long)n * hout * wout, &nb, &per);
         bp = std::max(bp, (size_t)nb * 128 * sizeof(float));
     }
+    // the whole-network data-gradient kernel keeps 323 bias partials per workgroup
+    bp = std::max(bp, (size_t)std::min(n, 2048) * 323 * sizeof(float));
     b.wpart = cur; cur += align256(wp);
     b.bpart = cur; cur += align256(bp);
+    b.bpart_bytes = bp;
     b.total = cur;
     return b;
 }

@@ -92,7 +92,7 @@ template <int C, int WO>
 struct LdsOut {
     char* smem;
     int region;
-    __device__ __forceinline__ void operator()(int ch, int y, int x, const f4& acc, const float* bias) const {
+    __device__ __forceinline__ void operator()(int, int ch, int y, int x, const f4& acc, const float* bias) const {
         lds_store4<C, WO>(smem, region, y, x, ch, acc, bias, true);
     }
 };
@@ -252,7 +252,7 @@ __device__ __forceinline__ void conv_phase(char* smem, int in, int zoff, const u
             const int ch = (tr * MT + m) * 16 + g * 4;
 #pragma unroll
             for (int p = 0; p < NPW; ++p)
-                epi(ch, oy[p], ox[p], acc[m][p], bias[m]);
+                epi(m, ch, oy[p], ox[p], acc[m][p], bias[m]);
         }
     }
 }
@@ -365,7 +365,7 @@ __device__ __forceinline__ void pairs_tiles(const PairsPanel<(C0 + C1) / 32, MT>
                     const int PP = PH0 + ph;
                     // output row, or its slot in a ring of ORING rows
                     const int orow = ORING ? (2 * ia[p] + (PP >> 1)) % (ORING > 0 ? ORING : 1) : 2 * ia[p] + (PP >> 1);
-                    epi(ch, orow, 2 * ib[p] + (PP & 1), acc[ph][m][p], P.bias[m]);
+                    epi(m, ch, orow, 2 * ib[p] + (PP & 1), acc[ph][m][p], P.bias[m]);
                 }
         }
     }
@@ -637,6 +637,7 @@ struct GSeg {
 };
 
 constexpr GSeg kNoSeg = {-1, nullptr, nullptr, nullptr, -1};
+constexpr int kBiasSlots = 323;  // biases of E1 E2 E3 D3 D2 D1 at 0, 32, 96, 224, 288, 320
 
 __device__ __forceinline__ void bf16x4_to_f32(uint2 w, float (&o)[4]) {
     o[0] = bf16_to_f32((uint16_t)(w.x & 0xffffu));
@@ -646,7 +647,8 @@ __device__ __forceinline__ void bf16x4_to_f32(uint2 w, float (&o)[4]) {
 }
 
 template <int C, int WO>
-__device__ __forceinline__ void grad_store(char* smem, const GSeg& sg, int lc, int y, int x, float (&v)[4]) {
+__device__ __forceinline__ void grad_store(char* smem, const GSeg& sg, int lc, int y, int x, float (&v)[4],
+                                           float* bsum) {
     const long pix = (long)y * WO + x;
     const int loffs = loff<C, WO>(y, x, lc >> 3) + ((lc >> 2) & 1) * 8;
     if (sg.gadd) {
@@ -672,22 +674,51 @@ __device__ __forceinline__ void grad_store(char* smem, const GSeg& sg, int lc, i
     w.y = (uint32_t)bf16_bits(v[2]) | ((uint32_t)bf16_bits(v[3]) << 16);
     if (sg.region >= 0) *(uint2*)(smem + sg.region + loffs) = w;
     if (sg.gdst) *(uint2*)(sg.gdst + pix * C + lc) = w;
+    if (bsum) {  // bias gradient: column sums of the stored (rounded) values
+        float r[4];
+        bf16x4_to_f32(w, r);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bsum[e] += r[e];
+    }
 }
 
 // Epilogue of a data-gradient GEMM whose rows are [segment 0 (C0 channels) |
 // segment 1 (C1 channels)], WO pixels per output row.
+// bsum (optional): per-lane sums of segment 0's stored values, 4 per row
+// block m of the wave (the bias gradient of the layer that produced them).
 template <int C0, int C1, int WO>
 struct GradOut {
     char* smem;
     GSeg s0, s1;
-    __device__ __forceinline__ void operator()(int ch, int y, int x, const f4& acc, const float* bias) const {
+    float* bsum;
+    __device__ __forceinline__ void operator()(int m, int ch, int y, int x, const f4& acc, const float* bias) const {
         float v[4] = {acc.x + bias[0], acc.y + bias[1], acc.z + bias[2], acc.w + bias[3]};
         if (C1 == 0 || ch < C0)
-            grad_store<C0, WO>(smem, s0, ch, y, x, v);
+            grad_store<C0, WO>(smem, s0, ch, y, x, v, bsum ? bsum + 4 * m : nullptr);
         else
-            grad_store<(C1 > 0 ? C1 : 8), WO>(smem, s1, ch - C0, y, x, v);
+            grad_store<(C1 > 0 ? C1 : 8), WO>(smem, s1, ch - C0, y, x, v, nullptr);
     }
 };
+
+// Adds a wave's per-lane column sums (4 per row block, MT row blocks of group
+// tr) into red[wave][slot0 + channel] for the channels below nrows: first over
+// the 16 lanes that share the channels (fixed butterfly), then one lane per
+// group of 4 channels writes.
+template <int MT>
+__device__ __forceinline__ void dump_bias(float* red, int slot0, const float* bsum, int tr, int nrows) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+#pragma unroll
+    for (int k = 0; k < 4 * MT; ++k) {
+        float v = bsum[k];
+        v += __shfl_xor(v, 1, 16);
+        v += __shfl_xor(v, 2, 16);
+        v += __shfl_xor(v, 4, 16);
+        v += __shfl_xor(v, 8, 16);
+        const int ch = (tr * MT + k / 4) * 16 + 4 * g + (k & 3);
+        if (r16 == 0 && ch < nrows) red[wave * kBiasSlots + slot0 + ch] = v;
+    }
+}
 
 struct DgradArgs {
     const float* dy;   // [n, H, W, 3] float32
@@ -695,11 +726,12 @@ struct DgradArgs {
     const uint16_t* w[6];  // backward-data packs in fragment order (layers 1..5 used)
     const uint16_t *u2, *u3, *h3, *h2, *h1;              // saved activations (masks)
     uint16_t *dz_u2, *dh1s, *dz_u3, *dz_h3, *dz_h2, *dz_h1;  // outputs
+    float* bias_part;  // [workgroup][kBiasSlots] column sums (bias gradients before the batch sum)
 };
 
 // dy (float32, 3 channels) -> LDS as BF16 with 8 channels (3..7 = 0).
 template <int H, int W>
-__device__ __forceinline__ void stage_dy(char* smem, int xs, const float* dm) {
+__device__ __forceinline__ void stage_dy(char* smem, int xs, const float* dm, float (&bs)[3]) {
     constexpr int Q = H * W / 4;  // groups of 4 pixels = 12 floats = 3 float4
     const int tid = opaque_tid();
     for (int q = tid; q < Q; q += FT) {
@@ -707,6 +739,10 @@ __device__ __forceinline__ void stage_dy(char* smem, int xs, const float* dm) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) v[k] = ((const float4*)dm)[q * 3 + k];
         const float* f = (const float*)v;
+#pragma unroll
+        for (int px = 0; px < 4; ++px)  // D1's bias gradient sums dy itself (float32)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) bs[c] += f[3 * px + c];
 #pragma unroll
         for (int px = 0; px < 4; ++px) {
             uint4 o;
@@ -730,37 +766,92 @@ __global__ __launch_bounds__(FT) void cae_fused_dgrad_kernel(const DgradArgs a) 
     constexpr int P5N = (HW / 1024) >= 4 ? 2 : 1;
     constexpr int P6N = (HW / 256) >= 16 ? 2 : 1;
     if (threadIdx.x < kZeroBytes / 16) *(uint4*)(smem + ZO + 16 * threadIdx.x) = uint4{0u, 0u, 0u, 0u};
+    // bias-gradient column sums over this workgroup's maps, per lane
+    float bs_u2[8] = {}, bs_u3[8] = {}, bs_h3[4] = {}, bs_h2[4] = {}, bs_h1[4] = {}, bs_dy[3] = {};
     for (int m = blockIdx.x; m < a.nmaps; m += gridDim.x) {
-        stage_dy<H, W>(smem, RA, a.dy + (long)m * HW * 3);
+        stage_dy<H, W>(smem, RA, a.dy + (long)m * HW * 3, bs_dy);
         __syncthreads();
         {   // D1^T: dy -> [dz_u2 (masked by u2) | dh1s]
             GradOut<32, 32, W / 2> e{smem, GSeg{RB, a.dz_u2 + m * S1, a.u2 + m * S1, nullptr, -1},
-                                     GSeg{-1, a.dh1s + m * S1, nullptr, nullptr, -1}};
+                                     GSeg{-1, a.dh1s + m * S1, nullptr, nullptr, -1}, bs_u2};
             conv_phase<H, W, 8, 64, 2, 4>(smem, RA, ZO, a.w[5], nullptr, e);
         }
         __syncthreads();
         {   // D2^T: dz_u2 -> [dz_u3 (masked by u3) | dh2s]
             GradOut<64, 64, W / 4> e{smem, GSeg{RA, a.dz_u3 + m * S2, a.u3 + m * S2, nullptr, -1},
-                                     GSeg{RA + 8 * HW, nullptr, nullptr, nullptr, -1}};
+                                     GSeg{RA + 8 * HW, nullptr, nullptr, nullptr, -1}, bs_u3};
             conv_phase<H / 2, W / 2, 32, 128, 2, P3N>(smem, RB, ZO, a.w[4], nullptr, e);
         }
         __syncthreads();
         {   // D3^T: dz_u3 -> dz_h3 (masked by h3)
-            GradOut<128, 0, W / 8> e{smem, GSeg{RB, a.dz_h3 + m * S3, a.h3 + m * S3, nullptr, -1}, kNoSeg};
+            GradOut<128, 0, W / 8> e{smem, GSeg{RB, a.dz_h3 + m * S3, a.h3 + m * S3, nullptr, -1}, kNoSeg, bs_h3};
             conv_phase<H / 4, W / 4, 64, 128, 1, P4N>(smem, RA, ZO, a.w[3], nullptr, e);
         }
         __syncthreads();
         {   // E3^T: dz_h3 -> dz_h2 = (. + dh2s) masked by h2
             GradOut<64, 0, W / 4> e{smem, GSeg{RB + 4 * HW, a.dz_h2 + m * S2, a.h2 + m * S2, nullptr, RA + 8 * HW},
-                                    kNoSeg};
+                                    kNoSeg, bs_h2};
             pairs_phase<H / 8, W / 8, 128, 0, 64, 1, P5N>(smem, RB, RB, ZO, a.w[2], nullptr, e);
         }
         __syncthreads();
         {   // E2^T: dz_h2 -> dz_h1 = (. + dh1s) masked by h1
-            GradOut<32, 0, W / 2> e{smem, GSeg{-1, a.dz_h1 + m * S1, a.h1 + m * S1, a.dh1s + m * S1, -1}, kNoSeg};
+            GradOut<32, 0, W / 2> e{smem, GSeg{-1, a.dz_h1 + m * S1, a.h1 + m * S1, a.dh1s + m * S1, -1}, kNoSeg,
+                                    bs_h1};
             pairs_phase<H / 4, W / 4, 64, 0, 32, 1, P6N>(smem, RB + 4 * HW, RB + 4 * HW, ZO, a.w[1], nullptr, e);
         }
         __syncthreads();
+    }
+    // Per-workgroup bias partials: lanes -> red[wave][slot] (LDS) -> fixed-order sums over the waves.
+    // The row-block group of each wave per layer is the one the phase functions used.
+    float* red = (float*)smem;
+    float* rdy = red + FW * kBiasSlots;
+    for (int i = threadIdx.x; i < FW * kBiasSlots; i += FT) red[i] = 0.0f;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    dump_bias<2>(red, 288, bs_u2, (wave + blockIdx.x) % 2, 32);   // D2 bias: dz_u2 (rows 0-31 of D1^T)
+    dump_bias<2>(red, 224, bs_u3, (wave + blockIdx.x) % 4, 64);   // D3 bias: dz_u3 (rows 0-63 of D2^T)
+    dump_bias<1>(red, 96, bs_h3, (wave + blockIdx.x) % 8, 128);   // E3 bias: dz_h3
+    dump_bias<1>(red, 32, bs_h2, ((wave + blockIdx.x) % 8) >> 1, 64);  // E2 bias: dz_h2 (pairs: group = 2 tr + set)
+    dump_bias<1>(red, 0, bs_h1, ((wave + blockIdx.x) % 4) >> 1, 32);   // E1 bias: dz_h1
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rdy[threadIdx.x * 3 + c] = bs_dy[c];
+    __syncthreads();
+    if (threadIdx.x < kBiasSlots) {
+        const int c = threadIdx.x;
+        float v = 0.0f;
+        if (c < 320) {
+            for (int w = 0; w < FW; ++w) v += red[w * kBiasSlots + c];
+        } else {
+            for (int t = 0; t < FT; ++t) v += rdy[t * 3 + (c - 320)];
+        }
+        a.bias_part[(long)blockIdx.x * kBiasSlots + c] = v;
+    }
+}
+
+// Bias gradients from the per-workgroup partials: dparams[bias of layer l][i]
+// = scale * (sum over workgroups, in order) of partial[.][slot(l) + i].
+struct BiasFinalArgs {
+    const float* part;
+    int nrows;
+    float scale;
+    float* dparams;
+    long boff[6];  // offsets of the six bias vectors in dparams
+};
+__global__ __launch_bounds__(256) void bias_final_kernel(const BiasFinalArgs a) {
+    __shared__ float red[256];
+    const int c = blockIdx.x;
+    float s = 0.0f;
+    for (int r = threadIdx.x; r < a.nrows; r += 256) s += a.part[(long)r * kBiasSlots + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int l = c < 32 ? 0 : c < 96 ? 1 : c < 224 ? 2 : c < 288 ? 3 : c < 320 ? 4 : 5;
+        const int s0[6] = {0, 32, 96, 224, 288, 320};
+        a.dparams[a.boff[l] + (c - s0[l])] = red[0] * a.scale;
     }
 }
 
@@ -856,10 +947,15 @@ drc_status fused_recompute(drc_cae* h, int n, int H, int W, const void* h2, void
 
 drc_status fused_dgrad(drc_cae* h, int n, int H, int W, const float* dy, const void* u2, const void* u3,
                        const void* h3, const void* h2, const void* h1, void* dz_u2, void* dh1s, void* dz_u3,
-                       void* dz_h3, void* dz_h2, void* dz_h1, hipStream_t s) {
+                       void* dz_h3, void* dz_h2, void* dz_h1, float* bias_part, size_t bias_part_bytes,
+                       float* dparams, float gscale, hipStream_t s) {
     if (h->prec != P_BF16 || !fused_forward_size(H, W))
         return drc_fail(DRC_ERR_UNSUPPORTED, "fused dgrad: BF16 maps of 32x32 or 64x64 only");
     if (n < 1) return DRC_OK;
+    const int grid = fused_forward_grid(h, n, H, W);
+    if ((size_t)grid * kBiasSlots * sizeof(float) > bias_part_bytes)
+        return drc_fail(DRC_ERR_WORKSPACE, "fused dgrad: bias partials need %zu bytes",
+                        (size_t)grid * kBiasSlots * sizeof(float));
     DgradArgs a;
     memset(&a, 0, sizeof a);
     a.dy = dy;
@@ -876,9 +972,19 @@ drc_status fused_dgrad(drc_cae* h, int n, int H, int W, const float* dy, const v
     a.dz_h3 = (uint16_t*)dz_h3;
     a.dz_h2 = (uint16_t*)dz_h2;
     a.dz_h1 = (uint16_t*)dz_h1;
-    const int grid = fused_forward_grid(h, n, H, W);
+    a.bias_part = bias_part;
     const long tok = prof_begin(h, PROF_FUSED_BWD, s);
     drc_status st = (H == 64) ? launch_dgrad<64, 64>(a, grid, s) : launch_dgrad<32, 32>(a, grid, s);
     prof_end(h, tok, s);
-    return st;
+    if (st != DRC_OK) return st;
+    BiasFinalArgs b;
+    b.part = bias_part;
+    b.nrows = grid;
+    b.scale = gscale;
+    b.dparams = dparams;
+    for (int l = 0; l < 6; ++l) b.boff[l] = layer_b_offset(l);
+    const long tb = prof_begin(h, PROF_BIAS, s);
+    hipLaunchKernelGGL(bias_final_kernel, dim3(kBiasSlots), dim3(256), 0, s, b);
+    prof_end(h, tb, s);
+    return check_launch("fused dgrad/bias");
 }

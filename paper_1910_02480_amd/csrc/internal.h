@@ -75,7 +75,7 @@ struct ActSizes {
 struct BwdLayout {
     size_t recomp[3];
     size_t dz_u2, dh1s, dz_u3, dh2s, dz_h3, dz_h2, dz_h1;
-    size_t wpart, bpart, total;
+    size_t wpart, bpart, bpart_bytes, total;
 };
 
 struct StepLayout {
@@ -154,7 +154,10 @@ drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int
 drc_status fused_recompute(drc_cae* h, int n, int H, int W, const void* h2, void* h3, void* u3, void* u2,
                            hipStream_t s);
 // dy -> dz_u2, dh1s, dz_u3, dz_h3, dz_h2, dz_h1 (the data gradients of D1..E2)
-// in one kernel, from the saved activations u2 u3 h3 h2 h1 (plain NHWC BF16).
+// in one kernel, from the saved activations u2 u3 h3 h2 h1 (plain NHWC BF16);
+// it also forms every bias gradient (column sums of dy and of the stored
+// output gradients), written scaled by gscale into dparams.
 drc_status fused_dgrad(drc_cae* h, int n, int H, int W, const float* dy, const void* u2, const void* u3,
                        const void* h3, const void* h2, const void* h1, void* dz_u2, void* dh1s, void* dz_u3,
-                       void* dz_h3, void* dz_h2, void* dz_h1, hipStream_t s);
+                       void* dz_h3, void* dz_h2, void* dz_h1, float* bias_part, size_t bias_part_bytes,
+                       float* dparams, float gscale, hipStream_t s);

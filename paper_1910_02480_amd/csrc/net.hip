@@ -438,7 +438,8 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
     // BF16 32x32 / 64x64: all data gradients of D1..E2 in one kernel first
     const bool fdg = P == P_BF16 && h->fused && fused_forward_size(H, W);
     if (fdg)
-        TRY(fused_dgrad(h, n, H, W, b.dy, b.u2, b.u3, b.h3, b.h2, b.h1, dz_u2, dh1s, dz_u3, dz_h3, dz_h2, dz_h1, s));
+        TRY(fused_dgrad(h, n, H, W, b.dy, b.u2, b.u3, b.h3, b.h2, b.h1, dz_u2, dh1s, dz_u3, dz_h3, dz_h2, dz_h1,
+                        bpart, L.bpart_bytes, dp, gscale, s));
 
     // D1: y = tconv([u2|h1]); its data gradient is a stride-2 conv of dy.
     {
@@ -459,7 +460,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         TRY(weight_grad<T>(5, n, H, W, b.dy, true, Src{b.u2, 32, 32}, Src{b.h1, 32, 32}, 0, wpart,
                            dp + layer_w_offset(5), gscale, s));
         prof_end(h, tok, s); }
-        { const long tok = prof_begin(h, PROF_BIAS, s);
+        if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(b.dy, true, 3, as.p0, bpart, dp + layer_b_offset(5), gscale, s));
         prof_end(h, tok, s); }
     }
@@ -481,7 +482,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         TRY(weight_grad<T>(4, n, H, W, dz_u2, false, Src{b.u3, 64, 64}, Src{b.h2, 64, 64}, 0, wpart,
                            dp + layer_w_offset(4), gscale, s));
         prof_end(h, tok, s); }
-        { const long tok = prof_begin(h, PROF_BIAS, s);
+        if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_u2, false, 32, as.p1, bpart, dp + layer_b_offset(4), gscale, s));
         prof_end(h, tok, s); }
     }
@@ -502,7 +503,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         TRY(weight_grad<T>(3, n, H, W, dz_u3, false, Src{b.h3, 128, 128}, Src{nullptr, 0, 0}, 0, wpart,
                            dp + layer_w_offset(3), gscale, s));
         prof_end(h, tok, s); }
-        { const long tok = prof_begin(h, PROF_BIAS, s);
+        if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_u3, false, 64, as.p2, bpart, dp + layer_b_offset(3), gscale, s));
         prof_end(h, tok, s); }
     }
@@ -525,7 +526,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         TRY(weight_grad<T>(2, n, H, W, dz_h3, false, Src{b.h2, 64, 64}, Src{nullptr, 0, 0}, 0, wpart,
                            dp + layer_w_offset(2), gscale, s));
         prof_end(h, tok, s); }
-        { const long tok = prof_begin(h, PROF_BIAS, s);
+        if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_h3, false, 128, as.p3, bpart, dp + layer_b_offset(2), gscale, s));
         prof_end(h, tok, s); }
     }
@@ -548,7 +549,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         TRY(weight_grad<T>(1, n, H, W, dz_h2, false, Src{b.h1, 32, 32}, Src{nullptr, 0, 0}, 0, wpart,
                            dp + layer_w_offset(1), gscale, s));
         prof_end(h, tok, s); }
-        { const long tok = prof_begin(h, PROF_BIAS, s);
+        if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_h2, false, 64, as.p2, bpart, dp + layer_b_offset(1), gscale, s));
         prof_end(h, tok, s); }
     }
@@ -558,7 +559,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         TRY(weight_grad<T>(0, n, H, W, dz_h1, false, Src{b.x, 7, 7}, Src{nullptr, 0, 0}, 7, wpart,
                            dp + layer_w_offset(0), gscale, s));
         prof_end(h, tok, s); }
-        { const long tok = prof_begin(h, PROF_BIAS, s);
+        if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_h1, false, 32, as.p1, bpart, dp + layer_b_offset(0), gscale, s));
         prof_end(h, tok, s); }
         if (b.dx) {
