@@ -413,6 +413,24 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
 // Wave w owns the (tap, channel) row blocks w, w+4, ... and all PB column
 // blocks, accumulating over the workgroup's strips; each workgroup writes
 // its own partial tile (summed later in a fixed order).
+// 8 x 8 transpose of 16-bit elements: in[i] holds elements 0..7 of row i,
+// out[c] holds element c of rows 0..7.
+__device__ __forceinline__ void transpose8x8_b16(const uint4 (&in)[8], uint4 (&out)[8]) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        uint32_t o[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint4& r0 = in[2 * j];
+            const uint4& r1 = in[2 * j + 1];
+            const uint32_t a = (c >> 1) == 0 ? r0.x : (c >> 1) == 1 ? r0.y : (c >> 1) == 2 ? r0.z : r0.w;
+            const uint32_t b = (c >> 1) == 0 ? r1.x : (c >> 1) == 1 ? r1.y : (c >> 1) == 2 ? r1.z : r1.w;
+            o[j] = (c & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+        }
+        out[c] = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+}
+
 struct WgradBArgs {
     const void* p; const void* p2;  // plain operand (bf16), channels [0, pc0) from p, the rest from p2
     int pc, pc0, pld, p2ld;
@@ -461,65 +479,119 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradBArgs a) {
         const int n = s / a.strips_per_map;
         const int u0 = (s - n * a.strips_per_map) * R;
         __syncthreads();  // the previous strip's LDS reads are done
-        // ---- stage the gathered operand (three column views)
-        const int ncols = 2 * Wr + 1;  // columns -1 .. 2 Wr - 1
-        constexpr int CG = QCP / 8;
-        for (int e = threadIdx.x; e < qrows * ncols * CG; e += 256) {
-            const int cg = e % CG;
-            const int rest = e / CG;
-            const int colp = rest % ncols, row = rest / ncols;
-            const int qi = 2 * u0 - 1 + row, qj = colp - 1;
-            float v8[8];
+        if constexpr (QCP == 8) {
+            // few channels (raw float32 input or gradient): one thread per loaded pixel
+            // ---- stage the gathered operand (three column views)
+            const int ncols = 2 * Wr + 1;  // columns -1 .. 2 Wr - 1
+            constexpr int CG = QCP / 8;
+            for (int e = threadIdx.x; e < qrows * ncols * CG; e += 256) {
+                const int cg = e % CG;
+                const int rest = e / CG;
+                const int colp = rest % ncols, row = rest / ncols;
+                const int qi = 2 * u0 - 1 + row, qj = colp - 1;
+                float v8[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) v8[k] = 0.0f;
-            if ((unsigned)qi < (unsigned)a.Hq && (unsigned)qj < (unsigned)a.Wq) {
-                const long base = (((long)n * a.Hq + qi) * a.Wq + qj) * a.qld + cg * 8;
-                if (a.q_raw) {
+                for (int k = 0; k < 8; ++k) v8[k] = 0.0f;
+                if ((unsigned)qi < (unsigned)a.Hq && (unsigned)qj < (unsigned)a.Wq) {
+                    const long base = (((long)n * a.Hq + qi) * a.Wq + qj) * a.qld + cg * 8;
+                    if (a.q_raw) {
 #pragma unroll
-                    for (int k = 0; k < 8; ++k)
-                        if (cg * 8 + k < a.qc) v8[k] = ((const float*)a.q)[base + k];
-                } else {
-                    const uint4 w = *(const uint4*)((const uint16_t*)a.q + base);
-                    const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+                        for (int k = 0; k < 8; ++k)
+                            if (cg * 8 + k < a.qc) v8[k] = ((const float*)a.q)[base + k];
+                    } else {
+                        const uint4 w = *(const uint4*)((const uint16_t*)a.q + base);
+                        const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        v8[2 * k] = bf16_to_f32((uint16_t)(ww[k] & 0xffffu));
-                        v8[2 * k + 1] = bf16_to_f32((uint16_t)(ww[k] >> 16));
+                        for (int k = 0; k < 4; ++k) {
+                            v8[2 * k] = bf16_to_f32((uint16_t)(ww[k] & 0xffffu));
+                            v8[2 * k + 1] = bf16_to_f32((uint16_t)(ww[k] >> 16));
+                        }
+                    }
+                }
+                // column qj feeds view kw at v = (qj + 1 - kw) / 2 when that is an integer in [0, Wr)
+#pragma unroll
+                for (int kw = 0; kw < 3; ++kw) {
+                    const int t2 = qj + 1 - kw;
+                    if (t2 < 0 || (t2 & 1)) continue;
+                    const int v = t2 >> 1;
+                    if (v >= Wr) continue;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const __bf16 b = (__bf16)v8[k];
+                        Qs[(size_t)(cg * 8 + k) * a.qcs + (row * 3 + kw) * Wr + v] = __builtin_bit_cast(uint16_t, b);
                     }
                 }
             }
-            // column qj feeds view kw at v = (qj + 1 - kw) / 2 when that is an integer in [0, Wr)
+        } else {
+            // ---- stage the gathered operand (three column views). A task reads 17
+            // consecutive columns (16 b - 1 .. 16 b + 15) of one row for 8 channels
+            // and writes, per view, 8 consecutive v of each channel (v in [8 b, 8 b + 8)):
+            // view kw takes column 2 v + kw - 1, i.e. task column 2 i + kw. Each
+            // view is an 8 x 8 transpose in registers and 8 16-byte LDS writes.
+            constexpr int CG = QCP / 8;
+            const int ncb = Wr / 8;
+            for (int e = threadIdx.x; e < qrows * ncb * CG; e += 256) {
+                const int cg = e % CG;
+                const int rest = e / CG;
+                const int cb = rest % ncb, row = rest / ncb;
+                const int qi = 2 * u0 - 1 + row;
+                const bool row_ok = (unsigned)qi < (unsigned)a.Hq;
+                uint4 col[17];
 #pragma unroll
-            for (int kw = 0; kw < 3; ++kw) {
-                const int t2 = qj + 1 - kw;
-                if (t2 < 0 || (t2 & 1)) continue;
-                const int v = t2 >> 1;
-                if (v >= Wr) continue;
+                for (int t = 0; t < 17; ++t) {
+                    const int qj = 16 * cb - 1 + t;
+                    col[t] = make_uint4(0, 0, 0, 0);
+                    if (row_ok && (unsigned)qj < (unsigned)a.Wq) {
+                        const long base = (((long)n * a.Hq + qi) * a.Wq + qj) * a.qld + cg * 8;
+                        if (a.q_raw) {
+                            uint16_t h8[8];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const __bf16 b = (__bf16)v8[k];
-                    Qs[(size_t)(cg * 8 + k) * a.qcs + (row * 3 + kw) * Wr + v] = __builtin_bit_cast(uint16_t, b);
+                            for (int k = 0; k < 8; ++k) {
+                                const float f = cg * 8 + k < a.qc ? ((const float*)a.q)[base + k] : 0.0f;
+                                h8[k] = __builtin_bit_cast(uint16_t, (__bf16)f);
+                            }
+                            col[t] = make_uint4((uint32_t)h8[0] | ((uint32_t)h8[1] << 16),
+                                                (uint32_t)h8[2] | ((uint32_t)h8[3] << 16),
+                                                (uint32_t)h8[4] | ((uint32_t)h8[5] << 16),
+                                                (uint32_t)h8[6] | ((uint32_t)h8[7] << 16));
+                        } else {
+                            col[t] = *(const uint4*)((const uint16_t*)a.q + base);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int kw = 0; kw < 3; ++kw) {
+                    uint4 in[8], out[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) in[i] = col[2 * i + kw];
+                    transpose8x8_b16(in, out);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        *(uint4*)(Qs + (size_t)(cg * 8 + c) * a.qcs + (row * 3 + kw) * Wr + 8 * cb) = out[c];
                 }
             }
         }
-        // ---- stage the plain operand, transposed
-        for (int e = threadIdx.x; e < K * PB * 2; e += 256) {
+        // ---- stage the plain operand, transposed: a task reads 8 consecutive
+        // reduction pixels (one row, Wr % 8 == 0) x 8 channels and writes 8
+        // channels x 8 pixels
+        for (int e = threadIdx.x; e < (K / 8) * PB * 2; e += 256) {
             const int cg = e % (PB * 2);
-            const int k = e / (PB * 2);
+            const int k = (e / (PB * 2)) * 8;
             const int u = u0 + k / Wr, v = k % Wr;
             const int c = cp0 + cg * 8;
-            uint4 w = make_uint4(0, 0, 0, 0);
-            if (u < a.Hr && c < a.pc) {
-                const long pix = ((long)n * a.Hr + u) * a.Wr + v;
-                w = (c < a.pc0) ? *(const uint4*)((const uint16_t*)a.p + pix * a.pld + c)
-                                : *(const uint4*)((const uint16_t*)a.p2 + pix * a.p2ld + (c - a.pc0));
-            }
-            const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+            uint4 in[8], out[8];
 #pragma unroll
-            for (int k2 = 0; k2 < 4; ++k2) {
-                Pt[(size_t)(cg * 8 + 2 * k2) * ptld + k] = (uint16_t)(ww[k2] & 0xffffu);
-                Pt[(size_t)(cg * 8 + 2 * k2 + 1) * ptld + k] = (uint16_t)(ww[k2] >> 16);
+            for (int i = 0; i < 8; ++i) {
+                in[i] = make_uint4(0, 0, 0, 0);
+                if (u < a.Hr && c < a.pc) {
+                    const long pix = ((long)n * a.Hr + u) * a.Wr + v + i;
+                    in[i] = (c < a.pc0) ? *(const uint4*)((const uint16_t*)a.p + pix * a.pld + c)
+                                        : *(const uint4*)((const uint16_t*)a.p2 + pix * a.p2ld + (c - a.pc0));
+                }
             }
+            transpose8x8_b16(in, out);
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc) *(uint4*)(Pt + (size_t)(cg * 8 + cc) * ptld + k) = out[cc];
         }
         __syncthreads();
         // ---- MFMAs over the strip
