@@ -88,11 +88,17 @@ __device__ __forceinline__ void lds_store4(char* smem, int region, int y, int x,
 __device__ __forceinline__ void mma(f4& acc, const uint4& a, const uint4& b) { Traits<P_BF16>::mma(acc, a, b); }
 
 // Forward epilogue: bias + ReLU, BF16 into an LDS tensor of C channels, WO wide.
+// Epilogue interface: prefetch(pre, m, ch, y, x) at the start of a tile
+// (global inputs of the epilogue, in flight during the tile's MFMAs), then
+// operator()(pre, m, ch, y, x, acc, bias) after the K loop.
 template <int C, int WO>
 struct LdsOut {
     char* smem;
     int region;
-    __device__ __forceinline__ void operator()(int, int ch, int y, int x, const f4& acc, const float* bias) const {
+    struct Pre {};
+    __device__ __forceinline__ void prefetch(Pre&, int, int, int, int) const {}
+    __device__ __forceinline__ void operator()(const Pre&, int, int ch, int y, int x, const f4& acc,
+                                               const float* bias) const {
         lds_store4<C, WO>(smem, region, y, x, ch, acc, bias, true);
     }
 };
@@ -223,6 +229,11 @@ __device__ __forceinline__ void conv_phase(char* smem, int in, int zoff, const u
                 }
             }
         }
+        typename Epi::Pre pre[MT][NPW];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) epi.prefetch(pre[m][p], m, (tr * MT + m) * 16 + g * 4, oy[p], ox[p]);
         f4 acc[MT][NPW];
 #pragma unroll
         for (int m = 0; m < MT; ++m)
@@ -252,7 +263,7 @@ __device__ __forceinline__ void conv_phase(char* smem, int in, int zoff, const u
             const int ch = (tr * MT + m) * 16 + g * 4;
 #pragma unroll
             for (int p = 0; p < NPW; ++p)
-                epi(m, ch, oy[p], ox[p], acc[m][p], bias[m]);
+                epi(pre[m][p], m, ch, oy[p], ox[p], acc[m][p], bias[m]);
         }
     }
 }
@@ -330,6 +341,19 @@ __device__ __forceinline__ void pairs_tiles(const PairsPanel<(C0 + C1) / 32, MT>
                     off[p][s][2 + dj] = ((dj && !right) || !down) ? zoff : b + ROW;
                 }
         }
+        // output row of phase PP (or its slot in a ring of ORING rows) and column
+        auto orow_of = [&](int p, int PP) {
+            return ORING ? (2 * ia[p] + (PP >> 1)) % (ORING > 0 ? ORING : 1) : 2 * ia[p] + (PP >> 1);
+        };
+        typename Epi::Pre pre[NPH][MT][NPW];
+#pragma unroll
+        for (int ph = 0; ph < NPH; ++ph)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int p = 0; p < NPW; ++p)
+                    epi.prefetch(pre[ph][m][p], m, (tr * MT + m) * 16 + g * 4, orow_of(p, PH0 + ph),
+                                 2 * ib[p] + ((PH0 + ph) & 1));
         f4 acc[NPH][MT][NPW];
 #pragma unroll
         for (int ph = 0; ph < NPH; ++ph)
@@ -363,9 +387,7 @@ __device__ __forceinline__ void pairs_tiles(const PairsPanel<(C0 + C1) / 32, MT>
 #pragma unroll
                 for (int p = 0; p < NPW; ++p) {
                     const int PP = PH0 + ph;
-                    // output row, or its slot in a ring of ORING rows
-                    const int orow = ORING ? (2 * ia[p] + (PP >> 1)) % (ORING > 0 ? ORING : 1) : 2 * ia[p] + (PP >> 1);
-                    epi(m, ch, orow, 2 * ib[p] + (PP & 1), acc[ph][m][p], P.bias[m]);
+                    epi(pre[ph][m][p], m, ch, orow_of(p, PP), 2 * ib[p] + (PP & 1), acc[ph][m][p], P.bias[m]);
                 }
         }
     }
@@ -646,14 +668,26 @@ __device__ __forceinline__ void bf16x4_to_f32(uint2 w, float (&o)[4]) {
     o[3] = bf16_to_f32((uint16_t)(w.y >> 16));
 }
 
+// Global epilogue inputs of one 4-channel store, fetched ahead of the tile.
+struct GradPre {
+    uint2 mk, ad;
+};
+
 template <int C, int WO>
-__device__ __forceinline__ void grad_store(char* smem, const GSeg& sg, int lc, int y, int x, float (&v)[4],
-                                           float* bsum) {
+__device__ __forceinline__ void grad_prefetch(const GSeg& sg, int lc, int y, int x, GradPre& pr) {
+    const long pix = (long)y * WO + x;
+    if (sg.mask) pr.mk = *(const uint2*)(sg.mask + pix * C + lc);
+    if (sg.gadd) pr.ad = *(const uint2*)(sg.gadd + pix * C + lc);
+}
+
+template <int C, int WO>
+__device__ __forceinline__ void grad_store(char* smem, const GSeg& sg, const GradPre& pr, int lc, int y, int x,
+                                           float (&v)[4], float* bsum) {
     const long pix = (long)y * WO + x;
     const int loffs = loff<C, WO>(y, x, lc >> 3) + ((lc >> 2) & 1) * 8;
     if (sg.gadd) {
         float ad[4];
-        bf16x4_to_f32(*(const uint2*)(sg.gadd + pix * C + lc), ad);
+        bf16x4_to_f32(pr.ad, ad);
 #pragma unroll
         for (int e = 0; e < 4; ++e) v[e] += ad[e];
     }
@@ -665,7 +699,7 @@ __device__ __forceinline__ void grad_store(char* smem, const GSeg& sg, int lc, i
     }
     if (sg.mask) {
         float mk[4];
-        bf16x4_to_f32(*(const uint2*)(sg.mask + pix * C + lc), mk);
+        bf16x4_to_f32(pr.mk, mk);
 #pragma unroll
         for (int e = 0; e < 4; ++e) v[e] = (mk[e] > 0.0f) ? v[e] : 0.0f;
     }
@@ -691,12 +725,20 @@ struct GradOut {
     char* smem;
     GSeg s0, s1;
     float* bsum;
-    __device__ __forceinline__ void operator()(int m, int ch, int y, int x, const f4& acc, const float* bias) const {
+    typedef GradPre Pre;
+    __device__ __forceinline__ void prefetch(Pre& pr, int, int ch, int y, int x) const {
+        if (C1 == 0 || ch < C0)
+            grad_prefetch<C0, WO>(s0, ch, y, x, pr);
+        else
+            grad_prefetch<(C1 > 0 ? C1 : 8), WO>(s1, ch - C0, y, x, pr);
+    }
+    __device__ __forceinline__ void operator()(const Pre& pr, int m, int ch, int y, int x, const f4& acc,
+                                               const float* bias) const {
         float v[4] = {acc.x + bias[0], acc.y + bias[1], acc.z + bias[2], acc.w + bias[3]};
         if (C1 == 0 || ch < C0)
-            grad_store<C0, WO>(smem, s0, ch, y, x, v, bsum ? bsum + 4 * m : nullptr);
+            grad_store<C0, WO>(smem, s0, pr, ch, y, x, v, bsum ? bsum + 4 * m : nullptr);
         else
-            grad_store<(C1 > 0 ? C1 : 8), WO>(smem, s1, ch - C0, y, x, v, nullptr);
+            grad_store<(C1 > 0 ? C1 : 8), WO>(smem, s1, pr, ch - C0, y, x, v, nullptr);
     }
 };
 
