@@ -226,6 +226,10 @@ __device__ __forceinline__ void conv_phase(char* smem, int in, int zoff, const u
 #pragma unroll
                     for (int kh = 0; kh < 3; ++kh)
                         off[p][kh * 3 + kw] = ((kh == 0 && !top) || (kw == 0 && !left)) ? zoff : b + kh * ROW;
+                    // a pixel block is one output row here: the top taps of row oy + 1
+                    // are the bottom taps of row oy, so the same offsets (and loads) serve
+                    if constexpr (WO == 16)
+                        if (p > 0) off[p][kw] = off[p - 1][6 + kw];
                 }
             }
         }
@@ -339,6 +343,10 @@ __device__ __forceinline__ void pairs_tiles(const PairsPanel<(C0 + C1) / 32, MT>
                     const int b = (s ? in1 : in0) + loff<C0, WI>(ia[p], ib[p] + dj, g);
                     off[p][s][dj] = (dj && !right) ? zoff : b;
                     off[p][s][2 + dj] = ((dj && !right) || !down) ? zoff : b + ROW;
+                    // a pixel block is one input row here: its upper neighbours are the
+                    // lower neighbours of the block above, so the same offsets (and loads) serve
+                    if constexpr (WI == 16)
+                        if (p > 0) off[p][s][dj] = off[p - 1][s][2 + dj];
                 }
         }
         // output row of phase PP (or its slot in a ring of ORING rows) and column
