@@ -23,6 +23,7 @@ struct PackArgs {
     int prec;
     const float* scale; // FP8: device pointer to the weight scale, else null
     void* dst;
+    void* frag;         // BF16: optional second copy in MFMA fragment order (kstride % 32 == 0)
 };
 
 // Weight pack element e of the layout [blk][row][k]:
@@ -32,12 +33,15 @@ struct PackArgs {
 //                  zero where the phase does not use the neighbour.
 // Forward pack: row = co, c = ci. Transposed pack (backward data pass):
 // row = ci, c = co.
-static __global__ void pack_weights_kernel(PackArgs a) {
+//
+// The fragment-ordered copy: fragment (row block rb, K step ks) is 64 lanes
+// x 8 elements, lane g * 16 + r holding row 16 rb + r, K [32 ks + 8 g, +8),
+// so one wave loads a whole MFMA A fragment as 1 KB of contiguous memory.
+__device__ __forceinline__ void pack_range(const PackArgs& a, long e0, long step) {
     const long total = (long)a.nblk * a.rows_pad * a.kstride;
     const int rows = a.transpose ? a.cin : a.cout;
     const int chans = a.transpose ? a.cout : a.cin;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-         e += (long)gridDim.x * blockDim.x) {
+    for (long e = e0; e < total; e += step) {
         const int k = (int)(e % a.kstride);
         int row = (int)((e / a.kstride) % a.rows_pad);
         const int blk = (int)(e / ((long)a.kstride * a.rows_pad));
@@ -71,13 +75,41 @@ static __global__ void pack_weights_kernel(PackArgs a) {
             const int ci = a.transpose ? row : c;
             v = a.w[((co * 3 + kh) * 3 + kw) * a.cin + ci];
         }
-        if (a.prec == P_F32)
+        if (a.prec == P_F32) {
             ((float*)a.dst)[e] = v;
-        else if (a.prec == P_BF16)
-            ((uint16_t*)a.dst)[e] = f32_to_bf16(v);
-        else
+        } else if (a.prec == P_BF16) {
+            const uint16_t hb = f32_to_bf16(v);
+            ((uint16_t*)a.dst)[e] = hb;
+            if (a.frag) {
+                const long R = e / a.kstride;  // row over all blocks
+                const int ksteps = a.kstride / 32, kk = k & 31;
+                const long f = ((R / 16) * ksteps + k / 32) * 64 + (kk >> 3) * 16 + (R & 15);
+                ((uint16_t*)a.frag)[f * 8 + (kk & 7)] = hb;
+            }
+        } else {
             ((uint8_t*)a.dst)[e] = f32_to_e4m3(v * a.scale[0]);
+        }
     }
+}
+
+// Every pack of a handle in one launch: blockIdx.y selects the pack; the
+// last y index copies the biases (float32) into their compact slots.
+constexpr int kMaxPacks = 18;
+struct PackAllArgs {
+    PackArgs p[kMaxPacks];
+    int np;
+    const float* bsrc[6];  // bias vectors of E1..D1 in the parameter vector
+    int bcount[6], bslot[6];
+    float* bdst;
+};
+static __global__ void pack_all_kernel(const PackAllArgs a) {
+    const long e0 = blockIdx.x * (long)blockDim.x + threadIdx.x, step = (long)gridDim.x * blockDim.x;
+    if ((int)blockIdx.y < a.np) {
+        pack_range(a.p[blockIdx.y], e0, step);
+        return;
+    }
+    for (int l = 0; l < 6; ++l)
+        for (long i = e0; i < a.bcount[l]; i += step) a.bdst[a.bslot[l] + i] = a.bsrc[l][i];
 }
 
 // ------------------------------------------------------------------ amax
@@ -138,22 +170,6 @@ static __global__ void l1_final_kernel(const double* partial, int nparts, long c
         __syncthreads();
     }
     if (threadIdx.x == 0) loss[0] = (float)(red[0] / (double)count);
-}
-
-// Reorders a BF16 weight pack [rows][ksteps * 32] into MFMA fragment order:
-// fragment (row block rb, K step ks) is 64 lanes x 16 bytes, lane g * 16 + r
-// holding row 16 rb + r, K elements [32 ks + 8 g, +8). One wave then loads a
-// whole fragment as 1 KB of contiguous memory.
-static __global__ void frag_order_kernel(const uint4* src, uint4* dst, int rows, int ksteps) {
-    const long total = (long)rows * ksteps * 4;
-    for (long u = blockIdx.x * (long)blockDim.x + threadIdx.x; u < total; u += (long)gridDim.x * blockDim.x) {
-        const int lane = (int)(u & 63);
-        const long f = u >> 6;
-        const int ks = (int)(f % ksteps);
-        const long rb = f / ksteps;
-        const int g = lane >> 4, r = lane & 15;
-        dst[u] = src[(rb * 16 + r) * (ksteps * 4) + ks * 4 + g];
-    }
 }
 
 // ------------------------------------------------------------------ bias gradient

@@ -480,11 +480,6 @@ extern "C" drc_status drc_cae_workspace_size(const drc_cae* h, int n, int H, int
 
 // ------------------------------------------------------------------ parameter packing
 static drc_status pack_all(drc_cae* h, const float* d_params, hipStream_t s) {
-    // biases (float32 copy, at the bias offsets of a compact array)
-    for (int l = 0; l < 6; ++l) {
-        HIPCHK(hipMemcpyAsync(h->bias + bias_slot(l), d_params + layer_b_offset(l),
-                              kLayers[l].cout * sizeof(float), hipMemcpyDeviceToDevice, s));
-    }
     if (h->prec == P_FP8) {
         HIPCHK(hipMemsetAsync(h->amax, 0, 16 * sizeof(unsigned), s));
         for (int l = 0; l < 6; ++l) {
@@ -495,13 +490,17 @@ static drc_status pack_all(drc_cae* h, const float* d_params, hipStream_t s) {
         hipLaunchKernelGGL(fp8_scale_kernel, dim3(1), dim3(64), 0, s, (const unsigned*)h->amax, h->scales, 6);
         TRY(check_launch("set_params/fp8 scales"));
     }
+    // every weight pack (and its fragment-ordered copy) and the biases in one launch
+    PackAllArgs pa;
+    memset(&pa, 0, sizeof pa);
+    long most = 0;
     for (int l = 0; l < 6; ++l) {
         for (int dir = 0; dir < 3; ++dir) {
             void* dst = dir == 0 ? h->wf[l] : (dir == 1 ? h->wb[l] : h->wcal[l]);
             if (!dst) continue;
             const int prec = dir == 2 ? P_F32 : h->prec;
             GemmGeom g = gemm_geom(l, dir == 1, prec);
-            PackArgs a;
+            PackArgs& a = pa.p[pa.np++];
             a.w = d_params + layer_w_offset(l);
             a.cout = kLayers[l].cout;
             a.cin = kLayers[l].cin;
@@ -514,23 +513,17 @@ static drc_status pack_all(drc_cae* h, const float* d_params, hipStream_t s) {
             a.prec = prec;
             a.scale = prec == P_FP8 ? h->scales + l : nullptr;
             a.dst = dst;
-            const long total = (long)g.nblk * g.rows_pad * g.kstride;
-            const int blocks = (int)std::min(1024L, (total + 255) / 256);
-            hipLaunchKernelGGL(pack_weights_kernel, dim3(blocks), dim3(256), 0, s, a);
+            a.frag = (prec == P_BF16 && dir < 2 && g.kstride % 32 == 0) ? (dir ? h->wbfrag[l] : h->wfrag[l])
+                                                                         : nullptr;
+            most = std::max(most, (long)g.nblk * g.rows_pad * g.kstride);
         }
+        pa.bsrc[l] = d_params + layer_b_offset(l);
+        pa.bcount[l] = kLayers[l].cout;
+        pa.bslot[l] = bias_slot(l);
     }
-    if (h->prec == P_BF16) {
-        for (int l = 0; l < 6; ++l)
-            for (int dir = 0; dir < 2; ++dir) {
-                GemmGeom g = gemm_geom(l, dir == 1, P_BF16);
-                if (g.kstride % 32) continue;  // (not a fused-kernel operand)
-                const int rows = g.nblk * g.rows_pad, ksteps = g.kstride / 32;
-                const long units = (long)rows * ksteps * 4;
-                hipLaunchKernelGGL(frag_order_kernel, dim3((int)std::min(1024L, (units + 255) / 256)), dim3(256), 0,
-                                   s, (const uint4*)(dir ? h->wb[l] : h->wf[l]),
-                                   (uint4*)(dir ? h->wbfrag[l] : h->wfrag[l]), rows, ksteps);
-            }
-    }
+    pa.bdst = h->bias;
+    const int bx = (int)std::min(256L, (most + 255) / 256);
+    hipLaunchKernelGGL(pack_all_kernel, dim3(bx, pa.np + 1), dim3(256), 0, s, pa);
     TRY(check_launch("set_params/pack"));
     return DRC_OK;
 }
