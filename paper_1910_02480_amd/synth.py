@@ -41,6 +41,7 @@ SEED_WEIGHTS = 0
 SEED_MAPS = 1
 SEED_MIXED_PERM = 2
 SEED_TRAIN = 3
+SEED_ENVMAP = 4
 
 
 def param_count() -> int:
@@ -157,6 +158,28 @@ def training_batch(n: int, h: int, w: int | None = None, seed: int = SEED_TRAIN,
     for k in range(n):
         x[k], t[k] = training_pair(start + k, h, w, seed)
     return x, t
+
+
+def predicted_map(m: int, h: int, w: int, seed: int = SEED_ENVMAP, noise: float = 0.05) -> np.ndarray:
+    """A stand-in for one denoised output map, float32 [h, w, 3].
+
+    Draw order: lobes as in ``training_pair`` (log1p applied), then Gaussian
+    noise of standard deviation ``noise`` [h,w,3]. The noise lets a few
+    values dip below zero, as the linear output layer's can.
+    """
+    rng = np.random.default_rng([seed, m])
+    t = np.log1p(_lobe_target(rng, h, w))
+    t += noise * rng.standard_normal((h, w, 3))
+    return t.astype(np.float32)
+
+
+def predicted_maps(n: int, h: int, w: int | None = None, seed: int = SEED_ENVMAP,
+                   start: int = 0) -> np.ndarray:
+    w = h if w is None else w
+    out = np.empty((n, h, w, OUT_CH), dtype=np.float32)
+    for k in range(n):
+        out[k] = predicted_map(start + k, h, w, seed)
+    return out
 
 
 # Mixed-resolution frame: 50 % 32x32, 35 % 64x64, 15 % 128x128, shuffled.
