@@ -91,6 +91,54 @@ def timed(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def event_timed(fn, steps, warmup):
+    """Seconds per call from HIP events recorded on the current stream (the
+    stream the library launches on) around `steps` back-to-back calls."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) * 1e-3 / steps
+
+
+def envmap_leg(B, y, steps, warmup, samples=64):
+    """Sampling tables of the forward's predicted maps (drc_envmap_build),
+    then `samples` directions per map and their densities. HBM-bound: the
+    build reads y (12 B per pixel) and writes the CDFs (4 B per pixel, 4 B
+    per row, 4 B per map); a sample reads 8 B of uniforms and writes 20 B, a
+    density evaluation reads 12 B and writes 4 B (table reads hit the caches)."""
+    import torch
+    n, H, W, _ = y.shape
+    dev = y.device
+    cu = torch.empty((n, H, W), device=dev)
+    cv = torch.empty((n, H), device=dev)
+    tot = torch.empty((n,), device=dev)
+    tb = event_timed(lambda: B.drc_envmap_build(y, cu, cv, tot), steps, warmup)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    xi = torch.rand((n, samples, 2), generator=gen, device=dev)
+    d = torch.empty((n, samples, 3), device=dev)
+    p = torch.empty((n, samples), device=dev)
+    pix = torch.empty((n, samples), dtype=torch.int32, device=dev)
+    ts = event_timed(lambda: B.drc_envmap_sample(cu, cv, xi, d, p, pix), steps, warmup)
+    p2 = torch.empty_like(p)
+    tp = event_timed(lambda: B.drc_envmap_pdf(cu, cv, d, p2), steps, warmup)
+    bb = n * (H * W * 16 + 4 * H + 4)
+    bs = n * samples * 28
+    bp = n * samples * 16
+    return {"maps": n, "H": H, "W": W, "samples_per_map": samples,
+            "build_ms": tb * 1e3, "build_maps_per_s": n / tb, "build_GB/s": bb / tb / 1e9,
+            "build_hbm_frac": bb / tb / 1e9 / PEAK_HBM_GBS, "build_alg_bytes": bb,
+            "sample_ms": ts * 1e3, "samples_per_s": n * samples / ts, "sample_GB/s": bs / ts / 1e9,
+            "pdf_ms": tp * 1e3, "pdf_evals_per_s": n * samples / tp, "pdf_GB/s": bp / tp / 1e9}
+
+
 def read_profile(B, h):
     return B.drc_cae_profile_read(h)
 
@@ -278,6 +326,11 @@ def main():
     log(f"bf16 forward: {value:,.0f} maps/s ({t * 1e3:.3f} ms / {n} maps)")
 
     if not args.main_only:
+        # ---------------- the step after the forward: sampling tables of the predicted maps
+        legs["envmap_of_bf16_fwd_output"] = em = envmap_leg(B, y, args.steps, args.warmup)
+        log(f"envmap build: {em['build_maps_per_s']:,.0f} maps/s ({em['build_ms']:.4f} ms, "
+            f"{em['build_GB/s']:.0f} GB/s); sample {em['samples_per_s'] / 1e9:.2f} G/s; "
+            f"pdf {em['pdf_evals_per_s'] / 1e9:.2f} G/s")
         # ---------------- the same BF16 forward, one kernel per layer (activations through HBM)
         cae.set_fused(False)
         if not args.no_autotune and fused_headline:

@@ -206,6 +206,46 @@ drc_status drc_cae_plan_launch(drc_plan* p, const float* d_x_packed, float* d_y_
                                size_t ws_bytes, void* stream);
 void drc_cae_plan_destroy(drc_plan* p);
 
+/* Sampling the predicted map R as an environment map (Sec. 3: the indirect
+ * term alternates samples drawn from R, as from an environment map with
+ * perfect visibility, with samples from the BRDF, combined by multiple
+ * importance sampling; Sec. 4.3: R is a hemispherical latitude-longitude
+ * map with the surface normal along +Z).
+ *
+ * Map geometry: row v (0 = at the normal) spans polar angles
+ * [v, v + 1] * (pi / 2) / H, column u spans azimuths [u, u + 1] * 2 pi / W.
+ * Directions are in the map's frame: (sin t cos p, sin t sin p, cos t).
+ * Distribution: piecewise constant over the (u, v) unit square, pixel weight
+ * max(0, 0.2126 R + 0.7152 G + 0.0722 B) * sin(row-centre polar angle)
+ * (luminance of BT.709 primaries times the pixel's solid angle).
+ * The tables are inclusive CDFs: cdf_v[m][v] = P(row <= v) and
+ * cdf_u[m][v][u] = P(column <= u | row v), non-decreasing, last entry 1. A
+ * row (or map) of zero total weight gets the uniform CDF (k + 1) / count,
+ * and total[m] = 0 marks a map that fell back entirely.
+ * Shapes: 0 <= n (n = 0 does nothing), 1 <= H <= 4096, 1 <= W <= 1024. All
+ * arrays are float32 (pix int32), contiguous, device, 4-byte aligned, owned
+ * by the caller. Inputs must be finite.
+ *
+ * build: d_y [n, H, W, 3] (e.g. drc_cae_forward's output) -> d_cdf_u
+ *   [n, H, W], d_cdf_v [n, H], d_total [n] (sum of the pixel weights). */
+drc_status drc_envmap_build(const float* d_y, int n, int H, int W, float* d_cdf_u, float* d_cdf_v,
+                            float* d_total, void* stream);
+
+/* S samples per map by inversion of the tables: d_xi [n, S, 2] uniforms in
+ * [0, 1) (values outside are clamped; xi[0] picks the row, xi[1] the
+ * column, and each places the sample linearly inside its pixel). Outputs:
+ * d_dir [n, S, 3] unit directions, d_pdf [n, S] their density with respect
+ * to solid angle (p(u, v) / (pi^2 sin t); 0 where sin t = 0), d_pix [n, S]
+ * the pixel v * W + u. */
+drc_status drc_envmap_sample(const float* d_cdf_u, const float* d_cdf_v, int n, int H, int W, int S,
+                             const float* d_xi, float* d_dir, float* d_pdf, int32_t* d_pix, void* stream);
+
+/* Solid-angle density of S directions per map, d_dir [n, S, 3] in the map's
+ * frame (any non-zero length), under that map's distribution -> d_pdf
+ * [n, S]; 0 below the horizon (z < 0) and along the normal. */
+drc_status drc_envmap_pdf(const float* d_cdf_u, const float* d_cdf_v, int n, int H, int W, int S,
+                          const float* d_dir, float* d_pdf, void* stream);
+
 /* Tile-shape tuning: time each implemented tile shape of every layer for
  * an n x H x W forward batch on the given stream and write the fastest to
  * the JSON cache file path (keyed by arch, precision, layer and

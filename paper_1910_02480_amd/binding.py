@@ -67,6 +67,9 @@ _SIGS = {
     "drc_cae_plan_workspace_size": (_I, [_VP, ctypes.POINTER(_SZ)]),
     "drc_cae_plan_launch": (_I, [_VP, _VP, _VP, _VP, _SZ, _VP]),
     "drc_cae_plan_destroy": (None, [_VP]),
+    "drc_envmap_build": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP]),
+    "drc_envmap_sample": (_I, [_VP, _VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
+    "drc_envmap_pdf": (_I, [_VP, _VP, _I, _I, _I, _I, _VP, _VP, _VP]),
     "drc_cae_autotune": (_I, [_VP, _I, _I, _I, _VP, _VP, _SZ, ctypes.c_char_p, _VP]),
     "drc_cae_set_tile": (_I, [_VP, _I, _I, _I]),
     "drc_cae_profile": (_I, [_VP, _I]),
@@ -225,6 +228,27 @@ def drc_cae_plan_launch(p, x_packed, y_packed, ws=None, stream=None):
 
 def drc_cae_plan_destroy(p):
     lib().drc_cae_plan_destroy(p)
+
+
+def drc_envmap_build(y, cdf_u, cdf_v, total, stream=None):
+    """y [n, H, W, 3] -> cdf_u [n, H, W], cdf_v [n, H], total [n]."""
+    n, H, W = _nhw(y, 3)
+    _check(lib().drc_envmap_build(_ptr(y), n, H, W, _ptr(cdf_u), _ptr(cdf_v), _ptr(total), _stream(stream)))
+
+
+def drc_envmap_sample(cdf_u, cdf_v, xi, dirs, pdf, pix, stream=None):
+    """xi [n, S, 2] -> dirs [n, S, 3], pdf [n, S], pix [n, S] (int32)."""
+    n, H, W = (int(v) for v in cdf_u.shape)
+    S = int(xi.shape[1])
+    _check(lib().drc_envmap_sample(_ptr(cdf_u), _ptr(cdf_v), n, H, W, S, _ptr(xi), _ptr(dirs), _ptr(pdf),
+                                   _ptr(pix), _stream(stream)))
+
+
+def drc_envmap_pdf(cdf_u, cdf_v, dirs, pdf, stream=None):
+    """dirs [n, S, 3] -> pdf [n, S]."""
+    n, H, W = (int(v) for v in cdf_u.shape)
+    S = int(dirs.shape[1])
+    _check(lib().drc_envmap_pdf(_ptr(cdf_u), _ptr(cdf_v), n, H, W, S, _ptr(dirs), _ptr(pdf), _stream(stream)))
 
 
 def drc_cae_autotune(h, x, ws, tune_cache, stream=None):

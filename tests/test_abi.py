@@ -100,3 +100,21 @@ def test_product_path_never_imports_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in txt.lower() or f == "synth.py", f
+
+
+def test_envmap_rejects_bad_shapes_and_pointers(B):
+    L = B.lib()
+    # shapes are checked first, then pointers; nothing reaches the device
+    assert L.drc_envmap_build(None, 1, 0, 8, None, None, None, None) == 2
+    assert L.drc_envmap_build(None, 1, 8, 1025, None, None, None, None) == 2
+    assert L.drc_envmap_build(None, 1, 4097, 8, None, None, None, None) == 2
+    assert L.drc_envmap_build(None, -1, 8, 8, None, None, None, None) == 2
+    assert L.drc_envmap_build(None, 1, 8, 8, None, None, None, None) == 1
+    assert L.drc_envmap_build(2, 1, 8, 8, 4, 4, 4, None) == 1          # misaligned d_y
+    assert L.drc_envmap_build(None, 0, 8, 8, None, None, None, None) == 0  # empty batch
+    assert L.drc_envmap_sample(None, None, 1, 8, 8, -1, None, None, None, None, None) == 2
+    assert L.drc_envmap_sample(None, None, 1, 8, 8, 4, None, None, None, None, None) == 1
+    assert L.drc_envmap_sample(None, None, 1, 8, 8, 0, None, None, None, None, None) == 0
+    assert L.drc_envmap_pdf(None, None, 1, 0, 8, 4, None, None, None) == 2
+    assert L.drc_envmap_pdf(None, None, 1, 8, 8, 4, None, None, None) == 1
+    assert "envmap_pdf" in B.drc_last_error()
