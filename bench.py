@@ -228,6 +228,8 @@ def main():
     ap.add_argument("--res", type=int, default=64)
     ap.add_argument("--train-maps", type=int, default=256)
     ap.add_argument("--main-only", action="store_true", help="time only the headline leg")
+    ap.add_argument("--with-envmap", action="store_true",
+                    help="with --main-only: also time the sampling tables of the forward's output")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calib", action="store_true",
@@ -325,12 +327,15 @@ def main():
                         "mfma_frac_flop_based": total_flops / t / (PEAK_TFLOPS["bf16"] * 1e12)}
     log(f"bf16 forward: {value:,.0f} maps/s ({t * 1e3:.3f} ms / {n} maps)")
 
-    if not args.main_only:
+    if not args.main_only or args.with_envmap:
         # ---------------- the step after the forward: sampling tables of the predicted maps
         legs["envmap_of_bf16_fwd_output"] = em = envmap_leg(B, y, args.steps, args.warmup)
+        if tr and "envmap build" in tr["kernels"]:
+            em["build_traffic_bytes"] = tr["kernels"]["envmap build"]["bytes_per_launch"]
         log(f"envmap build: {em['build_maps_per_s']:,.0f} maps/s ({em['build_ms']:.4f} ms, "
             f"{em['build_GB/s']:.0f} GB/s); sample {em['samples_per_s'] / 1e9:.2f} G/s; "
             f"pdf {em['pdf_evals_per_s'] / 1e9:.2f} G/s")
+    if not args.main_only:
         # ---------------- the same BF16 forward, one kernel per layer (activations through HBM)
         cae.set_fused(False)
         if not args.no_autotune and fused_headline:

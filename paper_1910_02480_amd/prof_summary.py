@@ -36,7 +36,10 @@ _LABELS = (
     (r"tconv_merged_kernel<1, 64, 32, 3,", "forward D1"),
     (r"cae_fused_forward_kernel<\d+, \d+, false>", "forward fused"),
     (r"cae_fused_forward_kernel<\d+, \d+, true>", "recompute fused"),
-    (r"pack_weights_kernel", "weight pack"),
+    (r"pack_weights_kernel|pack_all_kernel", "weight pack"),
+    (r"envmap_build_kernel", "envmap build"),
+    (r"envmap_sample_kernel", "envmap sample"),
+    (r"envmap_pdf_kernel", "envmap pdf"),
     (r"elementwise.*Mul|Mul.*elementwise", "copy (torch.mul, 256 MiB)"),
 )
 
