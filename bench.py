@@ -139,6 +139,23 @@ def envmap_leg(B, y, steps, warmup, samples=64):
             "pdf_ms": tp * 1e3, "pdf_evals_per_s": n * samples / tp, "pdf_GB/s": bp / tp / 1e9}
 
 
+def interp_leg(B, dev, steps, warmup, Hi=1080, Wi=1920, r=16, eps=1e-4):
+    """Cache-point interpolation weights of one Hi x Wi frame with a grid of
+    spacing r (drc_interp_weights). HBM-bound: 12 B of normal in and 32 B
+    of indices and probabilities out per pixel (cache normals hit the caches)."""
+    import torch
+    from paper_1910_02480_amd import synth
+    n = torch.from_numpy(synth.gbuffer_normals(Hi, Wi)).to(dev)
+    cn = n[::r, ::r].contiguous()
+    idx = torch.empty((Hi, Wi, 4), dtype=torch.int32, device=dev)
+    prob = torch.empty((Hi, Wi, 4), device=dev)
+    t = event_timed(lambda: B.drc_interp_weights(n, r, cn, eps, idx, prob), steps, warmup)
+    by = Hi * Wi * 44 + cn.numel() * 4
+    return {"image": [Hi, Wi], "r": r, "cache_points": int(cn.shape[0] * cn.shape[1]), "ms": t * 1e3,
+            "pixels_per_s": Hi * Wi / t, "GB/s": by / t / 1e9, "hbm_frac": by / t / 1e9 / PEAK_HBM_GBS,
+            "alg_bytes": by}
+
+
 def read_profile(B, h):
     return B.drc_cae_profile_read(h)
 
@@ -335,6 +352,8 @@ def main():
         log(f"envmap build: {em['build_maps_per_s']:,.0f} maps/s ({em['build_ms']:.4f} ms, "
             f"{em['build_GB/s']:.0f} GB/s); sample {em['samples_per_s'] / 1e9:.2f} G/s; "
             f"pdf {em['pdf_evals_per_s'] / 1e9:.2f} G/s")
+        legs["interp_weights_1080p"] = iw = interp_leg(B, dev, args.steps, args.warmup)
+        log(f"interpolation weights, 1920x1080, r=16: {iw['ms']:.4f} ms ({iw['GB/s']:.0f} GB/s)")
     if not args.main_only:
         # ---------------- the same BF16 forward, one kernel per layer (activations through HBM)
         cae.set_fused(False)

@@ -246,6 +246,27 @@ drc_status drc_envmap_sample(const float* d_cdf_u, const float* d_cdf_v, int n, 
 drc_status drc_envmap_pdf(const float* d_cdf_u, const float* d_cdf_v, int n, int H, int W, int S,
                           const float* d_dir, float* d_pdf, void* stream);
 
+/* Interpolation between cache points (Sec. 4.2, Eqs. 4-6): for each pixel
+ * of an Hi x Wi image, the probabilities of sampling the radiance maps of
+ * the cache points around it. Cache points lie on a grid of spacing r
+ * pixels, point (gy, gx) on pixel (gx r, gy r), Gy = (Hi - 1) / r + 1 rows
+ * and Gx = (Wi - 1) / r + 1 columns, numbered gy * Gx + gx. The candidates
+ * of pixel (x, y) are the corners k = 0..3 of its grid cell,
+ * (x / r + (k & 1), y / r + (k >> 1)), that lie inside the grid; each gets
+ * w = w_p w_n + w_p + eps with w_p = max(0, 1 - dist / r) (dist in pixels)
+ * and w_n = max(0, dot of the unit normals; 0 for a zero normal). The
+ * printed Eqs. 5 and 6 contradict the text around them; the text's reading
+ * is taken (weight falls with distance and rises with normal agreement).
+ * The weights are normalised to probabilities; if all vanish (eps = 0), the
+ * present corners are equally likely. Absent corners get index -1 and
+ * probability 0.
+ * d_normals [Hi, Wi, 3] pixel normals (primary hits) and d_cache_normals
+ * [Gy, Gx, 3], float32, any lengths, 4-byte aligned; outputs d_idx
+ * [Hi, Wi, 4] int32 and d_prob [Hi, Wi, 4] float32, 16-byte aligned. eps
+ * finite and >= 0; 1 <= r <= 4096; Hi * Wi < 2^31. */
+drc_status drc_interp_weights(const float* d_normals, int Hi, int Wi, int r, const float* d_cache_normals,
+                              float eps, int32_t* d_idx, float* d_prob, void* stream);
+
 /* Tile-shape tuning: time each implemented tile shape of every layer for
  * an n x H x W forward batch on the given stream and write the fastest to
  * the JSON cache file path (keyed by arch, precision, layer and

@@ -70,6 +70,7 @@ _SIGS = {
     "drc_envmap_build": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP]),
     "drc_envmap_sample": (_I, [_VP, _VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
     "drc_envmap_pdf": (_I, [_VP, _VP, _I, _I, _I, _I, _VP, _VP, _VP]),
+    "drc_interp_weights": (_I, [_VP, _I, _I, _I, _VP, ctypes.c_float, _VP, _VP, _VP]),
     "drc_cae_autotune": (_I, [_VP, _I, _I, _I, _VP, _VP, _SZ, ctypes.c_char_p, _VP]),
     "drc_cae_set_tile": (_I, [_VP, _I, _I, _I]),
     "drc_cae_profile": (_I, [_VP, _I]),
@@ -249,6 +250,15 @@ def drc_envmap_pdf(cdf_u, cdf_v, dirs, pdf, stream=None):
     n, H, W = (int(v) for v in cdf_u.shape)
     S = int(dirs.shape[1])
     _check(lib().drc_envmap_pdf(_ptr(cdf_u), _ptr(cdf_v), n, H, W, S, _ptr(dirs), _ptr(pdf), _stream(stream)))
+
+
+def drc_interp_weights(normals, r, cache_normals, eps, idx, prob, stream=None):
+    """normals [Hi, Wi, 3], cache_normals [Gy, Gx, 3] -> idx [Hi, Wi, 4] int32, prob [Hi, Wi, 4]."""
+    if normals.dim() != 3 or normals.shape[2] != 3:
+        raise ValueError(f"expected [Hi, Wi, 3] normals, got {tuple(normals.shape)}")
+    Hi, Wi = int(normals.shape[0]), int(normals.shape[1])
+    _check(lib().drc_interp_weights(_ptr(normals), Hi, Wi, int(r), _ptr(cache_normals), float(eps), _ptr(idx),
+                                    _ptr(prob), _stream(stream)))
 
 
 def drc_cae_autotune(h, x, ws, tune_cache, stream=None):

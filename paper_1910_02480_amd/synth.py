@@ -42,6 +42,7 @@ SEED_MAPS = 1
 SEED_MIXED_PERM = 2
 SEED_TRAIN = 3
 SEED_ENVMAP = 4
+SEED_GBUFFER = 5
 
 
 def param_count() -> int:
@@ -180,6 +181,32 @@ def predicted_maps(n: int, h: int, w: int | None = None, seed: int = SEED_ENVMAP
     for k in range(n):
         out[k] = predicted_map(start + k, h, w, seed)
     return out
+
+
+def gbuffer_normals(hi: int, wi: int, seed: int = SEED_GBUFFER, background: float = 0.05) -> np.ndarray:
+    """Primary-hit normals of an hi x wi image, float32 [hi, wi, 3].
+
+    A smooth height field z(x, y) (sum of 6 random sinusoids) gives the
+    unit normals (-dz/dx, -dz/dy, 1) / norm; then a random ``background``
+    fraction of pixels (rays that hit nothing) gets the zero vector.
+    Draw order: amplitudes [6], frequencies [6, 2], phases [6], background
+    mask [hi, wi].
+    """
+    rng = np.random.default_rng(seed)
+    amp = rng.uniform(0.2, 1.0, 6)
+    freq = rng.uniform(0.002, 0.05, (6, 2))
+    ph = rng.uniform(0.0, 2 * np.pi, 6)
+    y, x = np.meshgrid(np.arange(hi, dtype=np.float64), np.arange(wi, dtype=np.float64), indexing="ij")
+    dzdx = np.zeros((hi, wi))
+    dzdy = np.zeros((hi, wi))
+    for k in range(6):
+        c = amp[k] * np.cos(freq[k, 0] * x + freq[k, 1] * y + ph[k]) * 20.0
+        dzdx += c * freq[k, 0]
+        dzdy += c * freq[k, 1]
+    n = np.stack([-dzdx, -dzdy, np.ones_like(dzdx)], -1)
+    n /= np.linalg.norm(n, axis=-1, keepdims=True)
+    n[rng.random((hi, wi)) < background] = 0.0
+    return n.astype(np.float32)
 
 
 # Mixed-resolution frame: 50 % 32x32, 35 % 64x64, 15 % 128x128, shuffled.

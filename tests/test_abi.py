@@ -118,3 +118,15 @@ def test_envmap_rejects_bad_shapes_and_pointers(B):
     assert L.drc_envmap_pdf(None, None, 1, 0, 8, 4, None, None, None) == 2
     assert L.drc_envmap_pdf(None, None, 1, 8, 8, 4, None, None, None) == 1
     assert "envmap_pdf" in B.drc_last_error()
+
+
+def test_interp_rejects_bad_arguments(B):
+    L = B.lib()
+    f = ctypes.c_float
+    assert L.drc_interp_weights(None, 0, 8, 4, None, f(0.0), None, None, None) == 2
+    assert L.drc_interp_weights(None, 8, 8, 0, None, f(0.0), None, None, None) == 2
+    assert L.drc_interp_weights(None, 8, 8, 4, None, f(-1.0), None, None, None) == 1
+    assert L.drc_interp_weights(None, 8, 8, 4, None, f(float("nan")), None, None, None) == 1
+    assert L.drc_interp_weights(None, 8, 8, 4, None, f(1e-3), None, None, None) == 1
+    assert L.drc_interp_weights(16, 8, 8, 4, 16, f(1e-3), 8, 16, None) == 1   # d_idx not 16-byte aligned
+    assert L.drc_interp_weights(2, 8, 8, 4, 16, f(1e-3), 16, 16, None) == 1   # d_normals not 4-byte aligned
