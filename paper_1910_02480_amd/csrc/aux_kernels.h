@@ -644,6 +644,183 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradBArgs a) {
             }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 weight gradient with a 16-bit gathered operand (E2, E3, D3, D2), fed by
+// LDS transpose reads. Both operands are staged per strip of R reduction rows
+// as plain NHWC copies (16-byte chunks, pixel stride padded by 8 elements so
+// that the 4 pixels one 16-lane group reads fall on different banks), and the
+// MFMA operands (16 channels x 8 pixels per lane) come from ds_read_b64_tr_b16:
+// within a group of 16 lanes, lane i's slot j is element i % 4 of the 8 bytes
+// that lane 4 j + i / 4 addressed (measured on gfx950). So lane 4 j' + q of a
+// group addresses channels [4 q, 4 q + 4) of the group's pixel j', and two
+// reads (pixels 0-3 and 4-7) give each lane 8 pixels of one channel. The
+// stride-2 gather of the 3 x 3 taps is per-lane address arithmetic; the halo
+// column -1 reads a zero block. Rows and columns of the result, partial tiles
+// and their reduction are those of wgrad_bf16_kernel.
+struct WgradTArgs {
+    const void* p; const void* p2;  // plain operand (bf16), channels [0, pc0) from p, the rest from p2
+    int pc, pc0, pld, p2ld;
+    const void* q;                  // gathered operand (bf16)
+    int qld;
+    int Hr, Wr, Hq, Wq;
+    int R, strips_per_map, total_strips, strips_per_chunk;
+    float* partial;                 // [chunk][9*QC][pc]
+};
+
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4i16 lds_v4i16;
+
+__device__ __forceinline__ uint2 lds_read_tr16(const uint16_t* p) {
+    const v4i16 v = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+        (lds_v4i16*)((__attribute__((address_space(3))) uint16_t*)p));
+    return __builtin_bit_cast(uint2, v);
+}
+
+template <int QC, int PB>
+struct WgradTLds {
+    static constexpr int GS = QC + 8;       // elements per staged gathered pixel
+    static constexpr int PS = PB * 16 + 8;  // elements per staged plain pixel
+    static __host__ __device__ int bytes(int R, int Wr, int Wq) {
+        return ((2 * R + 1) * Wq * GS + R * Wr * PS + 16) * 2;
+    }
+};
+
+template <int JBW, int PB, int QC>
+__global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
+    using L = WgradTLds<QC, PB>;
+    constexpr int GS = L::GS, PS = L::PS;
+    constexpr int J = 9 * QC;
+    extern __shared__ __align__(16) char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int jq = r16 >> 2, qq = r16 & 3;  // this lane's pixel and channel quad in a transpose read
+    const int Wr = a.Wr, Wq = a.Wq, R = a.R, K = R * Wr;
+    uint16_t* Gs = (uint16_t*)smem;
+    uint16_t* Ps = Gs + (2 * R + 1) * Wq * GS;
+    uint16_t* zero = Ps + R * Wr * PS;
+    const int cp0 = blockIdx.y * PB * 16;
+    if (threadIdx.x < 2) *(uint4*)(zero + 8 * threadIdx.x) = make_uint4(0, 0, 0, 0);
+
+    // per owned row block: LDS offset of this lane's gathered address relative
+    // to the pixel (2 ul, 2 v) of the staged strip, and whether kw == 0
+    int aoff[JBW];
+    bool av[JBW], akw0[JBW];
+#pragma unroll
+    for (int i = 0; i < JBW; ++i) {
+        const int rb = wave + 4 * i;
+        av[i] = rb * 16 < J;
+        const int t = av[i] ? rb * 16 / QC : 0, c0 = av[i] ? rb * 16 % QC : 0;
+        const int kh = t / 3, kw = t - 3 * (t / 3);
+        akw0[i] = kw == 0;
+        aoff[i] = (kh * Wq + kw - 1) * GS + c0 + 4 * qq;
+    }
+    f4 acc[JBW][PB];
+#pragma unroll
+    for (int i = 0; i < JBW; ++i)
+#pragma unroll
+        for (int b = 0; b < PB; ++b) acc[i][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+    const int s_begin = blockIdx.x * a.strips_per_chunk;
+    const int s_end = min(a.total_strips, s_begin + a.strips_per_chunk);
+    for (int s = s_begin; s < s_end; ++s) {
+        const int n = s / a.strips_per_map;
+        const int u0 = (s - n * a.strips_per_map) * R;
+        __syncthreads();  // the previous strip's LDS reads are done
+        // ---- gathered rows 2 u0 - 1 .. 2 u0 + 2 R - 1, all columns, 8 channels per
+        // task; each thread issues up to U loads before its LDS writes
+        constexpr int U = 8;
+        {
+            constexpr int CG = QC / 8;
+            const int ntask = (2 * R + 1) * Wq * CG;
+            const uint16_t* qn = (const uint16_t*)a.q + ((long)n * a.Hq + 2 * u0 - 1) * Wq * a.qld;
+            for (int e0 = threadIdx.x; e0 < ntask; e0 += 256 * U) {
+                uint4 v[U];
+#pragma unroll
+                for (int t = 0; t < U; ++t) {
+                    const int e = e0 + 256 * t;
+                    const int cg = e % CG, pix = e / CG;
+                    const int row = pix / Wq;
+                    const int qi = 2 * u0 - 1 + row;
+                    v[t] = make_uint4(0, 0, 0, 0);
+                    if (e < ntask && (unsigned)qi < (unsigned)a.Hq)
+                        v[t] = *(const uint4*)(qn + ((long)row * Wq + (pix - row * Wq)) * a.qld + cg * 8);
+                }
+#pragma unroll
+                for (int t = 0; t < U; ++t) {
+                    const int e = e0 + 256 * t;
+                    if (e < ntask) *(uint4*)(Gs + (e / CG) * GS + (e % CG) * 8) = v[t];
+                }
+            }
+        }
+        // ---- plain rows u0 .. u0 + R - 1, channels [cp0, cp0 + 16 PB)
+        {
+            constexpr int CG = PB * 2;
+            const int ntask = K * CG;
+            for (int e0 = threadIdx.x; e0 < ntask; e0 += 256 * U) {
+                uint4 w[U];
+#pragma unroll
+                for (int t = 0; t < U; ++t) {
+                    const int e = e0 + 256 * t;
+                    const int cg = e % CG, k = e / CG;
+                    const int u = u0 + k / Wr, v = k - (k / Wr) * Wr;
+                    const int c = cp0 + cg * 8;
+                    w[t] = make_uint4(0, 0, 0, 0);
+                    if (e < ntask && u < a.Hr && c < a.pc) {
+                        const long pix = ((long)n * a.Hr + u) * Wr + v;
+                        w[t] = (c < a.pc0) ? *(const uint4*)((const uint16_t*)a.p + pix * a.pld + c)
+                                           : *(const uint4*)((const uint16_t*)a.p2 + pix * a.p2ld + (c - a.pc0));
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < U; ++t) {
+                    const int e = e0 + 256 * t;
+                    if (e < ntask) *(uint4*)(Ps + (e / CG) * PS + (e % CG) * 8) = w[t];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- MFMAs: this lane group's 8 reduction pixels are (ul, v0 .. v0 + 7)
+        for (int ks = 0; ks < K / 32; ++ks) {
+            const int k0 = ks * 32 + 8 * g;
+            const int ul = k0 / Wr, v0 = k0 - (k0 / Wr) * Wr;
+            uint4 bfr[PB];
+            const uint16_t* pb = Ps + (k0 + jq) * PS + 4 * qq;
+#pragma unroll
+            for (int b = 0; b < PB; ++b) {
+                const uint2 lo = lds_read_tr16(pb + b * 16);
+                const uint2 hi = lds_read_tr16(pb + 4 * PS + b * 16);
+                bfr[b] = make_uint4(lo.x, lo.y, hi.x, hi.y);
+            }
+            const uint16_t* gb = Gs + (2 * ul * Wq + 2 * (v0 + jq)) * GS;
+            const bool left = v0 + jq == 0;  // column -1 for kw == 0
+#pragma unroll
+            for (int i = 0; i < JBW; ++i) {
+                if (!av[i]) continue;
+                const uint2 lo = lds_read_tr16(left && akw0[i] ? zero + 4 * qq : gb + aoff[i]);
+                const uint2 hi = lds_read_tr16(gb + aoff[i] + 8 * GS);
+                const uint4 afr = make_uint4(lo.x, lo.y, hi.x, hi.y);
+#pragma unroll
+                for (int b = 0; b < PB; ++b)
+                    acc[i][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, afr),
+                                                                      __builtin_bit_cast(bf16x8, bfr[b]), acc[i][b],
+                                                                      0, 0, 0);
+            }
+        }
+    }
+    // ---- partial tile: lane holds rows 4*g + r of row block (wave + 4 i), column r16 of block b
+    float* out = a.partial + (long)blockIdx.x * J * a.pc;
+#pragma unroll
+    for (int i = 0; i < JBW; ++i)
+#pragma unroll
+        for (int b = 0; b < PB; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = (wave + 4 * i) * 16 + 4 * g + r;
+                const int cp = cp0 + b * 16 + r16;
+                if (j < J && cp < a.pc) out[(long)j * a.pc + cp] = acc[i][b][r];
+            }
+}
+
 // dW in the parameter layout from partial[chunk][j][cp] (fixed-order sum).
 // q_is_cout: 1 for transposed-convolution layers (j = t*Cout + co, cp = ci),
 // 0 for convolution layers (j = t*Cin + ci, cp = co).

@@ -332,6 +332,7 @@ WgradPlan wgrad_plan(int l, int n, int H, int W, int prec) {
 
     // BF16: LDS-staged operands on bf16 MFMA when a row holds whole groups of 8 pixels
     w.bf16 = 0;
+    w.tr = 0;
     if (prec == P_BF16 && w.Wr % 8 == 0) {
         w.QCP = (w.qc + 7) / 8 * 8;
         const int jb = (9 * w.qc + 15) / 16;
@@ -340,7 +341,23 @@ WgradPlan wgrad_plan(int l, int n, int H, int W, int prec) {
         w.bptiles = (w.pc + 16 * w.BPB - 1) / (16 * w.BPB);
         const bool inst = (w.JBW == 1 && (w.BPB == 2 || w.BPB == 4) && w.QCP == 8) ||
                           (w.JBW == 5 && w.BPB == 4 && w.QCP == 32) || (w.JBW == 9 && w.BPB == 4 && w.QCP == 64);
-        for (int R = std::max(1, 128 / w.Wr); R >= 1 && inst; R /= 2) {
+        // 16-bit gathered operand with 32 or 64 channels: both operands staged
+        // as plain NHWC tiles and read with LDS transpose reads
+        w.tr = 0;
+        if (inst && (w.qc == 32 || w.qc == 64)) {
+            for (int R = w.Hr; R >= 1; R /= 2) {
+                if ((R * w.Wr) % 32) continue;
+                const int GS = w.qc + 8, PS = w.BPB * 16 + 8;
+                const int lds = ((2 * R + 1) * 2 * w.Wr * GS + R * w.Wr * PS + 16) * 2;
+                if (lds > 64 * 1024) continue;
+                w.bf16 = 1;
+                w.tr = 1;
+                w.R = R;
+                w.lds = lds;
+                break;
+            }
+        }
+        for (int R = std::max(1, 128 / w.Wr); R >= 1 && inst && !w.tr; R /= 2) {
             if ((R * w.Wr) % 32) continue;
             int qcs = (2 * R + 1) * 3 * w.Wr;
             qcs = (qcs + 7) / 8 * 8;

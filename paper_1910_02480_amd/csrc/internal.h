@@ -105,6 +105,7 @@ struct WgradPlan {
     size_t partial_floats;
     // BF16 path with LDS-staged operands (bf16 = 1 when it applies)
     int bf16, QCP, JBW, BPB, R, strips_per_map, total_strips, strips_per_chunk, bchunks, bptiles, qcs, lds;
+    int tr;  // bf16 == 1 and the gathered operand is 16-bit with 32 or 64 channels: transpose-read kernel
 };
 WgradPlan wgrad_plan(int l, int n, int H, int W, int prec);
 void colsum_split(long npix, int* nblocks, long* per_block);

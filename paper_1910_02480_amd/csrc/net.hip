@@ -325,6 +325,35 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
     const WgradPlan wp = wgrad_plan(l, n, H, W, sizeof(T) == 2 ? P_BF16 : P_F32);
     int hin, win, hout, wout;
     layer_io(l, H, W, &hin, &win, &hout, &wout);
+    if (wp.tr) {
+        WgradTArgs b;
+        memset(&b, 0, sizeof b);
+        if (!L.tconv) {
+            b.p = g; b.pc = L.cout; b.pc0 = L.cout; b.pld = L.cout;
+            b.q = s0.p; b.qld = s0.ld; b.Hq = hin; b.Wq = win;
+        } else {
+            b.p = s0.p; b.p2 = s1.p; b.pc = L.cin; b.pc0 = s0.c; b.pld = s0.ld; b.p2ld = s1.ld;
+            b.q = g; b.qld = L.cout; b.Hq = hout; b.Wq = wout;
+        }
+        b.Hr = wp.Hr;
+        b.Wr = wp.Wr;
+        b.R = wp.R;
+        b.strips_per_map = wp.strips_per_map;
+        b.total_strips = wp.total_strips;
+        b.strips_per_chunk = wp.strips_per_chunk;
+        b.partial = partial;
+        if (b.Wq != 2 * b.Wr || b.Hq != 2 * b.Hr || wp.qc != (wp.JBW == 5 ? 32 : 64))
+            return drc_fail(DRC_ERR_STATE, "weight_grad: transpose-read plan does not fit layer %d", l);
+        dim3 grid(wp.bchunks, wp.bptiles);
+        if (wp.JBW == 5)
+            hipLaunchKernelGGL((wgrad_tr_kernel<5, 4, 32>), grid, dim3(256), wp.lds, s, b);
+        else
+            hipLaunchKernelGGL((wgrad_tr_kernel<9, 4, 64>), grid, dim3(256), wp.lds, s, b);
+        const long count = 9L * wp.qc * wp.pc;
+        hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)((count + 63) / 64)), dim3(1024), 0, s,
+                           (const float*)partial, wp.bchunks, wp.qc, wp.pc, (int)L.tconv, scale, out);
+        return check_launch("weight_grad");
+    }
     if (wp.bf16) {
         WgradBArgs b;
         memset(&b, 0, sizeof b);

@@ -40,6 +40,14 @@ _LABELS = (
     (r"envmap_build_kernel", "envmap build"),
     (r"envmap_sample_kernel", "envmap sample"),
     (r"envmap_pdf_kernel", "envmap pdf"),
+    (r"interp_weights_kernel", "interp weights"),
+    (r"cae_fused_dgrad_kernel", "fused data gradients"),
+    (r"wgrad_bf16_kernel", "weight gradient (BF16)"),
+    (r"wgrad_kernel", "weight gradient (FP32)"),
+    (r"wgrad_final_kernel", "weight-gradient reduction"),
+    (r"bias_final_kernel|colsum_", "bias gradients"),
+    (r"adam_kernel", "Adam"),
+    (r"l1_", "L1 loss"),
     (r"elementwise.*Mul|Mul.*elementwise", "copy (torch.mul, 256 MiB)"),
 )
 
@@ -72,14 +80,14 @@ def _short(name: str, n: int = 90) -> str:
     return name if len(name) <= n else name[: n - 3] + "..."
 
 
-def stats(csv_path: str, cmd: str, title: str) -> str:
+def stats(csv_path: str, cmd: str, title: str, top: int = 16) -> str:
     rows = list(csv.DictReader(open(csv_path)))
     tot = sum(float(r["TotalDurationNs"]) for r in rows) or 1.0
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     out = [f"# {title}", "", "Command (run from /tmp with TMPDIR=/tmp; $R = repository root):", "",
            f"    {cmd}", "", f"Source hash of the kernels: `{source_hash()}`", "",
            "| Kernel | Serves | Calls | Avg (us) | Total (ms) | Share |", "|---|---|--:|--:|--:|--:|"]
-    for r in rows[:16]:
+    for r in rows[:top]:
         lab = label(r["Name"]) or ""
         out.append(f"| `{_short(r['Name'])}` | {lab} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"{float(r['TotalDurationNs']) / 1e6:.3f} | {100 * float(r['TotalDurationNs']) / tot:.1f} % |")
@@ -159,6 +167,7 @@ def main():
     s.add_argument("csv")
     s.add_argument("--cmd", required=True)
     s.add_argument("--title", default="Kernel trace")
+    s.add_argument("--top", type=int, default=16)
     s.add_argument("--out", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
@@ -169,7 +178,7 @@ def main():
     t.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd_name == "stats":
-        text = stats(a.csv, a.cmd, a.title)
+        text = stats(a.csv, a.cmd, a.title, a.top)
     else:
         text = traffic(a.fetch_csv, a.write_csv, a.cmd_fetch, a.cmd_write, a.title)
     with open(a.out, "w") as fh:
