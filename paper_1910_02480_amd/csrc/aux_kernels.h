@@ -685,7 +685,7 @@ struct WgradTLds {
     }
 };
 
-template <int JBW, int PB, int QC>
+template <int JBW, int PB, int QC, int TG, int TP>
 __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
     using L = WgradTLds<QC, PB>;
     constexpr int GS = L::GS, PS = L::PS;
@@ -720,65 +720,63 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
 #pragma unroll
         for (int b = 0; b < PB; ++b) acc[i][b] = f4{0.f, 0.f, 0.f, 0.f};
 
-    const int s_begin = blockIdx.x * a.strips_per_chunk;
-    const int s_end = min(a.total_strips, s_begin + a.strips_per_chunk);
-    for (int s = s_begin; s < s_end; ++s) {
+    // Staging of a strip: gathered rows 2 u0 - 1 .. 2 u0 + 2 R - 1 (all
+    // columns) and plain rows u0 .. u0 + R - 1 (channels [cp0, cp0 + 16 PB)),
+    // 8 channels per task, at most TG and TP tasks per thread. The next
+    // strip's loads are issued before this strip's MFMAs and land in
+    // registers; they are written to LDS after the MFMAs.
+    constexpr int CGQ = QC / 8, CGP = PB * 2;
+    const int ntq = (2 * R + 1) * Wq * CGQ, ntp = K * CGP;
+    uint4 vq[TG], vp[TP];
+    auto load_strip = [&](int s) {
         const int n = s / a.strips_per_map;
         const int u0 = (s - n * a.strips_per_map) * R;
+        const uint16_t* qn = (const uint16_t*)a.q + ((long)n * a.Hq + 2 * u0 - 1) * Wq * a.qld;
+#pragma unroll
+        for (int t = 0; t < TG; ++t) {
+            const int e = threadIdx.x + 256 * t;
+            const int cg = e % CGQ, pix = e / CGQ;
+            const int row = pix / Wq;
+            const int qi = 2 * u0 - 1 + row;
+            vq[t] = make_uint4(0, 0, 0, 0);
+            if (e < ntq && (unsigned)qi < (unsigned)a.Hq)
+                vq[t] = *(const uint4*)(qn + ((long)row * Wq + (pix - row * Wq)) * a.qld + cg * 8);
+        }
+#pragma unroll
+        for (int t = 0; t < TP; ++t) {
+            const int e = threadIdx.x + 256 * t;
+            const int cg = e % CGP, k = e / CGP;
+            const int u = u0 + k / Wr, v = k - (k / Wr) * Wr;
+            const int c = cp0 + cg * 8;
+            vp[t] = make_uint4(0, 0, 0, 0);
+            if (e < ntp && u < a.Hr && c < a.pc) {
+                const long pix = ((long)n * a.Hr + u) * Wr + v;
+                vp[t] = (c < a.pc0) ? *(const uint4*)((const uint16_t*)a.p + pix * a.pld + c)
+                                    : *(const uint4*)((const uint16_t*)a.p2 + pix * a.p2ld + (c - a.pc0));
+            }
+        }
+    };
+    auto store_strip = [&]() {
+#pragma unroll
+        for (int t = 0; t < TG; ++t) {
+            const int e = threadIdx.x + 256 * t;
+            if (e < ntq) *(uint4*)(Gs + (e / CGQ) * GS + (e % CGQ) * 8) = vq[t];
+        }
+#pragma unroll
+        for (int t = 0; t < TP; ++t) {
+            const int e = threadIdx.x + 256 * t;
+            if (e < ntp) *(uint4*)(Ps + (e / CGP) * PS + (e % CGP) * 8) = vp[t];
+        }
+    };
+
+    const int s_begin = blockIdx.x * a.strips_per_chunk;
+    const int s_end = min(a.total_strips, s_begin + a.strips_per_chunk);
+    if (s_begin < s_end) load_strip(s_begin);
+    for (int s = s_begin; s < s_end; ++s) {
         __syncthreads();  // the previous strip's LDS reads are done
-        // ---- gathered rows 2 u0 - 1 .. 2 u0 + 2 R - 1, all columns, 8 channels per
-        // task; each thread issues up to U loads before its LDS writes
-        constexpr int U = 8;
-        {
-            constexpr int CG = QC / 8;
-            const int ntask = (2 * R + 1) * Wq * CG;
-            const uint16_t* qn = (const uint16_t*)a.q + ((long)n * a.Hq + 2 * u0 - 1) * Wq * a.qld;
-            for (int e0 = threadIdx.x; e0 < ntask; e0 += 256 * U) {
-                uint4 v[U];
-#pragma unroll
-                for (int t = 0; t < U; ++t) {
-                    const int e = e0 + 256 * t;
-                    const int cg = e % CG, pix = e / CG;
-                    const int row = pix / Wq;
-                    const int qi = 2 * u0 - 1 + row;
-                    v[t] = make_uint4(0, 0, 0, 0);
-                    if (e < ntask && (unsigned)qi < (unsigned)a.Hq)
-                        v[t] = *(const uint4*)(qn + ((long)row * Wq + (pix - row * Wq)) * a.qld + cg * 8);
-                }
-#pragma unroll
-                for (int t = 0; t < U; ++t) {
-                    const int e = e0 + 256 * t;
-                    if (e < ntask) *(uint4*)(Gs + (e / CG) * GS + (e % CG) * 8) = v[t];
-                }
-            }
-        }
-        // ---- plain rows u0 .. u0 + R - 1, channels [cp0, cp0 + 16 PB)
-        {
-            constexpr int CG = PB * 2;
-            const int ntask = K * CG;
-            for (int e0 = threadIdx.x; e0 < ntask; e0 += 256 * U) {
-                uint4 w[U];
-#pragma unroll
-                for (int t = 0; t < U; ++t) {
-                    const int e = e0 + 256 * t;
-                    const int cg = e % CG, k = e / CG;
-                    const int u = u0 + k / Wr, v = k - (k / Wr) * Wr;
-                    const int c = cp0 + cg * 8;
-                    w[t] = make_uint4(0, 0, 0, 0);
-                    if (e < ntask && u < a.Hr && c < a.pc) {
-                        const long pix = ((long)n * a.Hr + u) * Wr + v;
-                        w[t] = (c < a.pc0) ? *(const uint4*)((const uint16_t*)a.p + pix * a.pld + c)
-                                           : *(const uint4*)((const uint16_t*)a.p2 + pix * a.p2ld + (c - a.pc0));
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < U; ++t) {
-                    const int e = e0 + 256 * t;
-                    if (e < ntask) *(uint4*)(Ps + (e / CG) * PS + (e % CG) * 8) = w[t];
-                }
-            }
-        }
+        store_strip();
         __syncthreads();
+        if (s + 1 < s_end) load_strip(s + 1);
         // ---- MFMAs: this lane group's 8 reduction pixels are (ul, v0 .. v0 + 7)
         for (int ks = 0; ks < K / 32; ++ks) {
             const int k0 = ks * 32 + 8 * g;

@@ -350,6 +350,8 @@ WgradPlan wgrad_plan(int l, int n, int H, int W, int prec) {
                 const int GS = w.qc + 8, PS = w.BPB * 16 + 8;
                 const int lds = ((2 * R + 1) * 2 * w.Wr * GS + R * w.Wr * PS + 16) * 2;
                 if (lds > 64 * 1024) continue;
+                if ((2 * R + 1) * 2 * w.Wr * (w.qc / 8) > 256 * kWgradTG) continue;  // staging tasks per thread
+                if (R * w.Wr * 2 * w.BPB > 256 * kWgradTP) continue;
                 w.bf16 = 1;
                 w.tr = 1;
                 w.R = R;

@@ -99,6 +99,9 @@ size_t align256(size_t v);
 GemmGeom gemm_geom(int l, bool backward, int prec);
 ActSizes act_sizes(int prec, int n, int H, int W);
 void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout);
+// Staging tasks (16-byte chunks) per thread of the transpose-read weight
+// gradient, gathered and plain operand: the plan keeps a strip within them.
+constexpr int kWgradTG = 9, kWgradTP = 4;
 struct WgradPlan {
     int qc, pc, Hr, Wr, JB, PB, VEC, jtiles, ptiles, nchunks;
     long per_block;

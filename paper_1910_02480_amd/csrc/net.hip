@@ -346,9 +346,9 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
             return drc_fail(DRC_ERR_STATE, "weight_grad: transpose-read plan does not fit layer %d", l);
         dim3 grid(wp.bchunks, wp.bptiles);
         if (wp.JBW == 5)
-            hipLaunchKernelGGL((wgrad_tr_kernel<5, 4, 32>), grid, dim3(256), wp.lds, s, b);
+            hipLaunchKernelGGL((wgrad_tr_kernel<5, 4, 32, kWgradTG, kWgradTP>), grid, dim3(256), wp.lds, s, b);
         else
-            hipLaunchKernelGGL((wgrad_tr_kernel<9, 4, 64>), grid, dim3(256), wp.lds, s, b);
+            hipLaunchKernelGGL((wgrad_tr_kernel<9, 4, 64, kWgradTG, kWgradTP>), grid, dim3(256), wp.lds, s, b);
         const long count = 9L * wp.qc * wp.pc;
         hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)((count + 63) / 64)), dim3(1024), 0, s,
                            (const float*)partial, wp.bchunks, wp.qc, wp.pc, (int)L.tconv, scale, out);
