@@ -660,11 +660,11 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradBArgs a) {
 struct WgradTArgs {
     const void* p; const void* p2;  // plain operand (bf16), channels [0, pc0) from p, the rest from p2
     int pc, pc0, pld, p2ld;
-    const void* q;                  // gathered operand (bf16)
-    int qld;
+    const void* q;                  // gathered operand: bf16, or float32 with QR channels
+    int qc, qld;                    // channels (QC, or QR when float32), elements per pixel
     int Hr, Wr, Hq, Wq;
     int R, strips_per_map, total_strips, strips_per_chunk;
-    float* partial;                 // [chunk][9*QC][pc]
+    float* partial;                 // [chunk][9*qc][pc]
 };
 
 typedef short v4i16 __attribute__((ext_vector_type(4)));
@@ -676,19 +676,14 @@ __device__ __forceinline__ uint2 lds_read_tr16(const uint16_t* p) {
     return __builtin_bit_cast(uint2, v);
 }
 
-template <int QC, int PB>
-struct WgradTLds {
-    static constexpr int GS = QC + 8;       // elements per staged gathered pixel
-    static constexpr int PS = PB * 16 + 8;  // elements per staged plain pixel
-    static __host__ __device__ int bytes(int R, int Wr, int Wq) {
-        return ((2 * R + 1) * Wq * GS + R * Wr * PS + 16) * 2;
-    }
-};
-
-template <int JBW, int PB, int QC, int TG, int TP>
+// QC: staged gathered channels (a multiple of 4; 16-row MFMA blocks of
+// (tap, channel) rows may span several taps); QR > 0: the gathered operand
+// is float32 with QR <= QC channels, rounded to bf16 (RNE) when staged and
+// zero-padded to QC, one pixel per staging task.
+template <int JBW, int PB, int QC, int TG, int TP, int QR>
 __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
-    using L = WgradTLds<QC, PB>;
-    constexpr int GS = L::GS, PS = L::PS;
+    constexpr int GS = QC + 8;       // elements per staged gathered pixel
+    constexpr int PS = PB * 16 + 8;  // elements per staged plain pixel
     constexpr int J = 9 * QC;
     extern __shared__ __align__(16) char smem[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -702,17 +697,20 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
     if (threadIdx.x < 2) *(uint4*)(zero + 8 * threadIdx.x) = make_uint4(0, 0, 0, 0);
 
     // per owned row block: LDS offset of this lane's gathered address relative
-    // to the pixel (2 ul, 2 v) of the staged strip, and whether kw == 0
+    // to the pixel (2 ul, 2 v) of the staged strip (its 4 rows are channels
+    // c .. c + 3 of tap t), whether kw == 0, and whether the rows exist
     int aoff[JBW];
-    bool av[JBW], akw0[JBW];
+    bool av[JBW], alane[JBW], akw0[JBW];
 #pragma unroll
     for (int i = 0; i < JBW; ++i) {
         const int rb = wave + 4 * i;
         av[i] = rb * 16 < J;
-        const int t = av[i] ? rb * 16 / QC : 0, c0 = av[i] ? rb * 16 % QC : 0;
+        const int row = rb * 16 + 4 * qq;
+        alane[i] = row < J;
+        const int t = alane[i] ? row / QC : 0, c = alane[i] ? row % QC : 0;
         const int kh = t / 3, kw = t - 3 * (t / 3);
         akw0[i] = kw == 0;
-        aoff[i] = (kh * Wq + kw - 1) * GS + c0 + 4 * qq;
+        aoff[i] = (kh * Wq + kw - 1) * GS + c;
     }
     f4 acc[JBW][PB];
 #pragma unroll
@@ -725,22 +723,30 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
     // 8 channels per task, at most TG and TP tasks per thread. The next
     // strip's loads are issued before this strip's MFMAs and land in
     // registers; they are written to LDS after the MFMAs.
-    constexpr int CGQ = QC / 8, CGP = PB * 2;
+    constexpr int CGQ = QR ? 1 : QC / 8, CGP = PB * 2;
+    constexpr int QV = QR ? QR : 1;  // float32 values per task held in registers
     const int ntq = (2 * R + 1) * Wq * CGQ, ntp = K * CGP;
     uint4 vq[TG], vp[TP];
+    float vr[TG][QV];
     auto load_strip = [&](int s) {
         const int n = s / a.strips_per_map;
         const int u0 = (s - n * a.strips_per_map) * R;
-        const uint16_t* qn = (const uint16_t*)a.q + ((long)n * a.Hq + 2 * u0 - 1) * Wq * a.qld;
+        const long base = ((long)n * a.Hq + 2 * u0 - 1) * Wq * a.qld;
 #pragma unroll
         for (int t = 0; t < TG; ++t) {
             const int e = threadIdx.x + 256 * t;
             const int cg = e % CGQ, pix = e / CGQ;
             const int row = pix / Wq;
             const int qi = 2 * u0 - 1 + row;
-            vq[t] = make_uint4(0, 0, 0, 0);
-            if (e < ntq && (unsigned)qi < (unsigned)a.Hq)
-                vq[t] = *(const uint4*)(qn + ((long)row * Wq + (pix - row * Wq)) * a.qld + cg * 8);
+            const bool ok = e < ntq && (unsigned)qi < (unsigned)a.Hq;
+            const long off = base + ((long)row * Wq + (pix - row * Wq)) * a.qld;
+            if constexpr (QR > 0) {
+#pragma unroll
+                for (int c = 0; c < QR; ++c) vr[t][c] = ok ? ((const float*)a.q)[off + c] : 0.0f;
+            } else {
+                vq[t] = make_uint4(0, 0, 0, 0);
+                if (ok) vq[t] = *(const uint4*)((const uint16_t*)a.q + off + cg * 8);
+            }
         }
 #pragma unroll
         for (int t = 0; t < TP; ++t) {
@@ -760,7 +766,20 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
 #pragma unroll
         for (int t = 0; t < TG; ++t) {
             const int e = threadIdx.x + 256 * t;
-            if (e < ntq) *(uint4*)(Gs + (e / CGQ) * GS + (e % CGQ) * 8) = vq[t];
+            if constexpr (QR > 0) {
+                uint16_t h[QC];
+#pragma unroll
+                for (int c = 0; c < QC; ++c) h[c] = c < QR ? f32_to_bf16(vr[t][c]) : 0;
+                uint32_t w[QC / 2];
+#pragma unroll
+                for (int c = 0; c < QC / 2; ++c) w[c] = (uint32_t)h[2 * c] | ((uint32_t)h[2 * c + 1] << 16);
+                if (e < ntq) {
+                    if constexpr (QC == 8) *(uint4*)(Gs + e * GS) = make_uint4(w[0], w[1], w[2], w[3]);
+                    else *(uint2*)(Gs + e * GS) = make_uint2(w[0], w[1]);
+                }
+            } else {
+                if (e < ntq) *(uint4*)(Gs + (e / CGQ) * GS + (e % CGQ) * 8) = vq[t];
+            }
         }
 #pragma unroll
         for (int t = 0; t < TP; ++t) {
@@ -794,8 +813,8 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
 #pragma unroll
             for (int i = 0; i < JBW; ++i) {
                 if (!av[i]) continue;
-                const uint2 lo = lds_read_tr16(left && akw0[i] ? zero + 4 * qq : gb + aoff[i]);
-                const uint2 hi = lds_read_tr16(gb + aoff[i] + 8 * GS);
+                const uint2 lo = lds_read_tr16(!alane[i] || (left && akw0[i]) ? zero + 4 * qq : gb + aoff[i]);
+                const uint2 hi = lds_read_tr16(alane[i] ? gb + aoff[i] + 8 * GS : zero + 4 * qq);
                 const uint4 afr = make_uint4(lo.x, lo.y, hi.x, hi.y);
 #pragma unroll
                 for (int b = 0; b < PB; ++b)
@@ -806,16 +825,17 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
         }
     }
     // ---- partial tile: lane holds rows 4*g + r of row block (wave + 4 i), column r16 of block b
-    float* out = a.partial + (long)blockIdx.x * J * a.pc;
+    float* out = a.partial + (long)blockIdx.x * 9 * a.qc * a.pc;
 #pragma unroll
     for (int i = 0; i < JBW; ++i)
 #pragma unroll
         for (int b = 0; b < PB; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int j = (wave + 4 * i) * 16 + 4 * g + r;
+                const int jp = (wave + 4 * i) * 16 + 4 * g + r;  // (tap, staged channel) row
+                const int t = jp / QC, c = jp - (jp / QC) * QC;
                 const int cp = cp0 + b * 16 + r16;
-                if (j < J && cp < a.pc) out[(long)j * a.pc + cp] = acc[i][b][r];
+                if (jp < J && c < a.qc && cp < a.pc) out[((long)t * a.qc + c) * a.pc + cp] = acc[i][b][r];
             }
 }
 

@@ -341,23 +341,38 @@ WgradPlan wgrad_plan(int l, int n, int H, int W, int prec) {
         w.bptiles = (w.pc + 16 * w.BPB - 1) / (16 * w.BPB);
         const bool inst = (w.JBW == 1 && (w.BPB == 2 || w.BPB == 4) && w.QCP == 8) ||
                           (w.JBW == 5 && w.BPB == 4 && w.QCP == 32) || (w.JBW == 9 && w.BPB == 4 && w.QCP == 64);
-        // 16-bit gathered operand with 32 or 64 channels: both operands staged
-        // as plain NHWC tiles and read with LDS transpose reads
+        // Transpose-read kernel: both operands staged as plain NHWC tiles. A
+        // 16-bit gathered operand with 32 or 64 channels, or the float32 one
+        // of E1 (x, 7 channels, staged as 8) and D1 (dy, 3 channels, as 4).
         w.tr = 0;
-        if (inst && (w.qc == 32 || w.qc == 64)) {
-            for (int R = w.Hr; R >= 1; R /= 2) {
-                if ((R * w.Wr) % 32) continue;
-                const int GS = w.qc + 8, PS = w.BPB * 16 + 8;
-                const int lds = ((2 * R + 1) * 2 * w.Wr * GS + R * w.Wr * PS + 16) * 2;
-                if (lds > 64 * 1024) continue;
-                if ((2 * R + 1) * 2 * w.Wr * (w.qc / 8) > 256 * kWgradTG) continue;  // staging tasks per thread
-                if (R * w.Wr * 2 * w.BPB > 256 * kWgradTP) continue;
-                w.bf16 = 1;
-                w.tr = 1;
-                w.R = R;
-                w.lds = lds;
-                break;
-            }
+        w.QR = 0;
+        const bool raw = l == 0 || l == 5;
+        int tqc = 0, tjbw = 0, tpb = 0;
+        if (!raw && (w.qc == 32 || w.qc == 64) && inst) {
+            tqc = w.qc; tjbw = w.JBW; tpb = w.BPB;
+        } else if (raw && w.qc == (l == 0 ? 7 : 3)) {
+            tqc = l == 0 ? 8 : 4;
+            tjbw = ((9 * tqc + 15) / 16 + 3) / 4;
+            tpb = w.pc >= 64 ? 4 : 2;
+        }
+        for (int R = w.Hr; R >= 1 && tqc; R /= 2) {
+            if ((R * w.Wr) % 32) continue;
+            const int GS = tqc + 8, PS = tpb * 16 + 8;
+            const int lds = ((2 * R + 1) * 2 * w.Wr * GS + R * w.Wr * PS + 16) * 2;
+            if (lds > 64 * 1024) continue;
+            const int gtasks = (2 * R + 1) * 2 * w.Wr * (raw ? 1 : tqc / 8);
+            if (gtasks > 256 * (raw ? kWgradTGRaw : kWgradTG)) continue;  // staging tasks per thread
+            if (R * w.Wr * 2 * tpb > 256 * kWgradTP) continue;
+            w.bf16 = 1;
+            w.tr = 1;
+            w.QR = raw ? w.qc : 0;
+            w.QCP = tqc;
+            w.JBW = tjbw;
+            w.BPB = tpb;
+            w.bptiles = (w.pc + 16 * w.BPB - 1) / (16 * w.BPB);
+            w.R = R;
+            w.lds = lds;
+            break;
         }
         for (int R = std::max(1, 128 / w.Wr); R >= 1 && inst && !w.tr; R /= 2) {
             if ((R * w.Wr) % 32) continue;

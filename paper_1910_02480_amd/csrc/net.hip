@@ -342,13 +342,24 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
         b.total_strips = wp.total_strips;
         b.strips_per_chunk = wp.strips_per_chunk;
         b.partial = partial;
-        if (b.Wq != 2 * b.Wr || b.Hq != 2 * b.Hr || wp.qc != (wp.JBW == 5 ? 32 : 64))
-            return drc_fail(DRC_ERR_STATE, "weight_grad: transpose-read plan does not fit layer %d", l);
+        b.qc = wp.qc;
+        const bool raw = wp.QR > 0;
+        if (raw != (l == 0 ? a_raw_c > 0 : (l == 5 ? g_raw : false)))
+            return drc_fail(DRC_ERR_STATE, "weight_grad: operand type does not fit the plan of layer %d", l);
         dim3 grid(wp.bchunks, wp.bptiles);
-        if (wp.JBW == 5)
-            hipLaunchKernelGGL((wgrad_tr_kernel<5, 4, 32, kWgradTG, kWgradTP>), grid, dim3(256), wp.lds, s, b);
+        const int kind = wp.QCP * 100 + wp.JBW * 10 + wp.BPB;
+        if (b.Wq != 2 * b.Wr || b.Hq != 2 * b.Hr)
+            return drc_fail(DRC_ERR_STATE, "weight_grad: transpose-read plan does not fit layer %d", l);
+        if (kind == 3254 && !raw)
+            hipLaunchKernelGGL((wgrad_tr_kernel<5, 4, 32, kWgradTG, kWgradTP, 0>), grid, dim3(256), wp.lds, s, b);
+        else if (kind == 6494 && !raw)
+            hipLaunchKernelGGL((wgrad_tr_kernel<9, 4, 64, kWgradTG, kWgradTP, 0>), grid, dim3(256), wp.lds, s, b);
+        else if (kind == 822 && wp.QR == 7)
+            hipLaunchKernelGGL((wgrad_tr_kernel<2, 2, 8, kWgradTGRaw, kWgradTP, 7>), grid, dim3(256), wp.lds, s, b);
+        else if (kind == 414 && wp.QR == 3)
+            hipLaunchKernelGGL((wgrad_tr_kernel<1, 4, 4, kWgradTGRaw, kWgradTP, 3>), grid, dim3(256), wp.lds, s, b);
         else
-            hipLaunchKernelGGL((wgrad_tr_kernel<9, 4, 64, kWgradTG, kWgradTP>), grid, dim3(256), wp.lds, s, b);
+            return drc_fail(DRC_ERR_STATE, "weight_grad: no transpose-read kernel for layer %d", l);
         const long count = 9L * wp.qc * wp.pc;
         hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)((count + 63) / 64)), dim3(1024), 0, s,
                            (const float*)partial, wp.bchunks, wp.qc, wp.pc, (int)L.tconv, scale, out);
