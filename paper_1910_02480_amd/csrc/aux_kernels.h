@@ -680,8 +680,9 @@ __device__ __forceinline__ uint2 lds_read_tr16(const uint16_t* p) {
 // (tap, channel) rows may span several taps); QR > 0: the gathered operand
 // is float32 with QR <= QC channels, rounded to bf16 (RNE) when staged and
 // zero-padded to QC, one pixel per staging task.
-template <int JBW, int PB, int QC, int TG, int TP, int QR>
-__global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
+template <int NW, int JBW, int PB, int QC, int TG, int TP, int QR>
+__global__ __launch_bounds__(64 * NW) void wgrad_tr_kernel(WgradTArgs a) {
+    constexpr int NT = 64 * NW;
     constexpr int GS = QC + 8;       // elements per staged gathered pixel
     constexpr int PS = PB * 16 + 8;  // elements per staged plain pixel
     constexpr int J = 9 * QC;
@@ -703,7 +704,7 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
     bool av[JBW], alane[JBW], akw0[JBW];
 #pragma unroll
     for (int i = 0; i < JBW; ++i) {
-        const int rb = wave + 4 * i;
+        const int rb = wave + NW * i;
         av[i] = rb * 16 < J;
         const int row = rb * 16 + 4 * qq;
         alane[i] = row < J;
@@ -734,7 +735,7 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
         const long base = ((long)n * a.Hq + 2 * u0 - 1) * Wq * a.qld;
 #pragma unroll
         for (int t = 0; t < TG; ++t) {
-            const int e = threadIdx.x + 256 * t;
+            const int e = threadIdx.x + NT * t;
             const int cg = e % CGQ, pix = e / CGQ;
             const int row = pix / Wq;
             const int qi = 2 * u0 - 1 + row;
@@ -750,7 +751,7 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
         }
 #pragma unroll
         for (int t = 0; t < TP; ++t) {
-            const int e = threadIdx.x + 256 * t;
+            const int e = threadIdx.x + NT * t;
             const int cg = e % CGP, k = e / CGP;
             const int u = u0 + k / Wr, v = k - (k / Wr) * Wr;
             const int c = cp0 + cg * 8;
@@ -765,7 +766,7 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
     auto store_strip = [&]() {
 #pragma unroll
         for (int t = 0; t < TG; ++t) {
-            const int e = threadIdx.x + 256 * t;
+            const int e = threadIdx.x + NT * t;
             if constexpr (QR > 0) {
                 uint16_t h[QC];
 #pragma unroll
@@ -783,7 +784,7 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
         }
 #pragma unroll
         for (int t = 0; t < TP; ++t) {
-            const int e = threadIdx.x + 256 * t;
+            const int e = threadIdx.x + NT * t;
             if (e < ntp) *(uint4*)(Ps + (e / CGP) * PS + (e % CGP) * 8) = vp[t];
         }
     };
@@ -824,7 +825,7 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
             }
         }
     }
-    // ---- partial tile: lane holds rows 4*g + r of row block (wave + 4 i), column r16 of block b
+    // ---- partial tile: lane holds rows 4*g + r of row block (wave + NW i), column r16 of block b
     float* out = a.partial + (long)blockIdx.x * 9 * a.qc * a.pc;
 #pragma unroll
     for (int i = 0; i < JBW; ++i)
@@ -832,7 +833,7 @@ __global__ __launch_bounds__(256) void wgrad_tr_kernel(WgradTArgs a) {
         for (int b = 0; b < PB; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int jp = (wave + 4 * i) * 16 + 4 * g + r;  // (tap, staged channel) row
+                const int jp = (wave + NW * i) * 16 + 4 * g + r;  // (tap, staged channel) row
                 const int t = jp / QC, c = jp - (jp / QC) * QC;
                 const int cp = cp0 + b * 16 + r16;
                 if (jp < J && c < a.qc && cp < a.pc) out[((long)t * a.qc + c) * a.pc + cp] = acc[i][b][r];

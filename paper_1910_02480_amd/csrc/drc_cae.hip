@@ -347,26 +347,36 @@ WgradPlan wgrad_plan(int l, int n, int H, int W, int prec) {
         w.tr = 0;
         w.QR = 0;
         const bool raw = l == 0 || l == 5;
-        int tqc = 0, tjbw = 0, tpb = 0;
+        // D2 (32 gathered x 128 plain channels): 8 waves cover all plain
+        // channels in one tile, so the gathered operand is staged once (with
+        // 64 gathered channels the 8-wave tile would not fit the registers)
+        int tqc = 0, tnw = 4, tjbw = 0, tpb = 0, ttg = 0, ttp = 0;
         if (!raw && (w.qc == 32 || w.qc == 64) && inst) {
-            tqc = w.qc; tjbw = w.JBW; tpb = w.BPB;
+            tqc = w.qc;
+            if (w.qc == 32 && w.pc == 128) {
+                tnw = 8; tpb = 8; tjbw = 3; ttg = kWgradTG8; ttp = kWgradTP8;
+            } else {
+                tjbw = w.JBW; tpb = w.BPB; ttg = kWgradTG; ttp = kWgradTP;
+            }
         } else if (raw && w.qc == (l == 0 ? 7 : 3)) {
             tqc = l == 0 ? 8 : 4;
             tjbw = ((9 * tqc + 15) / 16 + 3) / 4;
             tpb = w.pc >= 64 ? 4 : 2;
+            ttg = kWgradTGRaw; ttp = kWgradTP;
         }
         for (int R = w.Hr; R >= 1 && tqc; R /= 2) {
             if ((R * w.Wr) % 32) continue;
             const int GS = tqc + 8, PS = tpb * 16 + 8;
             const int lds = ((2 * R + 1) * 2 * w.Wr * GS + R * w.Wr * PS + 16) * 2;
-            if (lds > 64 * 1024) continue;
+            if (lds > (tnw == 8 ? 96 : 64) * 1024) continue;
             const int gtasks = (2 * R + 1) * 2 * w.Wr * (raw ? 1 : tqc / 8);
-            if (gtasks > 256 * (raw ? kWgradTGRaw : kWgradTG)) continue;  // staging tasks per thread
-            if (R * w.Wr * 2 * tpb > 256 * kWgradTP) continue;
+            if (gtasks > 64 * tnw * ttg) continue;  // staging tasks per thread
+            if (R * w.Wr * 2 * tpb > 64 * tnw * ttp) continue;
             w.bf16 = 1;
             w.tr = 1;
             w.QR = raw ? w.qc : 0;
             w.QCP = tqc;
+            w.NW = tnw;
             w.JBW = tjbw;
             w.BPB = tpb;
             w.bptiles = (w.pc + 16 * w.BPB - 1) / (16 * w.BPB);

@@ -101,8 +101,9 @@ ActSizes act_sizes(int prec, int n, int H, int W);
 void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout);
 // Staging tasks (16-byte chunks) per thread of the transpose-read weight
 // gradient, gathered and plain operand: the plan keeps a strip within them.
-constexpr int kWgradTG = 9, kWgradTP = 4;
-constexpr int kWgradTGRaw = 5;  // float32 gathered operand: one pixel per task
+constexpr int kWgradTG = 9, kWgradTP = 4;   // 4-wave workgroups
+constexpr int kWgradTG8 = 5, kWgradTP8 = 4;  // 8-wave workgroups
+constexpr int kWgradTGRaw = 5;  // float32 gathered operand (4 waves): one pixel per task
 struct WgradPlan {
     int qc, pc, Hr, Wr, JB, PB, VEC, jtiles, ptiles, nchunks;
     long per_block;
@@ -110,7 +111,7 @@ struct WgradPlan {
     // BF16 path with LDS-staged operands (bf16 = 1 when it applies)
     int bf16, QCP, JBW, BPB, R, strips_per_map, total_strips, strips_per_chunk, bchunks, bptiles, qcs, lds;
     int tr;  // bf16 == 1 and the transpose-read kernel applies (QCP staged channels, QR float32 ones)
-    int QR;
+    int QR, NW;
 };
 WgradPlan wgrad_plan(int l, int n, int H, int W, int prec);
 void colsum_split(long npix, int* nblocks, long* per_block);

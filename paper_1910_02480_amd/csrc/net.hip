@@ -347,17 +347,20 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
         if (raw != (l == 0 ? a_raw_c > 0 : (l == 5 ? g_raw : false)))
             return drc_fail(DRC_ERR_STATE, "weight_grad: operand type does not fit the plan of layer %d", l);
         dim3 grid(wp.bchunks, wp.bptiles);
-        const int kind = wp.QCP * 100 + wp.JBW * 10 + wp.BPB;
+        const int kind = wp.NW * 10000 + wp.QCP * 100 + wp.JBW * 10 + wp.BPB;
         if (b.Wq != 2 * b.Wr || b.Hq != 2 * b.Hr)
             return drc_fail(DRC_ERR_STATE, "weight_grad: transpose-read plan does not fit layer %d", l);
-        if (kind == 3254 && !raw)
-            hipLaunchKernelGGL((wgrad_tr_kernel<5, 4, 32, kWgradTG, kWgradTP, 0>), grid, dim3(256), wp.lds, s, b);
-        else if (kind == 6494 && !raw)
-            hipLaunchKernelGGL((wgrad_tr_kernel<9, 4, 64, kWgradTG, kWgradTP, 0>), grid, dim3(256), wp.lds, s, b);
-        else if (kind == 822 && wp.QR == 7)
-            hipLaunchKernelGGL((wgrad_tr_kernel<2, 2, 8, kWgradTGRaw, kWgradTP, 7>), grid, dim3(256), wp.lds, s, b);
-        else if (kind == 414 && wp.QR == 3)
-            hipLaunchKernelGGL((wgrad_tr_kernel<1, 4, 4, kWgradTGRaw, kWgradTP, 3>), grid, dim3(256), wp.lds, s, b);
+        const dim3 block(64 * wp.NW);
+        if (kind == 43254 && !raw)
+            hipLaunchKernelGGL((wgrad_tr_kernel<4, 5, 4, 32, kWgradTG, kWgradTP, 0>), grid, block, wp.lds, s, b);
+        else if (kind == 83238 && !raw)
+            hipLaunchKernelGGL((wgrad_tr_kernel<8, 3, 8, 32, kWgradTG8, kWgradTP8, 0>), grid, block, wp.lds, s, b);
+        else if (kind == 46494 && !raw)
+            hipLaunchKernelGGL((wgrad_tr_kernel<4, 9, 4, 64, kWgradTG, kWgradTP, 0>), grid, block, wp.lds, s, b);
+        else if (kind == 40822 && wp.QR == 7)
+            hipLaunchKernelGGL((wgrad_tr_kernel<4, 2, 2, 8, kWgradTGRaw, kWgradTP, 7>), grid, block, wp.lds, s, b);
+        else if (kind == 40414 && wp.QR == 3)
+            hipLaunchKernelGGL((wgrad_tr_kernel<4, 1, 4, 4, kWgradTGRaw, kWgradTP, 3>), grid, block, wp.lds, s, b);
         else
             return drc_fail(DRC_ERR_STATE, "weight_grad: no transpose-read kernel for layer %d", l);
         const long count = 9L * wp.qc * wp.pc;
