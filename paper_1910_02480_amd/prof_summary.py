@@ -26,14 +26,19 @@ import re
 _HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 256 << 20  # one read and one write stream of this size
 
-# (regex on the demangled name, label); first match wins
+# (regex on the demangled name, label); first match wins. A first group,
+# when present, is the precision template argument (0 FP32, 1 BF16, 2 FP8).
+# Some layer-kernel instantiations serve two layers (same channel counts).
 _LABELS = (
-    (r"conv_layer_kernel<1, 0, 8, 8, 32,", "forward E1"),
-    (r"conv_layer_kernel<1, 0, 32, 32, 64,", "forward E2"),
-    (r"conv_layer_kernel<1, 0, 64, 64, 128,", "forward E3"),
-    (r"tconv_pairs_kernel<1, 128, 128, 64,", "forward D3"),
-    (r"tconv_pairs_kernel<1, 128, 64, 32,", "forward D2"),
-    (r"tconv_merged_kernel<1, 64, 32, 3,", "forward D1"),
+    (r"conv_layer_kernel<(\d), \d+, 8, 8, 32,", "forward E1"),
+    (r"conv_layer_kernel<(\d), \d+, 32, 32, 64,", "forward E2"),
+    (r"conv_layer_kernel<(\d), \d+, 64, 64, 128,", "forward E3 / data gradient D3"),
+    (r"conv_layer_kernel<(\d), \d+, 32, 32, 128,", "data gradient D2"),
+    (r"conv_layer_kernel<(\d), \d+, 4, 4, 64,", "data gradient D1"),
+    (r"tconv_pairs_kernel<(\d), 128, 128, 64,", "forward D3 / data gradient E3"),
+    (r"tconv_pairs_kernel<(\d), 128, 64, 32,", "forward D2"),
+    (r"tconv_pairs_kernel<(\d), 64, 64, 32,", "data gradient E2"),
+    (r"tconv_merged_kernel<(\d), 64, 32, 3,", "forward D1"),
     (r"cae_fused_forward_kernel<\d+, \d+, false>", "forward fused"),
     (r"cae_fused_forward_kernel<\d+, \d+, true>", "recompute fused"),
     (r"pack_weights_kernel|pack_all_kernel", "weight pack"),
@@ -42,6 +47,7 @@ _LABELS = (
     (r"envmap_pdf_kernel", "envmap pdf"),
     (r"interp_weights_kernel", "interp weights"),
     (r"cae_fused_dgrad_kernel", "fused data gradients"),
+    (r"wgrad_tr_kernel", "weight gradient (BF16, transpose reads)"),
     (r"wgrad_bf16_kernel", "weight gradient (BF16)"),
     (r"wgrad_kernel", "weight gradient (FP32)"),
     (r"wgrad_final_kernel", "weight-gradient reduction"),
@@ -50,12 +56,14 @@ _LABELS = (
     (r"l1_", "L1 loss"),
     (r"elementwise.*Mul|Mul.*elementwise", "copy (torch.mul, 256 MiB)"),
 )
+_PREC = {"0": "FP32", "1": "BF16", "2": "FP8"}
 
 
 def label(name: str) -> str | None:
     for pat, lab in _LABELS:
-        if re.search(pat, name):
-            return lab
+        m = re.search(pat, name)
+        if m:
+            return f"{_PREC.get(m.group(1), '?')} {lab}" if m.groups() else lab
     return None
 
 
