@@ -429,6 +429,19 @@ def main():
             legs[f"{comp}_train_step"]["breakdown_ms"] = {names[k]: round(ms_s[k], 4) for k in range(23)
                                                           if calls_s[k]}
             log(f"{comp} train step (batch {nt}): {nt / tt:,.0f} maps/s, {tt * 1e3:.3f} ms")
+            if comp == "bf16":
+                # augmentation of the step's batch (rotations and mirrors), before the step
+                gen = torch.Generator(device=dev)
+                gen.manual_seed(9)
+                roll = torch.randint(0, H, (nt,), generator=gen, device=dev, dtype=torch.int32)
+                flip = torch.randint(0, 2, (nt,), generator=gen, device=dev, dtype=torch.int32)
+                xa, ta = torch.empty_like(xt), torch.empty_like(tg)
+                tau = event_timed(lambda: B.drc_augment(xt, tg, roll, flip, xa, ta), args.steps, args.warmup)
+                ab = 2 * nt * H * H * (7 + 3) * 4
+                legs["bf16_augment"] = {"batch": nt, "ms": tau * 1e3, "GB/s": ab / tau / 1e9,
+                                        "hbm_frac": ab / tau / 1e9 / PEAK_HBM_GBS, "alg_bytes": ab,
+                                        "share_of_step": tau / tt}
+                log(f"augmentation of the batch: {tau * 1e3:.4f} ms ({ab / tau / 1e9:.0f} GB/s)")
         # ---------------- mixed-resolution frame: one graph replay per frame
         legs["bf16_mixed_frame"] = mixed_frame_leg(cae, tune_path, args)
         legs["speedup_bf16_vs_f32"] = {

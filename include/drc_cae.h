@@ -267,6 +267,21 @@ drc_status drc_envmap_pdf(const float* d_cdf_u, const float* d_cdf_v, int n, int
 drc_status drc_interp_weights(const float* d_normals, int Hi, int Wi, int r, const float* d_cache_normals,
                               float eps, int32_t* d_idx, float* d_prob, void* stream);
 
+/* Training-data augmentation (Sec. 5: the data loader rotates and flips the
+ * training maps), read as the symmetries of the hemispherical lat-long map
+ * (normal along +Z, Sec. 4.3): map m is turned by d_roll[m] columns about the
+ * normal (any integer, taken mod W) and, if d_flip[m] != 0, mirrored through
+ * a plane containing the normal. The value of column u goes to column
+ * (u + k) mod W, or (k - 1 - u) mod W when flipped (k = roll mod W); the
+ * normal channels (Nx, Ny) are reflected (Ny -> -Ny) when flipped and then
+ * rotated by 2 pi k / W; R, G, B, Nz, D and the target values are copied.
+ * d_x [n, H, W, 7] -> d_x_out, and d_t [n, H, W, 3] -> d_t_out (both NULL to
+ * leave targets out). float32, d_roll and d_flip int32 [n], all on the
+ * device, 4-byte aligned; outputs must not overlap inputs. n = 0 does
+ * nothing; H, W >= 1. */
+drc_status drc_augment(const float* d_x, const float* d_t, int n, int H, int W, const int32_t* d_roll,
+                       const int32_t* d_flip, float* d_x_out, float* d_t_out, void* stream);
+
 /* Tile-shape tuning: time each implemented tile shape of every layer for
  * an n x H x W forward batch on the given stream and write the fastest to
  * the JSON cache file path (keyed by arch, precision, layer and

@@ -71,6 +71,7 @@ _SIGS = {
     "drc_envmap_sample": (_I, [_VP, _VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
     "drc_envmap_pdf": (_I, [_VP, _VP, _I, _I, _I, _I, _VP, _VP, _VP]),
     "drc_interp_weights": (_I, [_VP, _I, _I, _I, _VP, ctypes.c_float, _VP, _VP, _VP]),
+    "drc_augment": (_I, [_VP, _VP, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
     "drc_cae_autotune": (_I, [_VP, _I, _I, _I, _VP, _VP, _SZ, ctypes.c_char_p, _VP]),
     "drc_cae_set_tile": (_I, [_VP, _I, _I, _I]),
     "drc_cae_profile": (_I, [_VP, _I]),
@@ -259,6 +260,13 @@ def drc_interp_weights(normals, r, cache_normals, eps, idx, prob, stream=None):
     Hi, Wi = int(normals.shape[0]), int(normals.shape[1])
     _check(lib().drc_interp_weights(_ptr(normals), Hi, Wi, int(r), _ptr(cache_normals), float(eps), _ptr(idx),
                                     _ptr(prob), _stream(stream)))
+
+
+def drc_augment(x, t, roll, flip, x_out, t_out=None, stream=None):
+    """x [n, H, W, 7] (and t [n, H, W, 3] or None), roll / flip int32 [n] -> x_out (t_out)."""
+    n, H, W = _nhw(x, 7)
+    _check(lib().drc_augment(_ptr(x), _ptr(t), n, H, W, _ptr(roll), _ptr(flip), _ptr(x_out), _ptr(t_out),
+                             _stream(stream)))
 
 
 def drc_cae_autotune(h, x, ws, tune_cache, stream=None):

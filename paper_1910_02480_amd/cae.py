@@ -88,6 +88,16 @@ class CAE:
         B.drc_cae_calibrate_fp8(self.h, x, ws)
 
 
+def augment(x: torch.Tensor, t: torch.Tensor | None, roll: torch.Tensor, flip: torch.Tensor):
+    """Rotated / mirrored copies of training maps (drc_augment): map m turned
+    by roll[m] columns about the normal and mirrored where flip[m] != 0."""
+    xo = torch.empty_like(x)
+    to = None if t is None else torch.empty_like(t)
+    B.drc_augment(x.contiguous(), None if t is None else t.contiguous(), roll.to(torch.int32).contiguous(),
+                  flip.to(torch.int32).contiguous(), xo, to)
+    return xo, to
+
+
 class Trainer:
     """Adam training on the device: one drc_cae_step per call."""
 

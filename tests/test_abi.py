@@ -130,3 +130,14 @@ def test_interp_rejects_bad_arguments(B):
     assert L.drc_interp_weights(None, 8, 8, 4, None, f(1e-3), None, None, None) == 1
     assert L.drc_interp_weights(16, 8, 8, 4, 16, f(1e-3), 8, 16, None) == 1   # d_idx not 16-byte aligned
     assert L.drc_interp_weights(2, 8, 8, 4, 16, f(1e-3), 16, 16, None) == 1   # d_normals not 4-byte aligned
+
+
+def test_augment_rejects_bad_arguments(B):
+    L = B.lib()
+    assert L.drc_augment(None, None, 1, 0, 8, None, None, None, None, None) == 2
+    assert L.drc_augment(None, None, -1, 8, 8, None, None, None, None, None) == 2
+    assert L.drc_augment(None, None, 0, 8, 8, None, None, None, None, None) == 0     # empty batch
+    assert L.drc_augment(None, None, 1, 8, 8, None, None, None, None, None) == 1
+    assert L.drc_augment(16, None, 1, 8, 8, 16, 16, 16, None, None) == 1            # output overlaps input
+    assert L.drc_augment(16, None, 1, 8, 8, 16, 16, 4096, 64, None) == 1            # target out without target
+    assert L.drc_augment(16, 64, 1, 8, 8, 16, 16, 4096, None, None) == 1            # target without target out
