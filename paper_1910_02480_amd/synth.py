@@ -43,6 +43,7 @@ SEED_MIXED_PERM = 2
 SEED_TRAIN = 3
 SEED_ENVMAP = 4
 SEED_GBUFFER = 5
+SEED_UNET = 6
 
 
 def param_count() -> int:
@@ -207,6 +208,46 @@ def gbuffer_normals(hi: int, wi: int, seed: int = SEED_GBUFFER, background: floa
     n /= np.linalg.norm(n, axis=-1, keepdims=True)
     n[rng.random((hi, wi)) < background] = 0.0
     return n.astype(np.float32)
+
+
+# The paper's own network (U-Net-like, Sec. 4.3 / 5): (name, cin, cout,
+# batch norm) in execution order, widths 64-128-256 with a 256-channel 4x4
+# bottleneck; "out" is the 1x1 output convolution.
+UNET_LAYERS = (
+    ("enc1a", 7, 64, True), ("enc1b", 64, 64, True),
+    ("enc2a", 64, 128, True), ("enc2b", 128, 128, True),
+    ("enc3a", 128, 256, True), ("enc3b", 256, 256, True),
+    ("mid_a", 256, 256, True), ("mid_b", 256, 256, True),
+    ("dec3a", 512, 256, True), ("dec3b", 256, 256, True),
+    ("dec2a", 384, 128, True), ("dec2b", 128, 128, True),
+    ("dec1a", 192, 64, False), ("dec1b", 64, 64, False),
+    ("out", 64, 3, False),
+)
+
+
+def unet_params(seed: int = SEED_UNET):
+    """Random-init parameters of the U-Net, float32: a list of per-layer
+    dicts {"w": [Cout, 3, 3, Cin] ([Cout, Cin] for the 1x1), "b": [Cout],
+    and for batch-normalised layers "gamma", "beta", "mean", "var"}.
+
+    Draw order per layer: w Kaiming-normal (std sqrt(2 / fan_in)), b
+    U(+-1/sqrt(fan_in)), then gamma U[0.8, 1.2], beta U[-0.1, 0.1], mean
+    U[-0.1, 0.1], var U[0.5, 1.5] (so that batch norm is not the identity).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for name, ci, co, bn in UNET_LAYERS:
+        k = 1 if name == "out" else 9
+        fan = k * ci
+        w = rng.standard_normal((co, ci) if k == 1 else (co, 3, 3, ci)) * np.sqrt(2.0 / fan)
+        d = {"w": w.astype(np.float32), "b": rng.uniform(-1, 1, co).astype(np.float32) / np.float32(np.sqrt(fan))}
+        if bn:
+            d["gamma"] = rng.uniform(0.8, 1.2, co).astype(np.float32)
+            d["beta"] = rng.uniform(-0.1, 0.1, co).astype(np.float32)
+            d["mean"] = rng.uniform(-0.1, 0.1, co).astype(np.float32)
+            d["var"] = rng.uniform(0.5, 1.5, co).astype(np.float32)
+        out.append(d)
+    return out
 
 
 # Mixed-resolution frame: 50 % 32x32, 35 % 64x64, 15 % 128x128, shuffled.
