@@ -156,6 +156,29 @@ def interp_leg(B, dev, steps, warmup, Hi=1080, Wi=1920, r=16, eps=1e-4):
             "alg_bytes": by}
 
 
+def unet_leg(B, dev, steps, warmup, n=4096, H=32):
+    """The paper's own network (inference, BF16 activations) over n maps of
+    H x H, the paper's map size. FLOPs are nominal: 2 * cout * cin * taps per
+    output pixel of every convolution."""
+    import torch
+    from paper_1910_02480_amd import synth
+    div = (1, 1, 2, 2, 4, 4, 8, 8, 4, 4, 2, 2, 1, 1, 1)  # resolution divisor per layer
+    flops = sum(2.0 * co * ci * (1 if name == "out" else 9) * n * (H // d) ** 2
+                for (name, ci, co, _), d in zip(synth.UNET_LAYERS, div))
+    u = B.drc_unet_create()
+    try:
+        B.drc_unet_set_params(u, torch.from_numpy(synth.unet_flat(synth.unet_params(0))).to(dev))
+        x = gen_maps(n, H).to(dev)
+        y = torch.empty((n, H, H, 3), device=dev)
+        ws = torch.empty(B.drc_unet_workspace_size(n, H, H) + 256, dtype=torch.uint8, device=dev)
+        ws = ws[(-ws.data_ptr()) % 256:]
+        t = event_timed(lambda: B.drc_unet_forward(u, x, y, ws), steps, warmup)
+    finally:
+        B.drc_unet_destroy(u)
+    return {"maps": n, "H": H, "ms": t * 1e3, "maps_per_s": n / t, "gflop_per_map": flops / n / 1e9,
+            "TFLOP/s": flops / t / 1e12, "mfma_frac_flop_based": flops / t / (PEAK_TFLOPS["bf16"] * 1e12)}
+
+
 def read_profile(B, h):
     return B.drc_cae_profile_read(h)
 
@@ -442,6 +465,10 @@ def main():
                                         "hbm_frac": ab / tau / 1e9 / PEAK_HBM_GBS, "alg_bytes": ab,
                                         "share_of_step": tau / tt}
                 log(f"augmentation of the batch: {tau * 1e3:.4f} ms ({ab / tau / 1e9:.0f} GB/s)")
+        # ---------------- the paper's own network (inference), 4096 maps of 32x32
+        legs["unet_bf16_fwd_4096x32x32"] = un = unet_leg(B, dev, max(3, args.steps // 4), 2)
+        log(f"paper's U-Net forward, 4096 maps of 32x32: {un['maps_per_s']:,.0f} maps/s "
+            f"({un['ms']:.3f} ms, {un['TFLOP/s']:.0f} TFLOP/s)")
         # ---------------- mixed-resolution frame: one graph replay per frame
         legs["bf16_mixed_frame"] = mixed_frame_leg(cae, tune_path, args)
         legs["speedup_bf16_vs_f32"] = {

@@ -282,6 +282,35 @@ drc_status drc_interp_weights(const float* d_normals, int Hi, int Wi, int r, con
 drc_status drc_augment(const float* d_x, const float* d_t, int n, int H, int W, const int32_t* d_roll,
                        const int32_t* d_flip, float* d_x_out, float* d_t_out, void* stream);
 
+/* The paper's own network (Sec. 4.3 and Sec. 5), inference form, BF16
+ * activations with FP32 accumulation: a U-Net-like autoencoder with two 3x3
+ * convolutions (stride 1, zero padding 1) per stage, each followed by batch
+ * normalisation (running statistics, eps 1e-5) and LeakyReLU (slope 0.01);
+ * 2x2 max-pool between encoder stages; decoder stages upsample 2x
+ * bilinearly (half-pixel centres, edges clamped), concatenate
+ * [upsampled | skip] and apply two 3x3 convolutions (the output stage
+ * without batch norm); a final 1x1 convolution to 3 channels with ReLU.
+ * Widths 64-128-256 with a 256-channel bottleneck (three 2x2 poolings;
+ * 4.83 M weights, the 20 MB model of Sec. 5). Layer order and shapes
+ * (cin -> cout): enc1a 7->64, enc1b 64->64, enc2a 64->128, enc2b 128->128,
+ * enc3a 128->256, enc3b 256->256, mid_a 256->256, mid_b 256->256,
+ * dec3a 512->256, dec3b 256->256, dec2a 384->128, dec2b 128->128,
+ * dec1a 192->64, dec1b 64->64 (no batch norm for dec1a/dec1b), out 64->3
+ * (1x1). Parameters: one flat float32 vector, per layer W[co][kh][kw][ci]
+ * (the 1x1: W[co][ci]), b[co], then for batch-normalised layers gamma, beta,
+ * running mean, running var (each [co]). Maps NHWC float32, x with the 7
+ * channels of drc_cae_forward, y with 3; H and W multiples of 8.
+ * create allocates the handle's packed weights; the other calls only
+ * enqueue work on the stream (no allocation, no synchronisation). */
+typedef struct drc_unet drc_unet;
+drc_status drc_unet_create(drc_unet** out);
+void drc_unet_destroy(drc_unet* u);
+size_t drc_unet_num_params(void);
+drc_status drc_unet_set_params(drc_unet* u, const float* d_params, void* stream);
+drc_status drc_unet_workspace_size(int n, int H, int W, size_t* bytes);
+drc_status drc_unet_forward(drc_unet* u, const float* d_x, float* d_y, int n, int H, int W, void* d_ws,
+                            size_t ws_bytes, void* stream);
+
 /* Tile-shape tuning: time each implemented tile shape of every layer for
  * an n x H x W forward batch on the given stream and write the fastest to
  * the JSON cache file path (keyed by arch, precision, layer and

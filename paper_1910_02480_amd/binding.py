@@ -72,6 +72,12 @@ _SIGS = {
     "drc_envmap_pdf": (_I, [_VP, _VP, _I, _I, _I, _I, _VP, _VP, _VP]),
     "drc_interp_weights": (_I, [_VP, _I, _I, _I, _VP, ctypes.c_float, _VP, _VP, _VP]),
     "drc_augment": (_I, [_VP, _VP, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
+    "drc_unet_create": (_I, [ctypes.POINTER(_VP)]),
+    "drc_unet_destroy": (None, [_VP]),
+    "drc_unet_num_params": (_SZ, []),
+    "drc_unet_set_params": (_I, [_VP, _VP, _VP]),
+    "drc_unet_workspace_size": (_I, [_I, _I, _I, ctypes.POINTER(_SZ)]),
+    "drc_unet_forward": (_I, [_VP, _VP, _VP, _I, _I, _I, _VP, _SZ, _VP]),
     "drc_cae_autotune": (_I, [_VP, _I, _I, _I, _VP, _VP, _SZ, ctypes.c_char_p, _VP]),
     "drc_cae_set_tile": (_I, [_VP, _I, _I, _I]),
     "drc_cae_profile": (_I, [_VP, _I]),
@@ -267,6 +273,35 @@ def drc_augment(x, t, roll, flip, x_out, t_out=None, stream=None):
     n, H, W = _nhw(x, 7)
     _check(lib().drc_augment(_ptr(x), _ptr(t), n, H, W, _ptr(roll), _ptr(flip), _ptr(x_out), _ptr(t_out),
                              _stream(stream)))
+
+
+def drc_unet_create():
+    u = _VP()
+    _check(lib().drc_unet_create(ctypes.byref(u)))
+    return u.value
+
+
+def drc_unet_destroy(u):
+    lib().drc_unet_destroy(u)
+
+
+def drc_unet_num_params():
+    return int(lib().drc_unet_num_params())
+
+
+def drc_unet_set_params(u, params, stream=None):
+    _check(lib().drc_unet_set_params(u, _ptr(params), _stream(stream)))
+
+
+def drc_unet_workspace_size(n, H, W):
+    b = _SZ()
+    _check(lib().drc_unet_workspace_size(n, H, W, ctypes.byref(b)))
+    return int(b.value)
+
+
+def drc_unet_forward(u, x, y, ws, stream=None):
+    n, H, W = _nhw(x, 7)
+    _check(lib().drc_unet_forward(u, _ptr(x), _ptr(y), n, H, W, _ptr(ws), _nbytes(ws), _stream(stream)))
 
 
 def drc_cae_autotune(h, x, ws, tune_cache, stream=None):

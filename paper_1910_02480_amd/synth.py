@@ -250,6 +250,17 @@ def unet_params(seed: int = SEED_UNET):
     return out
 
 
+def unet_flat(params) -> np.ndarray:
+    """The flat float32 parameter vector of the U-Net: per layer W (C order),
+    b, then gamma, beta, mean, var for batch-normalised layers."""
+    parts = []
+    for q in params:
+        parts += [q["w"].reshape(-1), q["b"]]
+        if "gamma" in q:
+            parts += [q["gamma"], q["beta"], q["mean"], q["var"]]
+    return np.concatenate(parts).astype(np.float32)
+
+
 # Mixed-resolution frame: 50 % 32x32, 35 % 64x64, 15 % 128x128, shuffled.
 MIXED_FRACTIONS = ((32, 0.50), (64, 0.35), (128, 0.15))
 

@@ -141,3 +141,16 @@ def test_augment_rejects_bad_arguments(B):
     assert L.drc_augment(16, None, 1, 8, 8, 16, 16, 16, None, None) == 1            # output overlaps input
     assert L.drc_augment(16, None, 1, 8, 8, 16, 16, 4096, 64, None) == 1            # target out without target
     assert L.drc_augment(16, 64, 1, 8, 8, 16, 16, 4096, None, None) == 1            # target without target out
+
+
+def test_unet_host_checks(B):
+    L = B.lib()
+    sz = ctypes.c_size_t()
+    assert L.drc_unet_workspace_size(1, 12, 16, ctypes.byref(sz)) == 2
+    assert L.drc_unet_workspace_size(0, 32, 32, ctypes.byref(sz)) == 2
+    assert L.drc_unet_workspace_size(1, 32, 32, None) == 1
+    assert L.drc_unet_forward(None, None, None, 1, 32, 32, None, 0, None) == 1
+    assert L.drc_unet_set_params(None, None, None) == 1
+    assert L.drc_unet_create(None) == 1
+    from oracle import unet as U
+    assert B.drc_unet_num_params() == U.num_params()
