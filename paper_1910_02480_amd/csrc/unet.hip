@@ -100,6 +100,7 @@ struct ConvArgsU {
     const float* scale;
     const float* shift;
     void* out;            // [n, H, W, cout] bf16, or float32 when out_f32
+    const uint4* zero;    // 16 zero bytes: the load of a tap outside the map
     int n, H, W, cinp, cout, ks, act, out_f32;
 };
 
@@ -148,30 +149,35 @@ __global__ __launch_bounds__(256) void unet_conv_kernel(ConvArgsU a) {
             c = 0;
         }
         const int dy = TAPS == 9 ? t / 3 - 1 : 0, dx = TAPS == 9 ? t % 3 - 1 : 0;
+        // every lane loads (taps outside the map read the zero block): loads
+        // under a per-lane condition would make the compiler wait for all
+        // loads in flight before the MFMAs that follow
 #pragma unroll
         for (int j = 0; j < NPW; ++j) {
             const int yy = px[j].y + dy, xx = px[j].x + dx;
             const bool ok = px[j].v && t < TAPS && (unsigned)yy < (unsigned)a.H && (unsigned)xx < (unsigned)a.W;
-            bf[j] = make_uint4(0, 0, 0, 0);
-            if (ok) bf[j] = *(const uint4*)(a.in + px[j].base + ((long)dy * a.W + dx) * a.cinp + c);
+            const uint4* src = (const uint4*)(a.in + px[j].base + ((long)dy * a.W + dx) * a.cinp + c);
+            bf[j] = *(ok ? src : a.zero);
         }
     };
     auto load_a = [&](int ks, uint4 (&af)[MT]) {
 #pragma unroll
         for (int i = 0; i < MT; ++i) {
             const int rb = rb0 + i;
-            af[i] = rb < nrb ? a.pack[((long)rb * a.ks + ks) * 64 + lane] : make_uint4(0, 0, 0, 0);
+            af[i] = *(rb < nrb ? a.pack + ((long)rb * a.ks + ks) * 64 + lane : a.zero);
         }
     };
     uint4 af[MT], bf[NPW];
     load_a(0, af);
     load_b(0, bf);
     for (int ks = 0; ks < a.ks; ++ks) {
+        // the next step's loads are unconditional (the last step reloads its
+        // own fragments): a load under a condition would make the compiler
+        // wait for every load in flight before the MFMAs
+        const int kn = min(ks + 1, a.ks - 1);
         uint4 an[MT], bn[NPW];
-        if (ks + 1 < a.ks) {
-            load_a(ks + 1, an);
-            load_b(ks + 1, bn);
-        }
+        load_a(kn, an);
+        load_b(kn, bn);
 #pragma unroll
         for (int i = 0; i < MT; ++i)
 #pragma unroll
@@ -179,12 +185,10 @@ __global__ __launch_bounds__(256) void unet_conv_kernel(ConvArgsU a) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i]),
                                                                   __builtin_bit_cast(bf16x8, bf[j]), acc[i][j], 0,
                                                                   0, 0);
-        if (ks + 1 < a.ks) {
 #pragma unroll
-            for (int i = 0; i < MT; ++i) af[i] = an[i];
+        for (int i = 0; i < MT; ++i) af[i] = an[i];
 #pragma unroll
-            for (int j = 0; j < NPW; ++j) bf[j] = bn[j];
-        }
+        for (int j = 0; j < NPW; ++j) bf[j] = bn[j];
     }
     // epilogue: lane holds channels 16 rb + 4 g .. + 3 of pixel 16 pb + r16
 #pragma unroll
@@ -349,6 +353,7 @@ UnetWs unet_ws(int n, int H, int W) {
 
 struct drc_unet {
     int device;
+    uint4* zero;  // 256 zero bytes
     uint16_t* pack[kUnetLayers];
     float* scale[kUnetLayers];
     float* shift[kUnetLayers];
@@ -388,9 +393,17 @@ extern "C" drc_status drc_unet_create(drc_unet** out) {
         offs[l][2] = bytes;
         bytes += ((size_t)kUnet[l].cout * 4 + 255) / 256 * 256;
     }
+    const size_t zoff = bytes;
+    bytes += 256;
     if (hipMalloc(&u->mem, bytes) != hipSuccess) {
         delete u;
         return drc_fail(DRC_ERR_HIP, "unet_create: device allocation of %zu bytes failed", bytes);
+    }
+    u->zero = (uint4*)((char*)u->mem + zoff);
+    if (hipMemset(u->zero, 0, 256) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(u->mem);
+        delete u;
+        return drc_fail(DRC_ERR_HIP, "unet_create: clearing the zero block failed");
     }
     for (int l = 0; l < kUnetLayers; ++l) {
         u->pack[l] = (uint16_t*)((char*)u->mem + offs[l][0]);
@@ -482,6 +495,7 @@ extern "C" drc_status drc_unet_forward(drc_unet* u, const float* d_x, float* d_y
         c.scale = u->scale[l];
         c.shift = u->shift[l];
         c.out = out;
+        c.zero = u->zero;
         c.n = n;
         c.H = h;
         c.W = w;
@@ -491,7 +505,6 @@ extern "C" drc_status drc_unet_forward(drc_unet* u, const float* d_x, float* d_y
         c.act = l == kUnetLayers - 1 ? 2 : 1;
         c.out_f32 = l == kUnetLayers - 1;
         if (kUnet[l].taps == 1) launch_conv<1, 4, 1>(c, s);
-        else if (c.cout >= 128) launch_conv<4, 2, 9>(c, s);
         else launch_conv<4, 4, 9>(c, s);
     };
     auto pool = [&](const uint16_t* in, uint16_t* out, int h, int w, int C) {
