@@ -46,6 +46,13 @@ _LABELS = (
     (r"envmap_sample_kernel", "envmap sample"),
     (r"envmap_pdf_kernel", "envmap pdf"),
     (r"interp_weights_kernel", "interp weights"),
+    (r"augment_kernel", "augmentation"),
+    (r"unet_conv_kernel<\d+, \d+, 9>", "U-Net 3x3 convolution"),
+    (r"unet_conv_kernel<\d+, \d+, 1>", "U-Net 1x1 output convolution"),
+    (r"unet_upcat_kernel", "U-Net upsample + concat"),
+    (r"unet_pool_kernel", "U-Net max-pool"),
+    (r"unet_cast_kernel", "U-Net input cast"),
+    (r"unet_pack_kernel", "U-Net weight pack"),
     (r"cae_fused_dgrad_kernel", "fused data gradients"),
     (r"wgrad_tr_kernel", "weight gradient (BF16, transpose reads)"),
     (r"wgrad_bf16_kernel", "weight gradient (BF16)"),
