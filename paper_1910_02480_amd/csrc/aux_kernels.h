@@ -140,14 +140,30 @@ static __global__ void fp8_scale_kernel(const unsigned int* amax, float* scale, 
 static __global__ __launch_bounds__(256) void l1_partial_kernel(const float* y, const float* t, long count,
                                                          long per_block, float dscale, float* dy,
                                                          double* partial) {
+    // per_block = 16 elements per thread: four 16-byte loads of y and of t per
+    // thread, all issued before the arithmetic (count is a multiple of 4)
     __shared__ double red[256];
     const long b0 = blockIdx.x * per_block;
-    const long b1 = min(count, b0 + per_block);
     double s = 0.0;
-    for (long e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
-        const float d = y[e] - t[e];
-        s += fabs((double)d);
-        dy[e] = (d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f)) * dscale;
+    float4 yv[4], tv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const long e = b0 + 4 * (threadIdx.x + 256 * k);
+        const bool ok = e < count;
+        yv[k] = ok ? *(const float4*)(y + e) : make_float4(0.f, 0.f, 0.f, 0.f);
+        tv[k] = ok ? *(const float4*)(t + e) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const long e = b0 + 4 * (threadIdx.x + 256 * k);
+        const float d[4] = {yv[k].x - tv[k].x, yv[k].y - tv[k].y, yv[k].z - tv[k].z, yv[k].w - tv[k].w};
+        float g[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            s += fabs((double)d[c]);
+            g[c] = (d[c] > 0.0f ? 1.0f : (d[c] < 0.0f ? -1.0f : 0.0f)) * dscale;
+        }
+        if (e < count) *(float4*)(dy + e) = make_float4(g[0], g[1], g[2], g[3]);
     }
     red[threadIdx.x] = s;
     __syncthreads();

@@ -421,7 +421,7 @@ void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout) {
     *wout = W / dout[l];
 }
 
-static const long kLossPerBlock = 16384;
+
 
 // Column-sum (bias gradient) grid: a multiple of 3 blocks, so that the
 // element stride 256 * VW * blocks is a multiple of every channel count

@@ -101,6 +101,7 @@ ActSizes act_sizes(int prec, int n, int H, int W);
 void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout);
 // Staging tasks (16-byte chunks) per thread of the transpose-read weight
 // gradient, gathered and plain operand: the plan keeps a strip within them.
+constexpr long kLossPerBlock = 4096;  // L1 loss elements per workgroup (16 per thread)
 constexpr int kWgradTG = 9, kWgradTP = 4;   // 4-wave workgroups
 constexpr int kWgradTG8 = 5, kWgradTP8 = 4;  // 8-wave workgroups
 constexpr int kWgradTGRaw = 5;  // float32 gathered operand (4 waves): one pixel per task

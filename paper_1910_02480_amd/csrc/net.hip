@@ -743,9 +743,9 @@ extern "C" drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, floa
     // L1 loss (mean) and dL/dy; dy is stored as sign(y - t) and the 1/M
     // factor is applied once, to the parameter gradients.
     const long M = a.p0 * 3;
-    const int nparts = (int)((M + 16383) / 16384);
+    const int nparts = (int)((M + kLossPerBlock - 1) / kLossPerBlock);
     const long ltok = prof_begin(h, PROF_LOSS, s);
-    hipLaunchKernelGGL(l1_partial_kernel, dim3(nparts), dim3(256), 0, s, (const float*)y, d_target, M, 16384L,
+    hipLaunchKernelGGL(l1_partial_kernel, dim3(nparts), dim3(256), 0, s, (const float*)y, d_target, M, kLossPerBlock,
                        1.0f, dy, (double*)(ws + S.loss_part));
     hipLaunchKernelGGL(l1_final_kernel, dim3(1), dim3(256), 0, s, (const double*)(ws + S.loss_part), nparts, M,
                        d_loss);
