@@ -401,7 +401,11 @@ WgradPlan wgrad_plan(int l, int n, int H, int W, int prec) {
             w.strips_per_map = (w.Hr + w.R - 1) / w.R;
             w.total_strips = n * w.strips_per_map;
             const long per_chunk = 9L * w.qc * w.pc;
-            long chunks = std::max(1L, 1024L / w.bptiles);
+            // about 4 strips per workgroup (the next strip's loads overlap the
+            // current MFMAs, and fewer partial tiles are written), between 256
+            // and 1024 workgroups in all
+            const long lo = std::max(1L, 256L / w.bptiles), hi = std::max(1L, 1024L / w.bptiles);
+            long chunks = std::min(hi, std::max(lo, (long)w.total_strips / 4));
             chunks = std::min(chunks, std::max(1L, (16L << 20) / per_chunk));
             chunks = std::min<long>(chunks, w.total_strips);
             w.strips_per_chunk = (int)((w.total_strips + chunks - 1) / chunks);
