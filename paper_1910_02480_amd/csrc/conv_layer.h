@@ -313,6 +313,31 @@ __device__ __forceinline__ typename Traits<P>::V gather(const ClassGeom& G, int 
     constexpr int SUB = VW < CIN ? VW : CIN;
     constexpr int NSUB = VW / SUB;
     V v = vzero<V>();
+    if constexpr (RAW && NSUB == 1) {
+        // float32 source: no per-lane branch around the loads (a branch makes
+        // the compiler wait for every load in flight). A tap outside the map,
+        // a K position past the last tap, or a pixel past the end reads the
+        // pixel's own (valid) position and is then zeroed.
+        const int t = kk / CIN, c = kk % CIN;
+        int di = 0, dj = 0;
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+            if (t == tt) {
+                di = tap_di<MODE, PHASE>(tt);
+                dj = tap_dj<MODE, PHASE>(tt);
+            }
+        const bool ok = ps.v && t < NT && (di < 0 ? ps.up : (di > 0 ? ps.down : true)) &&
+                        (dj < 0 ? ps.left : (dj > 0 ? ps.right : true));
+        const float* src = (const float*)G.s0.p + ps.off0 + (ok ? di * rowd0 + dj * G.s0.ld : 0);
+        float f[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) f[e] = src[min(c + e, raw_c - 1)];  // stays inside the pixel
+        T tmp[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) tmp[e] = ok && c + e < raw_c ? to_store<P>(f[e], raw_qscale) : T(0);
+        __builtin_memcpy(&v, tmp, sizeof(V));
+        return v;
+    }
     if (!ps.v) return v;
     T tmp[VW];
     if constexpr (NSUB > 1 || RAW) {
