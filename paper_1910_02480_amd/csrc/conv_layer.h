@@ -338,6 +338,30 @@ __device__ __forceinline__ typename Traits<P>::V gather(const ClassGeom& G, int 
         __builtin_memcpy(&v, tmp, sizeof(V));
         return v;
     }
+    if constexpr (!RAW && NSUB == 1) {
+        // one 16-byte (or 32-byte) load per lane, likewise without a branch:
+        // a tap outside the map or past the last tap, or a pixel past the end,
+        // reads the pixel's own position and the value is then zeroed
+        const int t = kk / CIN, c = kk % CIN;
+        int di = 0, dj = 0;
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+            if (t == tt) {
+                di = tap_di<MODE, PHASE>(tt);
+                dj = tap_dj<MODE, PHASE>(tt);
+            }
+        const bool ok = ps.v && t < NT && (di < 0 ? ps.up : (di > 0 ? ps.down : true)) &&
+                        (dj < 0 ? ps.left : (dj > 0 ? ps.right : true));
+        const T* src;
+        if constexpr (C0 >= CIN) {
+            src = (const T*)G.s0.p + ps.off0 + (ok ? di * rowd0 + dj * G.s0.ld : 0) + c;
+        } else {
+            src = (c < C0) ? (const T*)G.s0.p + ps.off0 + (ok ? di * rowd0 + dj * G.s0.ld : 0) + c
+                           : (const T*)G.s1.p + ps.off1 + (ok ? di * rowd1 + dj * G.s1.ld : 0) + (c - C0);
+        }
+        const V val = *(const V*)src;
+        return ok ? val : v;
+    }
     if (!ps.v) return v;
     T tmp[VW];
     if constexpr (NSUB > 1 || RAW) {
