@@ -28,7 +28,7 @@ struct GemmCfg {
                                                          : (4 * CIN + KS - 1) / KS * KS;
     static constexpr int WROWS = MODE == M_CONV ? RUP : (MODE == M_TCONV_PAIRS ? 9 * RUP : MROWS);
     static constexpr int LDS = WROWS * wlds_row_bytes(KSTRIDE, ES);
-    static constexpr bool WLDS = LDS <= 80 * 1024;
+    static constexpr bool WLDS = LDS <= 160 * 1024;
     // weights read from L2: split the row blocks over up to 4 waves for reuse
     static constexpr int RB = MODE == M_TCONV_MERGED ? MROWS / 16 : RUP / 16;
     static constexpr int WM = (WLDS || MODE == M_TCONV_MERGED) ? 1 : (RB % 4 == 0 ? 4 : (RB % 2 == 0 ? 2 : 1));

@@ -30,12 +30,12 @@ using namespace drc;
 // ------------------------------------------------------------------ tile shapes
 // MFMA accumulator blocks (16 rows) a wave holds per 16-pixel block.
 // Mirrors GemmCfg: row blocks are split over WM waves when the weight pack
-// does not fit the 80 KB LDS budget.
+// does not fit the 160 KB LDS budget (one workgroup per CU above 80 KB).
 static int acc_blocks(int prec, int layer, bool backward) {
     const GemmGeom g = gemm_geom(layer, backward, prec);
     const int rb = g.rows_pad / 16;
     const long lds = (long)g.nblk * g.rows_pad * (g.kstride * prec_esize(prec) + 16);
-    const int wm = (lds <= 80 * 1024 || g.mode == M_TCONV_MERGED) ? 1 : (rb % 4 == 0 ? 4 : (rb % 2 == 0 ? 2 : 1));
+    const int wm = (lds <= 160 * 1024 || g.mode == M_TCONV_MERGED) ? 1 : (rb % 4 == 0 ? 4 : (rb % 2 == 0 ? 2 : 1));
     return (g.mode == M_TCONV_PAIRS ? 4 * rb : rb) / wm;
 }
 
