@@ -74,14 +74,27 @@ def label(name: str) -> str | None:
     return None
 
 
-def source_hash() -> str:
-    """Hash of the HIP sources and the public header the library is built from."""
+# The HIP sources each labelled kernel is built from: a change to any of
+# them makes that kernel's stored counters stale. Other labels depend on
+# every source.
+_KERNEL_SOURCES = {
+    "forward fused": ("fused_fwd.hip", "common.h", "conv_layer.h", "internal.h"),
+    "envmap build": ("envmap.hip", "internal.h"),
+    "envmap sample": ("envmap.hip", "internal.h"),
+    "envmap pdf": ("envmap.hip", "internal.h"),
+    "interp weights": ("interp.hip", "internal.h"),
+}
+
+
+def source_hash(lab: str | None = None) -> str:
+    """Hash of the HIP sources and the public header a kernel (label) or the
+    whole library (None) is built from."""
     h = hashlib.sha256()
-    files = []
     csrc = os.path.join(_HERE, "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            files.append(os.path.join(csrc, f))
+    names = _KERNEL_SOURCES.get(lab) if lab else None
+    if names is None:
+        names = [f for f in sorted(os.listdir(csrc)) if f.endswith((".hip", ".h"))]
+    files = [os.path.join(csrc, f) for f in sorted(names)]
     files.append(os.path.join(_HERE, "..", "include", "drc_cae.h"))
     for p in files:
         h.update(os.path.basename(p).encode())
@@ -140,7 +153,7 @@ def traffic(fetch_csv: str, write_csv: str, cmd_fetch: str, cmd_write: str, titl
         fk, nf = f[key]
         wk, nw = w[key]
         d = {"name": name, "fetch_kib": fk, "write_kib": wk, "dispatches": min(nf, nw),
-             "bytes_per_launch": fk * 1024.0 * kf + wk * 1024.0 * kw}
+             "bytes_per_launch": fk * 1024.0 * kf + wk * 1024.0 * kw, "source_hash": source_hash(lab)}
         rows.append((lab, d))
         # a label's figure: its most dispatched instantiation (the one the timed loop runs)
         if lab not in kernels or d["dispatches"] > kernels[lab]["dispatches"]:
@@ -163,7 +176,8 @@ def traffic(fetch_csv: str, write_csv: str, cmd_fetch: str, cmd_write: str, titl
 
 
 def read_traffic(md_path: str):
-    """The json block of a traffic summary, or None when absent or stale."""
+    """The json block of a traffic summary without its stale kernels, or None
+    when absent or when every kernel is stale."""
     try:
         text = open(md_path).read()
     except OSError:
@@ -172,7 +186,10 @@ def read_traffic(md_path: str):
     if not m:
         return None
     doc = json.loads(m.group(1))
-    return doc if doc.get("source_hash") == source_hash() else None
+    # keep the kernels whose sources are unchanged since the counters were taken
+    doc["kernels"] = {lab: d for lab, d in doc.get("kernels", {}).items()
+                      if d.get("source_hash", doc.get("source_hash")) == source_hash(lab)}
+    return doc if doc["kernels"] else None
 
 
 def main():
