@@ -717,11 +717,10 @@ __global__ __launch_bounds__(64 * NW) void wgrad_tr_kernel(WgradTArgs a) {
     // to the pixel (2 ul, 2 v) of the staged strip (its 4 rows are channels
     // c .. c + 3 of tap t), whether kw == 0, and whether the rows exist
     int aoff[JBW];
-    bool av[JBW], alane[JBW], akw0[JBW];
+    bool alane[JBW], akw0[JBW];
 #pragma unroll
     for (int i = 0; i < JBW; ++i) {
         const int rb = wave + NW * i;
-        av[i] = rb * 16 < J;
         const int row = rb * 16 + 4 * qq;
         alane[i] = row < J;
         const int t = alane[i] ? row / QC : 0, c = alane[i] ? row % QC : 0;
@@ -827,18 +826,23 @@ __global__ __launch_bounds__(64 * NW) void wgrad_tr_kernel(WgradTArgs a) {
             }
             const uint16_t* gb = Gs + (2 * ul * Wq + 2 * (v0 + jq)) * GS;
             const bool left = v0 + jq == 0;  // column -1 for kw == 0
+            // every owned row block's fragment is read before the first MFMA so
+            // that the LDS latencies overlap; blocks past the last (tap,
+            // channel) row read the zero block and their sums are never stored
+            uint4 afr[JBW];
 #pragma unroll
             for (int i = 0; i < JBW; ++i) {
-                if (!av[i]) continue;
                 const uint2 lo = lds_read_tr16(!alane[i] || (left && akw0[i]) ? zero + 4 * qq : gb + aoff[i]);
                 const uint2 hi = lds_read_tr16(alane[i] ? gb + aoff[i] + 8 * GS : zero + 4 * qq);
-                const uint4 afr = make_uint4(lo.x, lo.y, hi.x, hi.y);
+                afr[i] = make_uint4(lo.x, lo.y, hi.x, hi.y);
+            }
+#pragma unroll
+            for (int i = 0; i < JBW; ++i)
 #pragma unroll
                 for (int b = 0; b < PB; ++b)
-                    acc[i][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, afr),
+                    acc[i][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, afr[i]),
                                                                       __builtin_bit_cast(bf16x8, bfr[b]), acc[i][b],
                                                                       0, 0, 0);
-            }
         }
     }
     // ---- partial tile: lane holds rows 4*g + r of row block (wave + NW i), column r16 of block b

@@ -304,6 +304,9 @@ extern "C" drc_status drc_cae_saved_size(const drc_cae* h, int n, int H, int W, 
 
 // Weight-gradient work split for layer l (see wgrad_kernel): MFMA tile
 // blocks, reduction pixels per workgroup and number of reduction chunks.
+// Weight-gradient workgroups in one wave of the chip (one per CU).
+constexpr int kWgradWave = 256;
+
 WgradPlan wgrad_plan(int l, int n, int H, int W, int prec) {
     const LayerDef& L = kLayers[l];
     int hin, win, hout, wout;
@@ -407,6 +410,10 @@ WgradPlan wgrad_plan(int l, int n, int H, int W, int prec) {
             const long lo = std::max(1L, 256L / w.bptiles), hi = std::max(1L, 1024L / w.bptiles);
             long chunks = std::min(hi, std::max(lo, (long)w.total_strips / 4));
             chunks = std::min(chunks, std::max(1L, (16L << 20) / per_chunk));
+            // whole waves of 256 workgroups: the large tiles run one workgroup
+            // per CU, and a partial last wave would leave CUs idle
+            if (chunks * w.bptiles > kWgradWave)
+                chunks = std::max(lo, chunks * w.bptiles / kWgradWave * kWgradWave / w.bptiles);
             chunks = std::min<long>(chunks, w.total_strips);
             w.strips_per_chunk = (int)((w.total_strips + chunks - 1) / chunks);
             w.bchunks = (w.total_strips + w.strips_per_chunk - 1) / w.strips_per_chunk;
