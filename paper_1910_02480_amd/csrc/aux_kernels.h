@@ -694,8 +694,11 @@ __device__ __forceinline__ uint2 lds_read_tr16(const uint16_t* p) {
 
 // QC: staged gathered channels (a multiple of 4; 16-row MFMA blocks of
 // (tap, channel) rows may span several taps); QR > 0: the gathered operand
-// is float32 with QR <= QC channels, rounded to bf16 (RNE) when staged and
-// zero-padded to QC, one pixel per staging task.
+// is float32 with QR <= QC channels and dense pixels (qld == QR, rows of
+// whole 16-byte chunks), rounded to bf16 (RNE) when staged and zero-padded
+// to QC; it is staged as 16-byte chunks of the strip's rows (TG per
+// thread), so every load is a full 16-byte one rather than QR scattered
+// 4-byte loads per pixel.
 template <int NW, int JBW, int PB, int QC, int TG, int TP, int QR>
 __global__ __launch_bounds__(64 * NW) void wgrad_tr_kernel(WgradTArgs a) {
     constexpr int NT = 64 * NW;
@@ -712,6 +715,11 @@ __global__ __launch_bounds__(64 * NW) void wgrad_tr_kernel(WgradTArgs a) {
     uint16_t* zero = Ps + R * Wr * PS;
     const int cp0 = blockIdx.y * PB * 16;
     if (threadIdx.x < 2) *(uint4*)(zero + 8 * threadIdx.x) = make_uint4(0, 0, 0, 0);
+    if constexpr (QR > 0) {
+        // the staging writes channels [0, QR) only: the pad channels stay zero
+        for (int i = threadIdx.x; i < (2 * R + 1) * Wq * GS / 8; i += NT)
+            *(uint4*)(Gs + 8 * i) = make_uint4(0, 0, 0, 0);
+    }
 
     // per owned row block: LDS offset of this lane's gathered address relative
     // to the pixel (2 ul, 2 v) of the staged strip (its 4 rows are channels
@@ -736,30 +744,40 @@ __global__ __launch_bounds__(64 * NW) void wgrad_tr_kernel(WgradTArgs a) {
 
     // Staging of a strip: gathered rows 2 u0 - 1 .. 2 u0 + 2 R - 1 (all
     // columns) and plain rows u0 .. u0 + R - 1 (channels [cp0, cp0 + 16 PB)),
-    // 8 channels per task, at most TG and TP tasks per thread. The next
-    // strip's loads are issued before this strip's MFMAs and land in
-    // registers; they are written to LDS after the MFMAs.
-    constexpr int CGQ = QR ? 1 : QC / 8, CGP = PB * 2;
-    constexpr int QV = QR ? QR : 1;  // float32 values per task held in registers
-    const int ntq = (2 * R + 1) * Wq * CGQ, ntp = K * CGP;
-    uint4 vq[TG], vp[TP];
-    float vr[TG][QV];
+    // 8 channels (float32: one 16-byte chunk) per task, at most TG and TP
+    // tasks per thread. The next strip's loads are issued before this
+    // strip's MFMAs and land in registers; they are written to LDS after the
+    // MFMAs.
+    constexpr int CGQ = QC / 8, CGP = PB * 2;
+    const int ntq = QR ? (2 * R + 1) * Wq * QR / 4 : (2 * R + 1) * Wq * CGQ, ntp = K * CGP;
+    const int rowf = Wq * QR;  // float32: floats per gathered row
+    uint4 vq[QR ? 1 : TG], vp[TP];
+    float4 vf[QR ? TG : 1];
     auto load_strip = [&](int s) {
         const int n = s / a.strips_per_map;
         const int u0 = (s - n * a.strips_per_map) * R;
         const long base = ((long)n * a.Hq + 2 * u0 - 1) * Wq * a.qld;
+        if constexpr (QR > 0) {
+            // every lane loads (rows outside the map read the operand's first
+            // chunk and are zeroed): a load under a per-lane condition would
+            // make the compiler wait for all loads in flight
 #pragma unroll
-        for (int t = 0; t < TG; ++t) {
-            const int e = threadIdx.x + NT * t;
-            const int cg = e % CGQ, pix = e / CGQ;
-            const int row = pix / Wq;
-            const int qi = 2 * u0 - 1 + row;
-            const bool ok = e < ntq && (unsigned)qi < (unsigned)a.Hq;
-            const long off = base + ((long)row * Wq + (pix - row * Wq)) * a.qld;
-            if constexpr (QR > 0) {
+            for (int t = 0; t < TG; ++t) {
+                const int e = threadIdx.x + NT * t;
+                const int qi = 2 * u0 - 1 + (4 * e) / rowf;
+                const bool ok = e < ntq && (unsigned)qi < (unsigned)a.Hq;
+                const float4 v = *(const float4*)((const float*)a.q + (ok ? base + 4L * e : 0L));
+                vf[t] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        } else {
 #pragma unroll
-                for (int c = 0; c < QR; ++c) vr[t][c] = ok ? ((const float*)a.q)[off + c] : 0.0f;
-            } else {
+            for (int t = 0; t < TG; ++t) {
+                const int e = threadIdx.x + NT * t;
+                const int cg = e % CGQ, pix = e / CGQ;
+                const int row = pix / Wq;
+                const int qi = 2 * u0 - 1 + row;
+                const bool ok = e < ntq && (unsigned)qi < (unsigned)a.Hq;
+                const long off = base + ((long)row * Wq + (pix - row * Wq)) * a.qld;
                 vq[t] = make_uint4(0, 0, 0, 0);
                 if (ok) vq[t] = *(const uint4*)((const uint16_t*)a.q + off + cg * 8);
             }
@@ -782,19 +800,17 @@ __global__ __launch_bounds__(64 * NW) void wgrad_tr_kernel(WgradTArgs a) {
 #pragma unroll
         for (int t = 0; t < TG; ++t) {
             const int e = threadIdx.x + NT * t;
+            if (e >= ntq) continue;
             if constexpr (QR > 0) {
-                uint16_t h[QC];
+                // float j of chunk e is channel (4 e + j) % QR of staged pixel (4 e + j) / QR
+                const float f[4] = {vf[t].x, vf[t].y, vf[t].z, vf[t].w};
 #pragma unroll
-                for (int c = 0; c < QC; ++c) h[c] = c < QR ? f32_to_bf16(vr[t][c]) : 0;
-                uint32_t w[QC / 2];
-#pragma unroll
-                for (int c = 0; c < QC / 2; ++c) w[c] = (uint32_t)h[2 * c] | ((uint32_t)h[2 * c + 1] << 16);
-                if (e < ntq) {
-                    if constexpr (QC == 8) *(uint4*)(Gs + e * GS) = make_uint4(w[0], w[1], w[2], w[3]);
-                    else *(uint2*)(Gs + e * GS) = make_uint2(w[0], w[1]);
+                for (int j = 0; j < 4; ++j) {
+                    const int k = 4 * e + j, pix = k / QR;
+                    Gs[pix * GS + (k - pix * QR)] = f32_to_bf16(f[j]);
                 }
             } else {
-                if (e < ntq) *(uint4*)(Gs + (e / CGQ) * GS + (e % CGQ) * 8) = vq[t];
+                *(uint4*)(Gs + (e / CGQ) * GS + (e % CGQ) * 8) = vq[t];
             }
         }
 #pragma unroll

@@ -365,14 +365,15 @@ WgradPlan wgrad_plan(int l, int n, int H, int W, int prec) {
             tqc = l == 0 ? 8 : 4;
             tjbw = ((9 * tqc + 15) / 16 + 3) / 4;
             tpb = w.pc >= 64 ? 4 : 2;
-            ttg = kWgradTGRaw; ttp = kWgradTP;
+            ttg = l == 0 ? kWgradTGRaw7 : kWgradTGRaw3; ttp = kWgradTP;
         }
         for (int R = w.Hr; R >= 1 && tqc; R /= 2) {
             if ((R * w.Wr) % 32) continue;
             const int GS = tqc + 8, PS = tpb * 16 + 8;
             const int lds = ((2 * R + 1) * 2 * w.Wr * GS + R * w.Wr * PS + 16) * 2;
             if (lds > (tnw == 8 ? 96 : 64) * 1024) continue;
-            const int gtasks = (2 * R + 1) * 2 * w.Wr * (raw ? 1 : tqc / 8);
+            // staging tasks: 16-byte chunks of the gathered rows (float32: dense rows)
+            const int gtasks = raw ? (2 * R + 1) * 2 * w.Wr * w.qc / 4 : (2 * R + 1) * 2 * w.Wr * (tqc / 8);
             if (gtasks > 64 * tnw * ttg) continue;  // staging tasks per thread
             if (R * w.Wr * 2 * tpb > 64 * tnw * ttp) continue;
             w.bf16 = 1;

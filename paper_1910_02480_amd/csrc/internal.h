@@ -104,7 +104,7 @@ void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout);
 constexpr long kLossPerBlock = 4096;  // L1 loss elements per workgroup (16 per thread)
 constexpr int kWgradTG = 9, kWgradTP = 4;   // 4-wave workgroups
 constexpr int kWgradTG8 = 5, kWgradTP8 = 4;  // 8-wave workgroups
-constexpr int kWgradTGRaw = 5;  // float32 gathered operand (4 waves): one pixel per task
+constexpr int kWgradTGRaw7 = 8, kWgradTGRaw3 = 2;  // float32 gathered operand of E1 / D1 (4 waves): 16-byte chunks
 struct WgradPlan {
     int qc, pc, Hr, Wr, JB, PB, VEC, jtiles, ptiles, nchunks;
     long per_block;

@@ -351,6 +351,11 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
         if (b.Wq != 2 * b.Wr || b.Hq != 2 * b.Hr)
             return drc_fail(DRC_ERR_STATE, "weight_grad: transpose-read plan does not fit layer %d", l);
         const dim3 block(64 * wp.NW);
+        // float32 gathered operand: staged as whole 16-byte chunks of dense
+        // rows (x and dy are dense and 16-byte aligned at the boundary)
+        if (raw && (b.qld != wp.QR || (uintptr_t)b.q % 16 != 0 || (b.Wq * wp.QR) % 4 != 0 ||
+                    (2L * wp.R + 1) * b.Wq * wp.QR / 4 > 64L * wp.NW * (wp.QR == 7 ? kWgradTGRaw7 : kWgradTGRaw3)))
+            return drc_fail(DRC_ERR_STATE, "weight_grad: float32 operand of layer %d is not staged densely", l);
         if (kind == 43254 && !raw)
             hipLaunchKernelGGL((wgrad_tr_kernel<4, 5, 4, 32, kWgradTG, kWgradTP, 0>), grid, block, wp.lds, s, b);
         else if (kind == 83238 && !raw)
@@ -358,9 +363,9 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
         else if (kind == 46494 && !raw)
             hipLaunchKernelGGL((wgrad_tr_kernel<4, 9, 4, 64, kWgradTG, kWgradTP, 0>), grid, block, wp.lds, s, b);
         else if (kind == 40822 && wp.QR == 7)
-            hipLaunchKernelGGL((wgrad_tr_kernel<4, 2, 2, 8, kWgradTGRaw, kWgradTP, 7>), grid, block, wp.lds, s, b);
+            hipLaunchKernelGGL((wgrad_tr_kernel<4, 2, 2, 8, kWgradTGRaw7, kWgradTP, 7>), grid, block, wp.lds, s, b);
         else if (kind == 40414 && wp.QR == 3)
-            hipLaunchKernelGGL((wgrad_tr_kernel<4, 1, 4, 4, kWgradTGRaw, kWgradTP, 3>), grid, block, wp.lds, s, b);
+            hipLaunchKernelGGL((wgrad_tr_kernel<4, 1, 4, 4, kWgradTGRaw3, kWgradTP, 3>), grid, block, wp.lds, s, b);
         else
             return drc_fail(DRC_ERR_STATE, "weight_grad: no transpose-read kernel for layer %d", l);
         const long count = 9L * wp.qc * wp.pc;
