@@ -137,6 +137,7 @@ struct FwdClass {
     int n, H, W;
     int tile_px[6];
     int npw[6];
+    int x_al16;  // every map of x starts on a 16-byte boundary
 };
 
 drc_status forward_dispatch(drc_cae* h, const FwdBufs& b, int n, int H, int W, int l0, int l1,

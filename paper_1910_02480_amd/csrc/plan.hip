@@ -99,6 +99,7 @@ struct PlanClass {
     long flops;              // forward work of the class (for picking shared tile shapes)
     std::vector<long> xoff;  // element offsets of each map's input / output
     std::vector<long> yoff;
+    bool x_al16 = true;                 // every xoff is a multiple of 4 floats
     size_t dev_xoff = 0, dev_yoff = 0;  // byte offsets into the plan's device table
     size_t act[5];           // byte offsets of h1..u2 inside the workspace
     int npw[6], tile_px[6];
@@ -143,6 +144,7 @@ extern "C" drc_status drc_cae_plan_create(drc_cae* h, const drc_map_desc* maps, 
         PlanClass& c = cls[idx[key]];
         c.n++;
         c.xoff.push_back((long)d.x_off);
+        c.x_al16 = c.x_al16 && d.x_off % 4 == 0;
         c.yoff.push_back((long)d.y_off);
     }
     std::sort(cls.begin(), cls.end(), [](const PlanClass& a, const PlanClass& b) {
@@ -238,6 +240,7 @@ static drc_status plan_enqueue(drc_plan* p, const float* x, float* y, char* ws, 
         f.n = pc.n;
         f.H = pc.H;
         f.W = pc.W;
+        f.x_al16 = pc.x_al16 && (uintptr_t)x % 16 == 0;
         for (int l = 0; l < 6; ++l) f.tile_px[l] = pc.tile_px[l];
         fc.push_back(f);
         from.push_back((int)c);
@@ -333,6 +336,7 @@ extern "C" drc_status drc_cae_autotune(drc_cae* h, int n, int H, int W, const fl
     fc.n = n;
     fc.H = H;
     fc.W = W;
+    fc.x_al16 = 1;  // d_x is 16-byte aligned and packed
     auto run = [&](int l0, int l1) -> drc_status {
         if (h->prec == P_F32) return forward_classes<P_F32>(h, h->wf, &fc, 1, l0, l1, s);
         if (h->prec == P_BF16) return forward_classes<P_BF16>(h, h->wf, &fc, 1, l0, l1, s);

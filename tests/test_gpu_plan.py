@@ -133,3 +133,39 @@ def test_autotune_keeps_results_bitwise(tmp_path, params):
         np.testing.assert_array_equal(yd.cpu().numpy(), y0.reshape(-1))
     finally:
         B.drc_cae_plan_destroy(plan)
+
+
+def test_layer_e1_staged_matches_gather(params):
+    """BF16 E1 of the layer path stages the float32 input rows in LDS when
+    every map starts on a 16-byte boundary and gathers it per lane
+    otherwise; both give bitwise-equal outputs (same operands, K order and
+    rounding). Frames with the maps packed, and with every map shifted by a
+    few floats, are compared map by map (32x32, 64x64, 128x128 through the
+    layer kernels, and a size the staged kernel does not take)."""
+    from paper_1910_02480_amd.cae import CAE
+    sizes = [(128, 128), (32, 32), (64, 64), (128, 128), (40, 40), (32, 32)]
+    x, xo, yo, ny = _frame(sizes)
+    shift = np.array([1 + m % 3 for m in range(len(sizes))])           # 1..3 floats: not 16-byte aligned
+    xo_u = xo + np.cumsum(shift)
+    xu = np.zeros(len(x) + int(shift.sum()), dtype=np.float32)
+    for m, (h, w) in enumerate(sizes):
+        xu[xo_u[m]:xo_u[m] + h * w * 7] = x[xo[m]:xo[m] + h * w * 7]
+    cae = CAE("bf16", torch.from_numpy(params).to(DEV), device=DEV)
+    cae.set_fused(False)
+    ys = []
+    for xx, offs in ((x, xo), (xu, xo_u)):
+        maps = [(h, w, int(offs[m]), int(yo[m])) for m, (h, w) in enumerate(sizes)]
+        plan = B.drc_cae_plan_create(cae.h, maps)
+        try:
+            ws = torch.empty(B.drc_cae_plan_workspace_size(plan) + 256, dtype=torch.uint8, device=DEV)
+            ws = ws[(-ws.data_ptr()) % 256:]
+            yd = torch.full((ny,), float("nan"), device=DEV)
+            B.drc_cae_plan_launch(plan, torch.from_numpy(xx).to(DEV), yd, ws, stream=0)
+            torch.cuda.synchronize()
+            ys.append(yd.cpu().numpy())
+        finally:
+            B.drc_cae_plan_destroy(plan)
+    assert np.all(np.isfinite(ys[0]))
+    for m, (h, w) in enumerate(sizes):
+        np.testing.assert_array_equal(ys[0][yo[m]:yo[m] + h * w * 3], ys[1][yo[m]:yo[m] + h * w * 3],
+                                      err_msg=f"map {m} ({h}x{w})")
