@@ -59,10 +59,12 @@ drc_status run_gemm(int layer, bool bwd, LayerArgs& a, int npw, int num_cu, hipS
 extern template drc_status run_gemm<P_F32>(int, bool, LayerArgs&, int, int, hipStream_t);
 extern template drc_status run_gemm<P_BF16>(int, bool, LayerArgs&, int, int, hipStream_t);
 extern template drc_status run_gemm<P_FP8>(int, bool, LayerArgs&, int, int, hipStream_t);
-// BF16 E1 with the float32 input staged in LDS by bands of output rows (e1_band.hip)
+// BF16 E1 and D1 with their inputs staged in LDS by bands of rows (layer_bands.hip)
 namespace drc {
 bool e1_band_fits(int Hin, int Win);
 drc_status e1_band_forward(const LayerArgs& a, int num_cu, hipStream_t s);
+bool d1_band_fits(int Hin, int Win);
+drc_status d1_band_forward(const LayerArgs& a, int num_cu, hipStream_t s);
 }  // namespace drc
 
 static Seg seg_none() {
@@ -197,7 +199,7 @@ drc_status forward_classes(drc_cae* h, void* const* packs, const FwdClass* fc, i
         }
         a.nclass = nclass;
         int npw = 0;
-        bool band = P == P_BF16 && l == 0;
+        bool band = P == P_BF16 && (l == 0 || l == 5);
         for (int c = 0; c < nclass; ++c) {
             a.cls[c] = class_geom(l, fc[c].n, fc[c].H, fc[c].W, false);
             fwd_tensors(l, fc[c].b, h->desc.final_relu, qout, a.cls[c]);
@@ -206,11 +208,12 @@ drc_status forward_classes(drc_cae* h, void* const* packs, const FwdClass* fc, i
                 auto it = h->tile_px.find({l, fc[c].H});
                 if (it != h->tile_px.end()) a.cls[c].tile_px = it->second;
             }
-            band = band && fc[c].x_al16 && e1_band_fits(fc[c].H, fc[c].W);
+            band = band && (l == 0 ? fc[c].x_al16 && e1_band_fits(fc[c].H, fc[c].W)
+                                   : d1_band_fits(fc[c].H / 2, fc[c].W / 2));
         }
         if (band) {
             const long tok = prof_begin(h, PROF_FWD + l, s);
-            TRY(e1_band_forward(a, h->num_cu, s));
+            TRY(l == 0 ? e1_band_forward(a, h->num_cu, s) : d1_band_forward(a, h->num_cu, s));
             prof_end(h, tok, s);
             continue;
         }

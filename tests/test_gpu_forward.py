@@ -119,14 +119,18 @@ def _half_ulp_bf16(v):
     return np.where(a > 0, 2.0 ** (e - 8), 0.0)
 
 
-def test_layers_bf16_round_to_nearest_even(oracle, params, params_dev):
+@pytest.mark.parametrize("n,H,fused", [(4, 32, True), (4, 32, False), (2, 64, False), (1, 128, False)])
+def test_layers_bf16_round_to_nearest_even(oracle, params, params_dev, n, H, fused):
     """Each stored BF16 activation is the RNE rounding of the exact layer
     output on the GPU's own BF16 inputs (allowing for the FP32 accumulation
-    near a rounding tie)."""
-    x = synth.radiance_maps(4, 32, 32)
+    near a rounding tie): the whole-network kernel, and the layer kernels
+    (whose E1 and D1 stage their inputs by bands of rows) at 32x32, 64x64
+    and 128x128."""
+    x = synth.radiance_maps(n, H, H, seed=11)
     cae = _cae("bf16", params_dev)
+    cae.set_fused(fused)
     y, saved, off = _run(cae, x, want_saved=True)
-    acts = saved_acts(saved, off, 4, 32, 32, "bf16")
+    acts = saved_acts(saved, off, n, H, H, "bf16")
     refs = _layer_refs(oracle, params, x, acts, "bf16")
     for name in ("h1", "h2", "h3", "u3", "u2"):
         g, r = acts[name], refs[name]
