@@ -653,7 +653,8 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
 // the skip-gradient sums applied in the epilogues. Every output gradient the
 // weight gradients need (dz_u2, dz_u3, dz_h3, dz_h2, dz_h1) and the skip
 // gradient dh1s go to HBM; the chain's inputs stay in LDS:
-//   RA [0, 16HW): dy as BF16 (8 channels), then dz_u3 [0, 8HW) and dh2s [8HW, 16HW)
+//   RA [0, 16HW): dy as BF16 (8 channels), then dz_u3 [0, 8HW) and dh2s [8HW, 16HW),
+//     then dh1s (staged from HBM for E2^T's epilogue)
 //   RB [16HW, 32HW): dz_u2, then dz_h3 [16HW, 20HW) and dz_h2 [20HW, 28HW)
 //   zeros at 32HW.
 // K order, rounding and epilogue order (add, then mask) are the layer
@@ -844,8 +845,10 @@ __global__ __launch_bounds__(FT) void cae_fused_dgrad_kernel(const DgradArgs a) 
             pairs_phase<H / 8, W / 8, 128, 0, 64, 1, P5N>(smem, RB, RB, ZO, a.w[2], nullptr, e);
         }
         __syncthreads();
-        {   // E2^T: dz_h2 -> dz_h1 = (. + dh1s) masked by h1
-            GradOut<32, 0, W / 2> e{smem, GSeg{-1, a.dz_h1 + m * S1, a.h1 + m * S1, a.dh1s + m * S1, -1}, kNoSeg,
+        {   // E2^T: dz_h2 -> dz_h1 = (. + dh1s) masked by h1; dh1s is staged in RA first
+            copy_in<32, H / 2, W / 2>(smem, RA, (const char*)(a.dh1s + m * S1));
+            __syncthreads();
+            GradOut<32, 0, W / 2> e{smem, GSeg{-1, a.dz_h1 + m * S1, a.h1 + m * S1, nullptr, RA}, kNoSeg,
                                     bs_h1};
             pairs_phase<H / 4, W / 4, 64, 0, 32, 1, P6N>(smem, RB + 4 * HW, RB + 4 * HW, ZO, a.w[1], nullptr, e);
         }

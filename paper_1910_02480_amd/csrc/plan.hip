@@ -306,6 +306,11 @@ extern "C" drc_status drc_cae_plan_launch(drc_plan* p, const float* d_x, float* 
     return DRC_OK;
 }
 
+namespace drc {
+bool e1_band_fits(int Hin, int Win);
+bool d1_band_fits(int Hin, int Win);
+}  // namespace drc
+
 // ------------------------------------------------------------------ autotuner
 extern "C" drc_status drc_cae_autotune(drc_cae* h, int n, int H, int W, const float* d_x, void* d_ws,
                                        size_t ws_bytes, const char* tune_cache, void* stream) {
@@ -354,9 +359,14 @@ extern "C" drc_status drc_cae_autotune(drc_cae* h, int n, int H, int W, const fl
     for (int l = 0; l < 6 && st == DRC_OK; ++l) {
         TuneEntry best;
         best.us = 1e30;
+        // BF16 E1 / D1 in band-staged kernels: the GEMM tile is not a choice (one timing)
+        const bool banded = h->prec == P_BF16 && ((l == 0 && e1_band_fits(H, W)) || (l == 5 && d1_band_fits(H / 2, W / 2)));
+        bool timed = false;
         for (int npw : {1, 2, 4, 8}) {
             if (!npw_supported(h->prec, l, false, npw)) continue;
             for (int mult : {1, 2, 4, 8}) {
+                if (banded && timed) continue;
+                timed = true;
                 fc.npw[l] = npw;
                 fc.tile_px[l] = 64 * npw * mult;
                 for (int r = 0; r < 2 && st == DRC_OK; ++r) st = run(l, l);  // warm-up
