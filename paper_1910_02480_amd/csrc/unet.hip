@@ -221,6 +221,141 @@ __global__ __launch_bounds__(256) void unet_conv_kernel(ConvArgsU a) {
     }
 }
 
+// Operands of K step ks for unet_conv_lds_kernel: ACH weight chunks (16 bytes
+// of fragment (rb0 + e / 64, ks), lane e % 64) and BCH activation chunks
+// (pixel e / 4, channels 8 (e % 4) .. + 8 of the step's tap); taps outside
+// the map are zero.
+template <int ACH, int BCH>
+__device__ __forceinline__ void unet_lds_load(const ConvArgsU& a, int ks, int rb0, const long (&bbase)[BCH],
+                                              const int (&by)[BCH], const int (&bx)[BCH], const bool (&bok)[BCH],
+                                              uint4 (&ra)[ACH], uint4 (&rb)[BCH]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < ACH; ++j) {
+        const int e = tid + 256 * j;
+        ra[j] = a.pack[((long)(rb0 + (e >> 6)) * a.ks + ks) * 64 + (e & 63)];
+    }
+    const int t = (32 * ks) / a.cinp, c = 32 * ks - t * a.cinp;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+#pragma unroll
+    for (int j = 0; j < BCH; ++j) {
+        // one unconditional load per lane (a selected offset, the value zeroed
+        // after): a load behind a selected pointer becomes two guarded loads
+        const int yy = by[j] + dy, xx = bx[j] + dx;
+        const bool ok = bok[j] && (unsigned)yy < (unsigned)a.H && (unsigned)xx < (unsigned)a.W;
+        const long off = ok ? bbase[j] + ((long)dy * a.W + dx) * a.cinp + c : 0;
+        const uint4 v = *(const uint4*)(a.in + off);
+        rb[j] = ok ? v : make_uint4(0, 0, 0, 0);
+    }
+}
+
+// Writes the staged operands to LDS buffer st: A fragments first (1 KB
+// each, as packed), then B fragments (pixel block q / 16, lane 16 kc + q % 16).
+template <int ACH, int BCH, int AF>
+__device__ __forceinline__ void unet_lds_store(char* st, const uint4 (&ra)[ACH], const uint4 (&rb)[BCH]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < ACH; ++j) *(uint4*)(st + (tid + 256 * j) * 16) = ra[j];
+#pragma unroll
+    for (int j = 0; j < BCH; ++j) {
+        const int e = tid + 256 * j, q = e >> 2, kc = e & 3;
+        *(uint4*)(st + AF * 1024 + (q >> 4) * 1024 + (16 * kc + (q & 15)) * 16) = rb[j];
+    }
+}
+
+// LDS-tiled variant for the 3x3 layers with cinp a multiple of 32 (all but
+// the first): a workgroup computes BM output channels x BN pixels with 4
+// waves of 64 x 64 (BM = 128: 2 x 2 waves, BN = 128; BM = 64: 1 x 4 waves,
+// BN = 256). Per K step the workgroup stages the BM rows' weight fragments
+// (1 KB each, as packed) and the BN pixels' 32 channels of the step's tap
+// (16-byte gathers, in MFMA fragment order) in LDS once, so each fragment
+// crosses the L1 once per workgroup instead of once per wave; the next
+// step's operands are loaded into registers during the current step's
+// MFMAs (double-buffered LDS, one barrier per step). Operands, K order and
+// epilogue are those of unet_conv_kernel, so the outputs are bitwise equal.
+template <int BM>
+__global__ __launch_bounds__(256) void unet_conv_lds_kernel(ConvArgsU a) {
+    constexpr int WR = BM / 64, WP = 4 / WR;  // waves along rows / pixels
+    constexpr int BN = WP * 64;               // pixels per workgroup
+    constexpr int AF = BM / 16, BF = BN / 16; // A / B fragments per K step
+    constexpr int ACH = AF * 64 / 256, BCH = BF * 64 / 256;  // 16-byte chunks per thread
+    constexpr int STAGE = (AF + BF) * 1024;   // bytes of one buffer
+    static_assert(ACH >= 1 && BCH >= 1, "every thread stages whole chunks");
+    extern __shared__ __align__(16) char smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int wr = wave / WP, wp = wave % WP;
+    const long npix = (long)a.n * a.H * a.W;
+    const long px0 = (long)blockIdx.x * BN;
+    const int rb0 = blockIdx.y * AF;
+
+    long bbase[BCH];
+    int by[BCH], bx[BCH];
+    bool bok[BCH];
+#pragma unroll
+    for (int j = 0; j < BCH; ++j) {
+        const int e = tid + 256 * j;  // (pixel, chunk) index of the tile
+        const long p = px0 + (e >> 2);
+        bok[j] = p < npix;
+        const long pp = bok[j] ? p : 0;
+        bx[j] = (int)(pp % a.W);
+        by[j] = (int)((pp / a.W) % a.H);
+        bbase[j] = pp * a.cinp + 8 * (e & 3);
+    }
+    uint4 ra[ACH], rb[BCH];
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    unet_lds_load<ACH, BCH>(a, 0, rb0, bbase, by, bx, bok, ra, rb);
+    unet_lds_store<ACH, BCH, AF>(smem, ra, rb);
+    __syncthreads();
+    for (int ks = 0; ks < a.ks; ++ks) {
+        const int cur = ks & 1;
+        // unconditional (the last step reloads itself into the idle buffer): operands
+        // loaded under a condition were kept in scratch memory by the compiler
+        unet_lds_load<ACH, BCH>(a, min(ks + 1, a.ks - 1), rb0, bbase, by, bx, bok, ra, rb);
+        const char* st = smem + cur * STAGE;
+        uint4 af[4], bf[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) af[i] = *(const uint4*)(st + (wr * 4 + i) * 1024 + lane * 16);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bf[j] = *(const uint4*)(st + AF * 1024 + (wp * 4 + j) * 1024 + lane * 16);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i]),
+                                                                  __builtin_bit_cast(bf16x8, bf[j]), acc[i][j], 0,
+                                                                  0, 0);
+        unet_lds_store<ACH, BCH, AF>(smem + (cur ^ 1) * STAGE, ra, rb);
+        __syncthreads();
+    }
+    // epilogue (as unet_conv_kernel): lane holds channels 16 rb + 4 g .. + 3 of pixel 16 pb + r16
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const long p = px0 + (wp * 4 + j) * 16 + r16;
+        if (p >= npix) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c0 = (rb0 + wr * 4 + i) * 16 + 4 * g;
+            if (c0 >= a.cout) continue;
+            float v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = min(c0 + r, a.cout - 1);
+                float y = acc[i][j][r] * a.scale[c] + a.shift[c];
+                y = a.act == 1 ? (y > 0.0f ? y : kSlope * y) : (a.act == 2 ? fmaxf(y, 0.0f) : y);
+                v[r] = y;
+            }
+            const uint32_t lo = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+            const uint32_t hi = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+            *(uint2*)((uint16_t*)a.out + p * a.cout + c0) = make_uint2(lo, hi);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ element kernels
 // x float32 [n, H, W, 7] -> bf16 [n, H, W, 8] (zero 8th channel)
 __global__ void unet_cast_kernel(const float* x, uint16_t* xb, long npix) {
@@ -472,6 +607,15 @@ static void launch_conv(const ConvArgsU& c, hipStream_t s) {
     hipLaunchKernelGGL((unet_conv_kernel<MT, NPW, TAPS>), grid, dim3(256), 0, s, c);
 }
 
+template <int BM>
+static void launch_conv_lds(const ConvArgsU& c, hipStream_t s) {
+    constexpr int BN = 4 / (BM / 64) * 64;
+    const long npix = (long)c.n * c.H * c.W;
+    const dim3 grid((unsigned)((npix + BN - 1) / BN), (unsigned)(c.cout / BM));
+    const int lds = 2 * (BM / 16 + BN / 16) * 1024;
+    hipLaunchKernelGGL((unet_conv_lds_kernel<BM>), grid, dim3(256), lds, s, c);
+}
+
 extern "C" drc_status drc_unet_forward(drc_unet* u, const float* d_x, float* d_y, int n, int H, int W,
                                        void* d_ws, size_t ws_bytes, void* stream) {
     if (!u) return drc_fail(DRC_ERR_INVALID_ARG, "unet_forward: handle is NULL");
@@ -505,6 +649,8 @@ extern "C" drc_status drc_unet_forward(drc_unet* u, const float* d_x, float* d_y
         c.act = l == kUnetLayers - 1 ? 2 : 1;
         c.out_f32 = l == kUnetLayers - 1;
         if (kUnet[l].taps == 1) launch_conv<1, 4, 1>(c, s);
+        else if (c.cinp % 32 == 0 && c.cout % 128 == 0 && !c.out_f32) launch_conv_lds<128>(c, s);
+        else if (c.cinp % 32 == 0 && c.cout % 64 == 0 && !c.out_f32) launch_conv_lds<64>(c, s);
         else launch_conv<4, 4, 9>(c, s);
     };
     auto pool = [&](const uint16_t* in, uint16_t* out, int h, int w, int C) {
