@@ -1,4 +1,4 @@
-// Layer-path kernels (BF16) whose input rows are staged in LDS by bands,
+// Layer-path kernels whose input rows are staged in LDS by bands,
 // for the first and the last layer of the autoencoder (Sec. 4.3), the two
 // whose generic kernels were the slowest of the layer path.
 //
@@ -7,8 +7,9 @@
 // loads per pixel and tap; about 1 TB/s at 128x128). Here a workgroup takes
 // a band of BR = 256 / Wout output rows of one map: it loads the 2 BR + 1
 // input rows the band reads as whole 16-byte chunks (a map's rows are
-// contiguous), writes them to LDS as BF16 with 8 channels per pixel (channel
-// 7 = 0), and runs the MFMAs from there.
+// contiguous), writes them to LDS in the compute type (BF16, or FP8 e4m3
+// with the input's scale) with 8 channels per pixel (channel 7 = 0), and
+// runs the MFMAs from there.
 //
 // D1 (stride-2 3x3 transposed convolution [u2 | h1] -> 3 channels, float32
 // out, the four output phases merged into one 16-row block): the generic
@@ -50,24 +51,32 @@ struct E1Args {
     long total;
 };
 
+// P = P_BF16: 3 K steps of 32 (lane group g takes tap 4 ks + g); P_FP8: one
+// K step of 128 (lane group g takes taps 4 g .. 4 g + 3, 8 bytes each).
+template <int P>
 __global__ __launch_bounds__(kThreads) void e1_band_kernel(const E1Args e) {
+    typedef typename Traits<P>::T T;
+    typedef typename Traits<P>::V V;
+    constexpr int PXB = 8 * (int)sizeof(T);        // staged bytes per pixel
+    constexpr int KST = P == P_FP8 ? 1 : kKSteps;  // K steps
     extern __shared__ __align__(16) char smem[];
     const LayerArgs& a = e.a;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, r16 = lane & 15;
-    uint16_t* xs = (uint16_t*)smem;                // [pixel][8] bf16
-    const int zoff = kMaxRowPx * 16;               // 16 zero bytes: taps left of the map
+    T* xs = (T*)smem;                              // [pixel][8]
+    const int zoff = kMaxRowPx * PXB;              // 16 zero bytes: taps left of the map
     // channel 7 of every staged pixel and the zero block stay zero: the
     // staging writes channels 0..6 only
-    for (int i = tid; i < kMaxRowPx + 1; i += kThreads) *(uint4*)(smem + 16 * i) = make_uint4(0, 0, 0, 0);
+    for (int i = tid; i < kMaxRowPx * PXB / 16 + 1; i += kThreads) *(uint4*)(smem + 16 * i) = make_uint4(0, 0, 0, 0);
 
     // A fragments of both 16-row blocks, every K step, from the row-major pack
-    uint4 A[kKSteps][2];
+    V A[KST][2];
 #pragma unroll
-    for (int ks = 0; ks < kKSteps; ++ks)
+    for (int ks = 0; ks < KST; ++ks)
 #pragma unroll
         for (int m = 0; m < 2; ++m)
-            A[ks][m] = *(const uint4*)((const uint16_t*)a.wpack + (size_t)(16 * m + r16) * a.kstride + 32 * ks + 8 * g);
+            A[ks][m] = *(const V*)((const T*)a.wpack + (size_t)(16 * m + r16) * a.kstride +
+                                   ks * Traits<P>::KS + g * Traits<P>::VW);
 
     auto class_of = [&](long item) {
         int c = 0;
@@ -116,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void e1_band_kernel(const E1Args e) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int q = 4 * i + j, pix = q / 7;
-                xs[pix * 8 + (q - pix * 7)] = to_store<P_BF16>(f[j], 1.0f);
+                xs[pix * 8 + (q - pix * 7)] = to_store<P>(f[j], a.raw_qscale);
             }
         }
         __syncthreads();
@@ -141,24 +150,30 @@ __global__ __launch_bounds__(kThreads) void e1_band_kernel(const E1Args e) {
 #pragma unroll
             for (int m = 0; m < 2; ++m) acc[m][p] = f4{0.f, 0.f, 0.f, 0.f};
         }
+        // staged row 0 is input row 2 oy0 - 1; rows past the map bottom are never read
+        auto tap_off = [&](int t, int p) {
+            const int kh = t / 3, kw = t - 3 * (t / 3);
+            const bool ok = t < 9 && (kw > 0 || ox[p] > 0);
+            return ok ? ((2 * oyl[p] + kh) * Win + 2 * ox[p] + kw - 1) * PXB : zoff;
+        };
 #pragma unroll
-        for (int ks = 0; ks < kKSteps; ++ks) {
-            const int t = 4 * ks + g, kh = t / 3, kw = t - 3 * (t / 3);
-            uint4 bv[4];
+        for (int ks = 0; ks < KST; ++ks) {
+            V bv[4];
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                // staged row 0 is input row 2 oy0 - 1; rows past the map bottom are never read
-                const bool ok = t < 9 && (kw > 0 || ox[p] > 0);
-                const int off = ok ? ((2 * oyl[p] + kh) * Win + 2 * ox[p] + kw - 1) * 16 : zoff;
-                bv[p] = *(const uint4*)(smem + off);
+                if constexpr (P == P_FP8) {
+                    uint2 h[4];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) h[s] = *(const uint2*)(smem + tap_off(4 * g + s, p));
+                    bv[p] = __builtin_bit_cast(V, h);
+                } else {
+                    bv[p] = *(const V*)(smem + tap_off(4 * ks + g, p));
+                }
             }
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int p = 0; p < 4; ++p)
-                    acc[m][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[ks][m]),
-                                                                      __builtin_bit_cast(bf16x8, bv[p]), acc[m][p],
-                                                                      0, 0, 0);
+                for (int p = 0; p < 4; ++p) Traits<P>::mma(acc[m][p], A[ks][m], bv[p]);
         }
         // epilogue: lane holds channels 16 m + 4 g .. + 3 of its pixel
 #pragma unroll
@@ -171,9 +186,9 @@ __global__ __launch_bounds__(kThreads) void e1_band_kernel(const E1Args e) {
                 float val[4] = {acc[m][p].x * a.acc_scale + bias[m][0], acc[m][p].y * a.acc_scale + bias[m][1],
                                 acc[m][p].z * a.acc_scale + bias[m][2], acc[m][p].w * a.acc_scale + bias[m][3]};
                 if (ch < G.seg0.c)
-                    store_seg<P_BF16, false>(G.seg0, doff0, opix, ch, val);
+                    store_seg<P, false>(G.seg0, doff0, opix, ch, val);
                 else if (ch - G.seg0.c < G.seg1.c)
-                    store_seg<P_BF16, false>(G.seg1, doff1, opix, ch - G.seg0.c, val);
+                    store_seg<P, false>(G.seg1, doff1, opix, ch - G.seg0.c, val);
             }
         }
     }
@@ -316,14 +331,14 @@ bool e1_band_fits(int Hin, int Win) {
            (2 * br + 1) * Win * 7 / 4 <= kThreads * kChunks;
 }
 
-drc_status e1_band_forward(const LayerArgs& a, int num_cu, hipStream_t s) {
+drc_status e1_band_forward(const LayerArgs& a, int prec, int num_cu, hipStream_t s) {
     E1Args e;
     e.a = a;
     long total = 0;
     for (int c = 0; c < a.nclass; ++c) {
         const ClassGeom& G = a.cls[c];
         if (!e1_band_fits(G.Hin, G.Win) || G.Hout * 2 != G.Hin || G.Wout * 2 != G.Win || a.raw_c != 7 ||
-            G.s0.ld != 7 || a.kstride < 32 * kKSteps)
+            G.s0.ld != 7 || a.kstride < (prec == P_FP8 ? 128 : 32 * kKSteps) || (prec != P_BF16 && prec != P_FP8))
             return drc_fail(DRC_ERR_STATE, "e1 band: class %d (%dx%d) does not fit", c, G.Hin, G.Win);
         e.bg[c].br = kBandPx / G.Wout;
         e.bg[c].bands_per_map = G.Hout / e.bg[c].br;
@@ -332,9 +347,11 @@ drc_status e1_band_forward(const LayerArgs& a, int num_cu, hipStream_t s) {
     }
     e.total = total;
     if (total == 0) return DRC_OK;
-    const int lds = (kMaxRowPx + 1) * 16;
     const long grid = std::min(total, (long)num_cu * 2);  // two resident workgroups per CU (184 registers)
-    hipLaunchKernelGGL(e1_band_kernel, dim3((unsigned)grid), dim3(kThreads), lds, s, e);
+    if (prec == P_FP8)
+        hipLaunchKernelGGL(e1_band_kernel<P_FP8>, dim3((unsigned)grid), dim3(kThreads), kMaxRowPx * 8 + 16, s, e);
+    else
+        hipLaunchKernelGGL(e1_band_kernel<P_BF16>, dim3((unsigned)grid), dim3(kThreads), kMaxRowPx * 16 + 16, s, e);
     return check_launch("e1 band");
 }
 

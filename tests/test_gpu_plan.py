@@ -135,9 +135,10 @@ def test_autotune_keeps_results_bitwise(tmp_path, params):
         B.drc_cae_plan_destroy(plan)
 
 
-def test_layer_e1_staged_matches_gather(params):
-    """BF16 E1 of the layer path stages the float32 input rows in LDS when
-    every map starts on a 16-byte boundary and gathers it per lane
+@pytest.mark.parametrize("compute", ["bf16", "fp8"])
+def test_layer_e1_staged_matches_gather(params, compute):
+    """E1 of the layer path (BF16, FP8) stages the float32 input rows in LDS
+    when every map starts on a 16-byte boundary and gathers it per lane
     otherwise; both give bitwise-equal outputs (same operands, K order and
     rounding). Frames with the maps packed, and with every map shifted by a
     few floats, are compared map by map (32x32, 64x64, 128x128 through the
@@ -150,8 +151,10 @@ def test_layer_e1_staged_matches_gather(params):
     xu = np.zeros(len(x) + int(shift.sum()), dtype=np.float32)
     for m, (h, w) in enumerate(sizes):
         xu[xo_u[m]:xo_u[m] + h * w * 7] = x[xo[m]:xo[m] + h * w * 7]
-    cae = CAE("bf16", torch.from_numpy(params).to(DEV), device=DEV)
+    cae = CAE(compute, torch.from_numpy(params).to(DEV), device=DEV)
     cae.set_fused(False)
+    if compute == "fp8":
+        cae.calibrate_fp8(torch.from_numpy(synth.radiance_maps(4, 64, 64, seed=3)).to(DEV))
     ys = []
     for xx, offs in ((x, xo), (xu, xo_u)):
         maps = [(h, w, int(offs[m]), int(yo[m])) for m, (h, w) in enumerate(sizes)]
