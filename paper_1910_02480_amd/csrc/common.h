@@ -14,14 +14,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i8v __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------- casts
-// float -> bfloat16, round to nearest even; NaN stays NaN (quiet bit set).
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u)
-        return (u & 0x007fffffu) ? (uint16_t)((u >> 16) | 0x40u) : (uint16_t)(u >> 16);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// float -> bfloat16, round to nearest even (the hardware conversion,
+// v_cvt_pk_bf16_f32; a NaN stays a NaN).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
     return __uint_as_float((uint32_t)h << 16);
 }
