@@ -62,9 +62,10 @@ def test_forward_batch16_32x32(oracle, params, params_dev, compute, gate):
 
 @pytest.mark.parametrize("compute,gate", [("f32", 1e-5), ("bf16", 1e-2)])
 @pytest.mark.parametrize("n,H,W", [(1, 8, 8), (2, 8, 24), (3, 40, 40), (2, 64, 64), (1, 128, 128),
-                                   (5, 24, 16)])
+                                   (5, 24, 16), (2, 32, 64), (1, 128, 64)])
 def test_forward_shapes(oracle, params, params_dev, compute, gate, n, H, W):
-    """Smallest map, non-square maps, ragged tile tails (40x40: 25-pixel bottleneck), 128x128."""
+    """Smallest map, non-square maps, ragged tile tails (40x40: 25-pixel bottleneck), 128x128, and
+    non-square maps whose E1 and D1 run in the band-staged kernels (32x64, 128x64)."""
     x = synth.radiance_maps(n, H, W, seed=7)
     y, _, _ = _run(_cae(compute, params_dev), x)
     r = oracle.forward(params, x)["y"]
