@@ -12,7 +12,7 @@
 // runs the MFMAs from there.
 //
 // D1 (stride-2 3x3 transposed convolution [u2 | h1] -> 3 channels, float32
-// out, the four output phases merged into one 16-row block): the generic
+// out, the four output phases merged into one 16-row block; BF16 or FP8): the generic
 // kernel reads each input pixel from L2 once per GEMM pixel that has it as
 // a neighbour (4 times). Here a workgroup stages BR = 256 / Win input rows
 // plus the row below them (64 channels, 16-byte chunks) and gathers the
@@ -36,9 +36,9 @@ constexpr int kChunks = 8;       // E1: staged 16-byte chunks per thread (input 
 constexpr int kKSteps = 3;       // E1: K = 9 taps x 8 channels, padded to 96
 constexpr int kMaxRowPx = 1152;  // E1: staged pixels, (2 BR + 1) Win = 2 * kBandPx * 2 + Win <= 1152 for Win <= 128
 constexpr int kD1Chunks = 10;    // D1: staged 16-byte chunks per thread, (BR + 1) Win * 8 <= 2560
-constexpr int kD1PixB = 144;     // D1: LDS bytes per staged pixel (64 channels + 16 bytes against bank conflicts)
 constexpr int kD1MaxPx = 320;    // D1: staged pixels, (BR + 1) Win = kBandPx + Win <= 320 for Win <= 64
-constexpr int kD1YOff = kD1MaxPx * kD1PixB + 16;  // D1: the band's output (2 BR rows x 2 Win x 3 floats = 12 KB)
+constexpr int kD1YOff = kD1MaxPx * 144 + 32;  // D1: the band's output (2 BR rows x 2 Win x 3 floats = 12 KB),
+                                              // after the staged pixels (at most 144 bytes each) and the zero block
 
 struct BandGeom {
     int bands_per_map, br;  // bands of a map, output rows per band
@@ -198,18 +198,28 @@ __global__ __launch_bounds__(kThreads) void e1_band_kernel(const E1Args e) {
 // D1: rows r = phase * 3 + co of the 16-row block (12 used), K = (neighbour,
 // channel) in steps of 32 (8 steps); lane group g of step ks takes neighbour
 // ks / 2, channels 32 (ks % 2) + 8 g .. + 8 (u2 below 32, h1 above).
+// P = P_BF16: 8 K steps of 32 (above); P_FP8: 2 K steps of 128, lane group g
+// of step ks taking neighbour 2 ks + g / 2, channels 32 (g % 2) .. + 32.
+template <int P>
 __global__ __launch_bounds__(kThreads) void d1_band_kernel(const E1Args e) {
+    typedef typename Traits<P>::T T;
+    typedef typename Traits<P>::V V;
+    constexpr int ES = (int)sizeof(T);
+    constexpr int PIXB = 64 * ES + 16;     // staged bytes per pixel (64 channels + 16 against bank conflicts)
+    constexpr int CPS = 2 * ES;            // 16-byte chunks per source (32 channels)
+    constexpr int CPP = 2 * CPS;           // chunks per pixel
+    constexpr int KST = 256 / Traits<P>::KS;
     extern __shared__ __align__(16) char smem[];
     const LayerArgs& a = e.a;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, r16 = lane & 15;
-    const int zoff = kD1MaxPx * kD1PixB;  // 16 zero bytes: neighbours right of the map
-    if (tid == 0) *(uint4*)(smem + zoff) = make_uint4(0, 0, 0, 0);
+    const int zoff = kD1MaxPx * PIXB;  // 32 zero bytes: neighbours right of the map
+    if (tid < 2) *(uint4*)(smem + zoff + 16 * tid) = make_uint4(0, 0, 0, 0);
 
-    uint4 A[8];
+    V A[KST];
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks)
-        A[ks] = *(const uint4*)((const uint16_t*)a.wpack + (size_t)r16 * a.kstride + 32 * ks + 8 * g);
+    for (int ks = 0; ks < KST; ++ks)
+        A[ks] = *(const V*)((const T*)a.wpack + (size_t)r16 * a.kstride + ks * Traits<P>::KS + g * Traits<P>::VW);
     float bias[4];
     int rph[4], rco[4];
 #pragma unroll
@@ -236,16 +246,16 @@ __global__ __launch_bounds__(kThreads) void d1_band_kernel(const E1Args e) {
         const ClassGeom& G = a.cls[c];
         const long b = item - e.bg[c].band0;
         const int n = (int)(b / e.bg[c].bands_per_map), a0 = (int)(b % e.bg[c].bands_per_map) * e.bg[c].br;
-        const int nch = (e.bg[c].br + 1) * G.Win * 8;
+        const int nch = (e.bg[c].br + 1) * G.Win * CPP;
         const long pix0 = ((long)n * G.Hin + a0) * G.Win;
 #pragma unroll
         for (int k = 0; k < kD1Chunks; ++k) {
             const int i = tid + kThreads * k;
-            const int px = i >> 3, part = i & 7;
+            const int px = i / CPP, part = i % CPP;
             const bool ok = i < nch && a0 + px / G.Win < G.Hin;
             const long pix = ok ? pix0 + px : 0;
-            const uint16_t* src = part < 4 ? (const uint16_t*)G.s0.p + pix * G.s0.ld + 8 * part
-                                           : (const uint16_t*)G.s1.p + pix * G.s1.ld + 8 * (part - 4);
+            const T* src = part < CPS ? (const T*)G.s0.p + pix * G.s0.ld + (16 / ES) * part
+                                      : (const T*)G.s1.p + pix * G.s1.ld + (16 / ES) * (part - CPS);
             const uint4 v = *(const uint4*)src;
             vq[k] = ok ? v : make_uint4(0, 0, 0, 0);
         }
@@ -259,12 +269,12 @@ __global__ __launch_bounds__(kThreads) void d1_band_kernel(const E1Args e) {
         const long b = item - e.bg[c].band0;
         const int n = (int)(b / e.bg[c].bands_per_map), a0 = (int)(b % e.bg[c].bands_per_map) * br;
         const int Win = G.Win;
-        const int nch = (br + 1) * Win * 8;
+        const int nch = (br + 1) * Win * CPP;
         __syncthreads();  // the previous band's LDS reads are done
 #pragma unroll
         for (int k = 0; k < kD1Chunks; ++k) {
             const int i = tid + kThreads * k;
-            if (i < nch) *(uint4*)(smem + (i >> 3) * kD1PixB + (i & 7) * 16) = vq[k];
+            if (i < nch) *(uint4*)(smem + (i / CPP) * PIXB + (i % CPP) * 16) = vq[k];
         }
         __syncthreads();
         if (item + gridDim.x < e.total) load_band(item + gridDim.x);
@@ -279,21 +289,20 @@ __global__ __launch_bounds__(kThreads) void d1_band_kernel(const E1Args e) {
             acc[p] = f4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-            const int nb = ks >> 1, di = nb >> 1, dj = nb & 1;
-            const int chunk = 4 * (ks & 1) + g;  // 16-byte chunk of the staged pixel
-            uint4 bv[4];
+        for (int ks = 0; ks < KST; ++ks) {
+            // neighbour and byte offset of this lane's K elements within the staged pixel
+            const int nb = P == P_FP8 ? 2 * ks + (g >> 1) : ks >> 1, di = nb >> 1, dj = nb & 1;
+            const int cb = P == P_FP8 ? 32 * (g & 1) : (4 * (ks & 1) + g) * 16;
+            V bv[4];
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 // the row below the band is staged (zero below the map)
                 const bool ok = !dj || bj[p] + 1 < Win;
-                const int off = ok ? ((al[p] + di) * Win + bj[p] + dj) * kD1PixB + chunk * 16 : zoff;
-                bv[p] = *(const uint4*)(smem + off);
+                const int off = ok ? ((al[p] + di) * Win + bj[p] + dj) * PIXB + cb : zoff;
+                bv[p] = *(const V*)(smem + off);
             }
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
-                acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[ks]),
-                                                                __builtin_bit_cast(bf16x8, bv[p]), acc[p], 0, 0, 0);
+            for (int p = 0; p < 4; ++p) Traits<P>::mma(acc[p], A[ks], bv[p]);
         }
         // epilogue: lane holds rows 4 g .. 4 g + 3 = (phase, channel) of its
         // GEMM pixel; the band's 2 BR output rows (contiguous in y) are
@@ -361,15 +370,15 @@ bool d1_band_fits(int Hin, int Win) {
     return Hin % br == 0 && (br + 1) * Win <= kD1MaxPx && (br + 1) * Win * 8 <= kThreads * kD1Chunks;
 }
 
-drc_status d1_band_forward(const LayerArgs& a, int num_cu, hipStream_t s) {
+drc_status d1_band_forward(const LayerArgs& a, int prec, int num_cu, hipStream_t s) {
     E1Args e;
     e.a = a;
     long total = 0;
     for (int c = 0; c < a.nclass; ++c) {
         const ClassGeom& G = a.cls[c];
         if (!d1_band_fits(G.Hin, G.Win) || G.Hout != 2 * G.Hin || G.Wout != 2 * G.Win || G.s0.c != 32 ||
-            G.s1.c != 32 || G.s0.ld % 8 || G.s1.ld % 8 || G.seg0.c != 3 || G.seg0.ld != 3 || a.kstride < 256 ||
-            a.raw_c)
+            G.s1.c != 32 || G.s0.ld % 16 || G.s1.ld % 16 || G.seg0.c != 3 || G.seg0.ld != 3 || a.kstride < 256 ||
+            a.raw_c || (prec != P_BF16 && prec != P_FP8))
             return drc_fail(DRC_ERR_STATE, "d1 band: class %d (%dx%d) does not fit", c, G.Hin, G.Win);
         e.bg[c].br = kBandPx / G.Win;
         e.bg[c].bands_per_map = G.Hin / e.bg[c].br;
@@ -378,9 +387,13 @@ drc_status d1_band_forward(const LayerArgs& a, int num_cu, hipStream_t s) {
     }
     e.total = total;
     if (total == 0) return DRC_OK;
-    const int lds = kD1YOff + 12 * kBandPx * 4;
     const long grid = std::min(total, (long)num_cu * 2);
-    hipLaunchKernelGGL(d1_band_kernel, dim3((unsigned)grid), dim3(kThreads), lds, s, e);
+    if (prec == P_FP8)
+        hipLaunchKernelGGL(d1_band_kernel<P_FP8>, dim3((unsigned)grid), dim3(kThreads), kD1YOff + 12 * kBandPx * 4, s,
+                           e);
+    else
+        hipLaunchKernelGGL(d1_band_kernel<P_BF16>, dim3((unsigned)grid), dim3(kThreads), kD1YOff + 12 * kBandPx * 4, s,
+                           e);
     return check_launch("d1 band");
 }
 

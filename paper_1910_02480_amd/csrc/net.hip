@@ -64,7 +64,7 @@ namespace drc {
 bool e1_band_fits(int Hin, int Win);
 drc_status e1_band_forward(const LayerArgs& a, int prec, int num_cu, hipStream_t s);
 bool d1_band_fits(int Hin, int Win);
-drc_status d1_band_forward(const LayerArgs& a, int num_cu, hipStream_t s);
+drc_status d1_band_forward(const LayerArgs& a, int prec, int num_cu, hipStream_t s);
 }  // namespace drc
 
 static Seg seg_none() {
@@ -199,8 +199,8 @@ drc_status forward_classes(drc_cae* h, void* const* packs, const FwdClass* fc, i
         }
         a.nclass = nclass;
         int npw = 0;
-        // BF16 and FP8 E1, BF16 D1: input rows staged in LDS by bands
-        bool band = (l == 0 && P != P_F32) || (l == 5 && P == P_BF16);
+        // BF16 and FP8 E1 and D1: input rows staged in LDS by bands
+        bool band = P != P_F32 && (l == 0 || l == 5);
         for (int c = 0; c < nclass; ++c) {
             a.cls[c] = class_geom(l, fc[c].n, fc[c].H, fc[c].W, false);
             fwd_tensors(l, fc[c].b, h->desc.final_relu, qout, a.cls[c]);
@@ -214,7 +214,7 @@ drc_status forward_classes(drc_cae* h, void* const* packs, const FwdClass* fc, i
         }
         if (band) {
             const long tok = prof_begin(h, PROF_FWD + l, s);
-            TRY(l == 0 ? e1_band_forward(a, P, h->num_cu, s) : d1_band_forward(a, h->num_cu, s));
+            TRY(l == 0 ? e1_band_forward(a, P, h->num_cu, s) : d1_band_forward(a, P, h->num_cu, s));
             prof_end(h, tok, s);
             continue;
         }

@@ -359,9 +359,8 @@ extern "C" drc_status drc_cae_autotune(drc_cae* h, int n, int H, int W, const fl
     for (int l = 0; l < 6 && st == DRC_OK; ++l) {
         TuneEntry best;
         best.us = 1e30;
-        // E1 (BF16, FP8) / D1 (BF16) in band-staged kernels: the GEMM tile is not a choice (one timing)
-        const bool banded = (h->prec != P_F32 && l == 0 && e1_band_fits(H, W)) ||
-                            (h->prec == P_BF16 && l == 5 && d1_band_fits(H / 2, W / 2));
+        // E1 / D1 (BF16, FP8) in band-staged kernels: the GEMM tile is not a choice (one timing)
+        const bool banded = h->prec != P_F32 && ((l == 0 && e1_band_fits(H, W)) || (l == 5 && d1_band_fits(H / 2, W / 2)));
         bool timed = false;
         for (int npw : {1, 2, 4, 8}) {
             if (!npw_supported(h->prec, l, false, npw)) continue;

@@ -180,6 +180,11 @@ def test_fp8_forward_reported(oracle, params, params_dev):
         assert np.mean(d == 0) >= 0.99, name
         assert np.mean(d > 1.01) <= 0.005, name
         assert d.max() <= 2.01, name
+    # D1 (float32 out) on the stored e4m3 inputs: the FP8 MFMA's accumulation of
+    # 256 exact products (measured 3e-5 of the map's largest output)
+    mr_y = max_rel_per_map(y, refs["y"])
+    print(f"fp8 layer y: max_rel {mr_y.max():.2e}")
+    assert mr_y.max() <= 1e-4
 
 
 def test_batch_composition_independence(params_dev):
