@@ -48,6 +48,9 @@ _LABELS = (
     (r"interp_weights_kernel", "interp weights"),
     (r"augment_kernel", "augmentation"),
     (r"unet_conv_kernel<\d+, \d+, 9>", "U-Net 3x3 convolution"),
+    (r"unet_conv_lds_kernel<\d+>", "U-Net 3x3 convolution (LDS-tiled)"),
+    (r"e1_band_kernel<(\d)>", "forward E1 (band-staged)"),
+    (r"d1_band_kernel<(\d)>", "forward D1 (band-staged)"),
     (r"unet_conv_kernel<\d+, \d+, 1>", "U-Net 1x1 output convolution"),
     (r"unet_upcat_kernel", "U-Net upsample + concat"),
     (r"unet_pool_kernel", "U-Net max-pool"),
