@@ -117,9 +117,16 @@ size_t drc_cae_num_params(const drc_cae* h);
 
 /* Convert the float32 master parameters d_params into the handle's packed
  * weights (forward and transposed backward packs, in the compute type) and
- * bias copy. Must be called before forward/backward; drc_cae_step repacks by
- * itself after its update. For FP8 handles the weight scales are computed
- * here (448 / max |W| per layer). */
+ * bias copy: the network's learnable parameters (the weights and biases of
+ * the six layers of Sec. 4.3, kept in float32 as the Adam state of Sec. 5).
+ * Must be called before forward/backward; drc_cae_step repacks by itself
+ * after its update. For FP8 handles the weight scales are computed here
+ * (448 / max |W| per layer) and the call synchronises the stream to read
+ * them. d_params: 206 819 floats, device, 4-byte aligned, read only.
+ * Errors: DRC_ERR_INVALID_ARG for a NULL handle or a NULL / misaligned
+ * d_params; DRC_ERR_HIP if the packing launch fails. The packs are
+ * replaced in place: work already enqueued on another stream that still
+ * reads them must be complete first. */
 drc_status drc_cae_set_params(drc_cae* h, const float* d_params, void* stream);
 
 /* Activation recompute policy for training (default 0).
@@ -157,15 +164,35 @@ drc_status drc_cae_workspace_size(const drc_cae* h, int n, int H, int W, int fla
 /* Forward pass (Sec. 4.3, Eq. 2's R): d_x [n,H,W,7] -> d_y [n,H,W,3].
  * d_saved may be NULL (inference) or a buffer of drc_cae_saved_size bytes
  * that receives the activations for a later drc_cae_backward; it must stay
- * untouched until then. */
+ * untouched until then. d_ws: drc_cae_workspace_size(DRC_WS_FORWARD)
+ * bytes (may be NULL when that size is 0).
+ * Errors (nothing is enqueued): DRC_ERR_INVALID_ARG for a NULL handle,
+ * NULL d_x / d_y / d_ws, d_x or d_y not 16-byte aligned, or d_saved /
+ * d_ws not 256-byte aligned; DRC_ERR_SHAPE for n < 1, H or W not a
+ * multiple of 8 (>= 8), or n*H*W > 2^28; DRC_ERR_WORKSPACE when ws_bytes
+ * is below the required size; DRC_ERR_STATE before drc_cae_set_params
+ * (FP8: before drc_cae_calibrate_fp8) or when the current device is not
+ * the handle's. */
 drc_status drc_cae_forward(drc_cae* h, const float* d_x, float* d_y, int n, int H, int W,
                            void* d_saved, void* d_ws, size_t ws_bytes, void* stream);
 
-/* Backward pass: given d_dy = dL/dy [n,H,W,3] and the d_saved of the
- * forward pass on d_x, writes dL/dparams (flat layout) to d_dparams and,
- * when d_dx is not NULL, dL/dx [n,H,W,7]. ReLU derivatives use the rule
- * relu'(z) = [z > 0] evaluated on the stored activations. Float32 and
- * bfloat16 handles only. */
+/* Backward pass of the network of Sec. 4.3 (the gradient that training
+ * with the L1 loss of Sec. 4.3 and Adam, Sec. 5, needs): given d_dy =
+ * dL/dy [n,H,W,3] and the d_saved of the forward pass on d_x, writes
+ * dL/dparams (flat layout) to d_dparams and, when d_dx is not NULL, dL/dx
+ * [n,H,W,7]. ReLU derivatives use the rule relu'(z) = [z > 0] evaluated on
+ * the stored activations; a transposed convolution's data gradient is the
+ * matching stride-2 convolution with channel-transposed weights and vice
+ * versa; the skip concatenations split their gradient and add it to h1,
+ * h2. Float32 and bfloat16 handles only. d_saved is read only (with the
+ * recompute policy on, h3, u3 and u2 are recomputed into d_ws). d_ws:
+ * drc_cae_workspace_size(DRC_WS_BACKWARD) bytes.
+ * Errors (nothing is enqueued): DRC_ERR_INVALID_ARG for a NULL handle or
+ * NULL / misaligned d_x, d_dy, d_dparams (16 bytes), d_saved, d_ws (256
+ * bytes), or misaligned d_dx; DRC_ERR_SHAPE as drc_cae_forward;
+ * DRC_ERR_WORKSPACE for a short workspace; DRC_ERR_STATE before
+ * drc_cae_set_params or on another device; DRC_ERR_UNSUPPORTED for FP8
+ * handles and for final_relu = 1. */
 drc_status drc_cae_backward(drc_cae* h, const float* d_x, const float* d_dy, const void* d_saved,
                             float* d_dparams, float* d_dx, int n, int H, int W, void* d_ws,
                             size_t ws_bytes, void* stream);
@@ -175,7 +202,17 @@ drc_status drc_cae_backward(drc_cae* h, const float* d_x, const float* d_dy, con
  * backward (recompute policy of the handle), Adam update of d_params with
  * moments d_m, d_v at step count t (>= 1), then repack of the weights.
  * dL/dy = sign(y - t) / (n H W 3) with sign(0) = 0. d_dparams may be NULL;
- * when given it receives the gradient used by the update. */
+ * when given it receives the gradient used by the update. d_params, d_m,
+ * d_v are updated in place (206 819 floats each). d_ws:
+ * drc_cae_workspace_size(DRC_WS_STEP) bytes.
+ * The step packs d_params itself when the handle was not packed from
+ * that buffer, so drc_cae_set_params is optional here.
+ * Errors (nothing is enqueued): DRC_ERR_INVALID_ARG for a NULL handle or
+ * adam, bad Adam hyper-parameters (lr <= 0, betas outside [0, 1),
+ * eps < 0), t < 1, or a NULL / misaligned buffer (16 bytes; d_loss 4,
+ * d_ws 256); DRC_ERR_SHAPE and DRC_ERR_WORKSPACE as drc_cae_backward;
+ * DRC_ERR_STATE on another device; DRC_ERR_UNSUPPORTED for FP8 handles
+ * and for final_relu = 1. */
 drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, float* d_v, int64_t t,
                         const drc_adam_cfg* adam, const float* d_x, const float* d_target,
                         float* d_loss, float* d_dparams, int n, int H, int W, void* d_ws,
@@ -183,7 +220,15 @@ drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, float* d_v, int
 
 /* FP8 handles: static per-tensor activation scales (448 / max |value|) from
  * a float32 forward over the calibration batch d_x. Must follow set_params.
- * The scales of x, [u2|h1], [u3|h2] and h3 are kept in the handle. */
+ * The scales of x, [u2|h1], [u3|h2] and h3 are kept in the handle. This is
+ * the precision form of the network of Sec. 4.3 (the paper evaluates it in
+ * float32; e4m3 with per-tensor scales is this library's inference
+ * variant). d_ws: drc_cae_workspace_size(DRC_WS_CALIBRATE) bytes.
+ * Synchronises the stream (the scales are read back to the host).
+ * Errors: DRC_ERR_INVALID_ARG for a NULL handle or NULL / misaligned d_x,
+ * d_ws; DRC_ERR_STATE for a handle that is not FP8 or before
+ * drc_cae_set_params; DRC_ERR_SHAPE and DRC_ERR_WORKSPACE as
+ * drc_cae_forward. */
 drc_status drc_cae_calibrate_fp8(drc_cae* h, const float* d_x, int n, int H, int W, void* d_ws,
                                  size_t ws_bytes, void* stream);
 
@@ -192,19 +237,36 @@ drc_status drc_cae_calibrate_fp8(drc_cae* h, const float* d_x, int n, int H, int
  * stream. */
 drc_status drc_cae_get_fp8_scales(const drc_cae* h, float out[10], void* stream);
 
-/* Mixed-resolution frames (many maps of different sizes, one pass).
+/* Mixed-resolution frames (many maps of different sizes, one pass). The
+ * network is fully convolutional, so the weights of the 32x32 maps of
+ * Sec. 4.3 serve any size; larger maps keep more detail (Sec. 6.3) and
+ * fixed 32x32 maps are a limitation the paper names (Sec. 7).
  * plan_create sorts the maps into resolution classes, builds per-layer work
  * lists (tile shapes per resolution from the tuning cache file, NULL =
- * built-in defaults) and uploads them. plan_launch runs the whole frame as
- * one captured HIP graph of persistent kernels on the given stream; the
- * graph is recorded on the first launch for a given (workspace, stream,
- * x, y) and replayed afterwards. */
+ * built-in defaults) and uploads them (it allocates the plan's device
+ * tables). maps[m]: h, w multiples of 8 (>= 8), at most 4 distinct sizes;
+ * x_off, y_off >= 0 element offsets (a map whose x_off is not a multiple
+ * of 4 floats runs through the layer kernels). Errors: DRC_ERR_SHAPE for
+ * count < 1 or a bad size, DRC_ERR_INVALID_ARG for a negative offset or a
+ * NULL handle / out, DRC_ERR_UNSUPPORTED for more than 4 sizes.
+ * plan_workspace_size gives the bytes of d_ws for plan_launch.
+ * plan_launch runs the whole frame on the given stream: on a non-null
+ * stream as one captured HIP graph, recorded on the first launch for a
+ * given (workspace, stream, x, y) and after any call that changes the
+ * handle (set_params, calibrate_fp8, set_fused, set_tile, autotune), and
+ * replayed otherwise; on the null stream directly. Errors:
+ * DRC_ERR_INVALID_ARG for NULL / misaligned pointers, DRC_ERR_WORKSPACE,
+ * DRC_ERR_STATE before set_params (FP8: calibrate_fp8). plan_destroy frees
+ * the plan and its graph; the handle must outlive its plans. */
 drc_status drc_cae_plan_create(drc_cae* h, const drc_map_desc* maps, int count,
                                const char* tune_cache, drc_plan** out);
 drc_status drc_cae_plan_workspace_size(const drc_plan* p, size_t* bytes);
 drc_status drc_cae_plan_launch(drc_plan* p, const float* d_x_packed, float* d_y_packed, void* d_ws,
                                size_t ws_bytes, void* stream);
 void drc_cae_plan_destroy(drc_plan* p);
+/* Number of times plan_launch has recorded the plan's graph (introspection:
+ * a replay does not record). Errors: DRC_ERR_INVALID_ARG for NULL. */
+drc_status drc_cae_plan_captures(const drc_plan* p, int64_t* count);
 
 /* Sampling the predicted map R as an environment map (Sec. 3: the indirect
  * term alternates samples drawn from R, as from an environment map with
@@ -321,6 +383,18 @@ drc_status drc_cae_autotune(drc_cae* h, int n, int H, int W, const float* d_x, v
 /* Tile shape (pixel blocks of 16 per wave) the forward uses for layer
  * 0..5 (E1..D1) at resolution H; 0 = built-in default. */
 drc_status drc_cae_set_tile(drc_cae* h, int layer, int H, int npw);
+
+/* Weight-gradient schedule (host only; enqueues nothing, needs no GPU):
+ * for layer 0..5 (E1..D1) of an n x H x W backward in compute type
+ * DRC_F32 or DRC_BF16, info[0] = kernel (0: float32 MFMA with register
+ * prefetch, 1: BF16 with LDS-staged operands, 2: BF16 with LDS transpose
+ * reads), info[1] = reduction rows per strip (BF16) or 0, info[2] = strips
+ * per workgroup chunk (BF16) or reduction pixels per chunk (float32),
+ * info[3] = chunks (workgroups per tile column). Each chunk sums its strips
+ * in order into one partial tile; the partial tiles are then summed in a
+ * fixed order. Errors: DRC_ERR_INVALID_ARG (NULL info, bad layer or
+ * compute), DRC_ERR_UNSUPPORTED (FP8), DRC_ERR_SHAPE. */
+drc_status drc_cae_wgrad_schedule(int compute, int layer, int n, int H, int W, int64_t info[4]);
 
 /* Kernel timing (profiling hook). enable = 1 creates a pool of HIP events
  * and records one event pair on the call's stream around each group of

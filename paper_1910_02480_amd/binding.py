@@ -67,6 +67,7 @@ _SIGS = {
     "drc_cae_plan_workspace_size": (_I, [_VP, ctypes.POINTER(_SZ)]),
     "drc_cae_plan_launch": (_I, [_VP, _VP, _VP, _VP, _SZ, _VP]),
     "drc_cae_plan_destroy": (None, [_VP]),
+    "drc_cae_plan_captures": (_I, [_VP, ctypes.POINTER(ctypes.c_int64)]),
     "drc_envmap_build": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP]),
     "drc_envmap_sample": (_I, [_VP, _VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
     "drc_envmap_pdf": (_I, [_VP, _VP, _I, _I, _I, _I, _VP, _VP, _VP]),
@@ -80,6 +81,7 @@ _SIGS = {
     "drc_unet_forward": (_I, [_VP, _VP, _VP, _I, _I, _I, _VP, _SZ, _VP]),
     "drc_cae_autotune": (_I, [_VP, _I, _I, _I, _VP, _VP, _SZ, ctypes.c_char_p, _VP]),
     "drc_cae_set_tile": (_I, [_VP, _I, _I, _I]),
+    "drc_cae_wgrad_schedule": (_I, [_I, _I, _I, _I, _I, ctypes.POINTER(ctypes.c_int64)]),
     "drc_cae_profile": (_I, [_VP, _I]),
     "drc_cae_profile_read": (_I, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "drc_status_string": (ctypes.c_char_p, [_I]),
@@ -238,6 +240,12 @@ def drc_cae_plan_destroy(p):
     lib().drc_cae_plan_destroy(p)
 
 
+def drc_cae_plan_captures(p):
+    c = ctypes.c_int64()
+    _check(lib().drc_cae_plan_captures(p, ctypes.byref(c)))
+    return int(c.value)
+
+
 def drc_envmap_build(y, cdf_u, cdf_v, total, stream=None):
     """y [n, H, W, 3] -> cdf_u [n, H, W], cdf_v [n, H], total [n]."""
     n, H, W = _nhw(y, 3)
@@ -312,6 +320,14 @@ def drc_cae_autotune(h, x, ws, tune_cache, stream=None):
 
 def drc_cae_set_tile(h, layer, H, npw):
     _check(lib().drc_cae_set_tile(h, layer, H, npw))
+
+
+def drc_cae_wgrad_schedule(compute, layer, n, H, W):
+    """(kernel, rows per strip, strips (or pixels) per chunk, chunks) of a
+    layer's weight gradient; host only."""
+    info = (ctypes.c_int64 * 4)()
+    _check(lib().drc_cae_wgrad_schedule(int(compute), int(layer), int(n), int(H), int(W), info))
+    return tuple(int(v) for v in info)
 
 
 def drc_cae_profile(h, enable):

@@ -44,6 +44,18 @@ class CAE:
         assert params.dtype == torch.float32 and params.numel() == self.num_params
         self.params = params.contiguous()
         B.drc_cae_set_params(self.h, self.params)
+        # what the packs were made from: storage and its in-place version
+        self._packed = (self.params.data_ptr(), self.params._version)
+
+    def ensure_packed(self, params: torch.Tensor):
+        """Check that the handle's packs hold the current values of params:
+        repack after an in-place update of the packed tensor (its version
+        counter moved); a different tensor is an error, since the packs
+        would silently hold other weights."""
+        if self.params is None or params.data_ptr() != self._packed[0]:
+            raise ValueError("params is not the tensor this handle was packed from: call cae.set_params(params)")
+        if params._version != self._packed[1]:
+            self.set_params(params.detach())
 
     def set_recompute(self, on: bool):
         B.drc_cae_set_recompute(self.h, int(on))
@@ -123,12 +135,14 @@ class Trainer:
 class CAEFunction(torch.autograd.Function):
     """y = CAE(x; params) with the library's forward and backward kernels.
 
-    The parameters must already be packed into the handle (cae.set_params);
-    the params tensor is an input only so that autograd routes its gradient.
+    params must be the tensor the handle was packed from (cae.set_params);
+    an in-place update of it since then (e.g. an optimizer step) is repacked
+    before the forward, and any other tensor is rejected.
     """
 
     @staticmethod
     def forward(ctx, x, params, cae: CAE):
+        cae.ensure_packed(params)
         x = x.contiguous()
         n, H, W, _ = x.shape
         saved, _ = cae.saved_buffer(n, H, W)

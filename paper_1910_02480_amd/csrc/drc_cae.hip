@@ -202,6 +202,7 @@ extern "C" drc_status drc_cae_set_fused(drc_cae* h, int on) {
     if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "set_fused: handle is NULL");
     if (on != 0 && on != 1) return drc_fail(DRC_ERR_INVALID_ARG, "set_fused: on must be 0 or 1");
     h->fused = on;
+    h->gen++;
     return DRC_OK;
 }
 
@@ -216,6 +217,7 @@ extern "C" drc_status drc_cae_set_tile(drc_cae* h, int layer, int H, int npw) {
     } else {
         h->tile[{layer, H}] = npw;
     }
+    h->gen++;
     return DRC_OK;
 }
 
@@ -424,6 +426,28 @@ WgradPlan wgrad_plan(int l, int n, int H, int W, int prec) {
     return w;
 }
 
+extern "C" drc_status drc_cae_wgrad_schedule(int compute, int layer, int n, int H, int W, int64_t info[4]) {
+    if (!info) return drc_fail(DRC_ERR_INVALID_ARG, "wgrad_schedule: info is NULL");
+    if (compute != DRC_F32 && compute != DRC_BF16)
+        return drc_fail(compute == DRC_FP8_E4M3 ? DRC_ERR_UNSUPPORTED : DRC_ERR_INVALID_ARG,
+                        "wgrad_schedule: compute %d (float32 and bfloat16 handles have a backward)", compute);
+    if (layer < 0 || layer > 5) return drc_fail(DRC_ERR_INVALID_ARG, "wgrad_schedule: layer %d", layer);
+    TRY(check_shape("wgrad_schedule", n, H, W));
+    const WgradPlan w = wgrad_plan(layer, n, H, W, compute);
+    if (w.bf16) {
+        info[0] = w.tr ? 2 : 1;
+        info[1] = w.R;
+        info[2] = w.strips_per_chunk;
+        info[3] = w.bchunks;
+    } else {
+        info[0] = 0;
+        info[1] = 0;
+        info[2] = w.per_block;
+        info[3] = w.nchunks;
+    }
+    return DRC_OK;
+}
+
 void layer_io(int l, int H, int W, int* hin, int* win, int* hout, int* wout) {
     static const int din[6] = {1, 2, 4, 8, 4, 2};   // input = H / din
     static const int dout[6] = {2, 4, 8, 4, 2, 1};  // output = H / dout
@@ -595,6 +619,7 @@ extern "C" drc_status drc_cae_set_params(drc_cae* h, const float* d_params, void
     }
     h->params_set = true;
     h->packed_from = d_params;
+    h->gen++;
     return DRC_OK;
 }
 

@@ -48,6 +48,11 @@ struct drc_cae {
     bool params_set = false;
     bool calibrated = false;
     const float* packed_from = nullptr;
+    // Bumped by every call that changes what a forward computes or how it is
+    // scheduled (set_params, calibrate_fp8, set_fused, set_tile, autotune):
+    // a plan's captured graph bakes in kernel arguments (FP8 scales, the
+    // fused/layer route, tile shapes) and is re-recorded when this changes.
+    unsigned long gen = 1;
     std::map<std::pair<int, int>, int> tile;     // (layer, H) -> pixel blocks per wave
     std::map<std::pair<int, int>, int> tile_px;  // (layer, H) -> GEMM pixels per work item
     // optional timing of kernel groups with events on the caller's stream

@@ -850,5 +850,6 @@ extern "C" drc_status drc_cae_calibrate_fp8(drc_cae* h, const float* d_x, int n,
     HIPCHK(hipMemcpyAsync(h->scales + 6, h->host_scales + 6, 4 * sizeof(float), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     h->calibrated = true;
+    h->gen++;
     return DRC_OK;
 }

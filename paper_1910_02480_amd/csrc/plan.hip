@@ -113,7 +113,9 @@ struct drc_plan {
     size_t ws_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    const void* key[4] = {nullptr, nullptr, nullptr, nullptr};  // ws, stream, x, y of the captured graph
+    // ws, stream, x, y and the handle's generation of the captured graph
+    const void* key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    long captures = 0;  // graphs recorded so far
 };
 
 extern "C" drc_status drc_cae_plan_create(drc_cae* h, const drc_map_desc* maps, int count,
@@ -198,6 +200,12 @@ extern "C" drc_status drc_cae_plan_workspace_size(const drc_plan* p, size_t* byt
     return DRC_OK;
 }
 
+extern "C" drc_status drc_cae_plan_captures(const drc_plan* p, int64_t* count) {
+    if (!p || !count) return drc_fail(DRC_ERR_INVALID_ARG, "plan_captures: NULL argument");
+    *count = p->captures;
+    return DRC_OK;
+}
+
 extern "C" void drc_cae_plan_destroy(drc_plan* p) {
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -220,7 +228,9 @@ static drc_status plan_enqueue(drc_plan* p, const float* x, float* y, char* ws, 
         const PlanClass& pc = p->cls[c];
         const long* xo = (const long*)(p->d_tables + pc.dev_xoff);
         const long* yo = (const long*)(p->d_tables + pc.dev_yoff);
-        if (h->fused && h->prec == P_BF16 && fused_forward_size(pc.H, pc.W)) {
+        // (its input staging reads 16-byte vectors: every map must start on a 16-byte boundary)
+        if (h->fused && h->prec == P_BF16 && fused_forward_size(pc.H, pc.W) && pc.x_al16 &&
+            (uintptr_t)x % 16 == 0) {
             // the class's h1 region (n maps) holds the per-workgroup slots
             st = fused_forward(h, x, y, pc.n, pc.H, pc.W, xo, yo, ws + pc.act[0],
                                (size_t)pc.n * 16 * pc.H * pc.W, s);
@@ -279,7 +289,7 @@ extern "C" drc_status drc_cae_plan_launch(drc_plan* p, const float* d_x, float* 
         return drc_fail(DRC_ERR_WORKSPACE, "plan_launch: workspace %zu < %zu bytes", ws_bytes, p->ws_bytes);
     hipStream_t s = (hipStream_t)stream;
     if (!s) return plan_enqueue(p, d_x, d_y, (char*)d_ws, s);  // the null stream cannot be captured
-    const void* key[4] = {d_ws, (const void*)s, d_x, d_y};
+    const void* key[5] = {d_ws, (const void*)s, d_x, d_y, (const void*)(uintptr_t)h->gen};
     if (!p->exec || memcmp(key, p->key, sizeof key) != 0) {
         if (p->exec) {
             (void)hipGraphExecDestroy(p->exec);
@@ -301,6 +311,7 @@ extern "C" drc_status drc_cae_plan_launch(drc_plan* p, const float* d_x, float* 
         p->graph = g;
         HIPCHK(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
         memcpy(p->key, key, sizeof key);
+        p->captures++;
     }
     HIPCHK(hipGraphLaunch(p->exec, s));
     return DRC_OK;
@@ -388,6 +399,7 @@ extern "C" drc_status drc_cae_autotune(drc_cae* h, int n, int H, int W, const fl
         }
         if (st == DRC_OK) {
             tune[tune_key(h->arch, h->prec, l, H, W)] = best;
+            h->gen++;
             h->tile[{l, H}] = best.npw;
             h->tile_px[{l, H}] = best.tile_px;
             fc.npw[l] = best.npw;

@@ -154,3 +154,22 @@ def test_unet_host_checks(B):
     assert L.drc_unet_create(None) == 1
     from oracle import unet as U
     assert B.drc_unet_num_params() == U.num_params()
+
+
+def test_wgrad_schedule_host_only(B):
+    """The weight-gradient schedule is computed on the host: the parity tests'
+    small batches run one strip per chunk, the benchmark's training batch
+    (256 x 64x64) at least two in every BF16 layer."""
+    for l in range(6):
+        kind, R, spc, chunks = B.drc_cae_wgrad_schedule(B.DRC_BF16, l, 256, 64, 64)
+        assert kind == 2 and R >= 4 and spc >= 2 and chunks >= 128, (l, kind, R, spc, chunks)
+        kind, R, spc, chunks = B.drc_cae_wgrad_schedule(B.DRC_BF16, l, 4, 64, 64)
+        assert kind == 2 and spc == 1, (l, spc)
+        kind, R, per, chunks = B.drc_cae_wgrad_schedule(B.DRC_F32, l, 256, 64, 64)
+        assert kind == 0 and per >= 64 and chunks >= 1
+    _expect(B, 3, B.drc_cae_wgrad_schedule, B.DRC_FP8_E4M3, 0, 4, 64, 64)
+    _expect(B, 1, B.drc_cae_wgrad_schedule, B.DRC_BF16, 6, 4, 64, 64)
+    _expect(B, 2, B.drc_cae_wgrad_schedule, B.DRC_BF16, 0, 0, 64, 64)
+    _expect(B, 2, B.drc_cae_wgrad_schedule, B.DRC_BF16, 0, 4, 60, 64)
+    L = B.lib()
+    assert L.drc_cae_wgrad_schedule(1, 0, 4, 64, 64, None) == 1

@@ -192,3 +192,25 @@ def _saved_again(cae, x):
     saved, _ = cae.saved_buffer(n, H, W)
     cae.forward(x, saved=saved)
     return (saved,)
+
+
+def test_autograd_function_tracks_params(params):
+    """CAEFunction computes with the current values of params: an in-place
+    update is repacked before the next forward, and a tensor the handle was
+    not packed from is rejected."""
+    from paper_1910_02480_amd.cae import CAE, CAEFunction
+    x, _ = synth.training_batch(2, 32)
+    xd = torch.from_numpy(x).to(DEV)
+    p = torch.from_numpy(params.copy()).to(DEV).requires_grad_(True)
+    cae = CAE("f32", p.detach(), device=DEV)
+    y0 = CAEFunction.apply(xd, p, cae).detach().clone()
+    with torch.no_grad():
+        p.mul_(2.0)
+    y1 = CAEFunction.apply(xd, p, cae).detach()
+    ref = CAE("f32", p.detach().clone(), device=DEV).forward(xd)
+    torch.cuda.synchronize()
+    assert not torch.equal(y0, y1)
+    assert torch.equal(y1, ref)
+    other = p.detach().clone().requires_grad_(True)
+    with pytest.raises(ValueError):
+        CAEFunction.apply(xd, other, cae)

@@ -54,10 +54,11 @@ def test_plan_mixed_frame(oracle, params, compute, gate):
             ref[m] = cae.forward(xm).cpu().numpy().reshape(-1)
         outs = []
         stream = torch.cuda.Stream(device=DEV)  # a capturable (non-null) stream
+        yd = torch.empty((ny,), device=DEV)     # one output buffer: reps 2 and 3 replay the graph
         torch.cuda.synchronize()
         for rep in range(3):
             with torch.cuda.stream(stream):
-                yd = torch.full((ny,), float("nan"), device=DEV)
+                yd.fill_(float("nan"))
                 B.drc_cae_plan_launch(plan, xd, yd, ws)      # captured once, then replayed
                 junk = torch.randn(1 << 20, device=DEV).sum()  # eager work between replays
             torch.cuda.synchronize()
@@ -66,6 +67,7 @@ def test_plan_mixed_frame(oracle, params, compute, gate):
                 np.testing.assert_array_equal(y[yo[m]:yo[m] + h * w * 3], ref[m], err_msg=f"rep {rep} map {m}")
             outs.append(y)
             del junk
+        assert B.drc_cae_plan_captures(plan) == 1
         # null stream: direct launches, same result
         yd = torch.zeros((ny,), device=DEV)
         B.drc_cae_plan_launch(plan, xd, yd, ws, stream=0)
@@ -172,3 +174,54 @@ def test_layer_e1_staged_matches_gather(params, compute):
     for m, (h, w) in enumerate(sizes):
         np.testing.assert_array_equal(ys[0][yo[m]:yo[m] + h * w * 3], ys[1][yo[m]:yo[m] + h * w * 3],
                                       err_msg=f"map {m} ({h}x{w})")
+
+
+def test_plan_recaptures_after_handle_changes(params):
+    """A plan's graph bakes in kernel arguments of the handle (FP8 scales, the
+    fused or layer route, tile shapes). After set_params with doubled weights
+    and a new FP8 calibration, or a switch of the route, the next launch on
+    the same buffers records the graph again and equals an eager forward."""
+    from paper_1910_02480_amd.cae import CAE
+    sizes = [(32, 32)] * 3 + [(64, 64)] * 2 + [(128, 128)]
+    x, xo, yo, ny = _frame(sizes)
+    maps = [(h, w, int(xo[m]), int(yo[m])) for m, (h, w) in enumerate(sizes)]
+    xd = torch.from_numpy(x).to(DEV)
+    calib = torch.from_numpy(synth.radiance_maps(8, 64, 64, seed=3)).to(DEV)
+    stream = torch.cuda.Stream(device=DEV)
+    for compute in ("fp8", "bf16"):
+        cae = CAE(compute, torch.from_numpy(params).to(DEV), device=DEV)
+        if compute == "fp8":
+            cae.calibrate_fp8(calib)
+        plan = B.drc_cae_plan_create(cae.h, maps)
+        try:
+            ws = torch.empty(B.drc_cae_plan_workspace_size(plan) + 256, dtype=torch.uint8, device=DEV)
+            ws = ws[(-ws.data_ptr()) % 256:]
+            yd = torch.empty((ny,), device=DEV)
+
+            def launch_and_compare(tag):
+                with torch.cuda.stream(stream):
+                    yd.fill_(float("nan"))
+                    B.drc_cae_plan_launch(plan, xd, yd, ws)
+                torch.cuda.synchronize()
+                y = yd.cpu().numpy()
+                for m, (h, w) in enumerate(sizes):
+                    xm = xd[xo[m]:xo[m] + h * w * 7].view(1, h, w, 7)
+                    ref = cae.forward(xm).cpu().numpy().reshape(-1)
+                    np.testing.assert_array_equal(y[yo[m]:yo[m] + h * w * 3], ref, err_msg=f"{tag} map {m}")
+                return y
+
+            y0 = launch_and_compare(f"{compute} first")
+            launch_and_compare(f"{compute} replay")
+            assert B.drc_cae_plan_captures(plan) == 1
+            cae.set_params(torch.from_numpy(2.0 * params).to(DEV))
+            if compute == "fp8":
+                cae.calibrate_fp8(calib)
+            y1 = launch_and_compare(f"{compute} new weights")
+            assert not np.array_equal(y0, y1)
+            if compute == "bf16":
+                cae.set_fused(False)
+                y2 = launch_and_compare("bf16 layer route")
+                np.testing.assert_array_equal(y1, y2)  # both routes agree bit for bit
+            assert B.drc_cae_plan_captures(plan) == (3 if compute == "bf16" else 2)
+        finally:
+            B.drc_cae_plan_destroy(plan)
