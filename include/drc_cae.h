@@ -268,6 +268,25 @@ void drc_cae_plan_destroy(drc_plan* p);
  * a replay does not record). Errors: DRC_ERR_INVALID_ARG for NULL. */
 drc_status drc_cae_plan_captures(const drc_plan* p, int64_t* count);
 
+/* Forward pass that allocates nothing and takes no workspace, for callers
+ * that cannot allocate device memory (code under HIP graph capture, serving
+ * loops or harnesses that forbid hipMalloc): the same computation, kernels
+ * and results as drc_cae_forward(h, d_x, d_y, n, H, W, NULL, ws, ...) (no
+ * saved activations), with the layer path's intermediate activations in a
+ * scratch array the library keeps in device memory, one per device, of
+ * drc_cae_static_scratch_bytes() bytes (64 MiB; held from the first
+ * drc_cae_create on that device until the process ends). The BF16
+ * whole-network route of 32x32 and 64x64 maps needs no scratch; other
+ * batches need drc_cae_workspace_size(DRC_WS_FORWARD) bytes of it.
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (nothing in it has to start at zero): calls that may overlap on
+ * one device, on different streams or from different threads, race and
+ * must be ordered by the caller. Errors: as drc_cae_forward, plus
+ * DRC_ERR_WORKSPACE when the batch needs more scratch than the array holds
+ * (split the batch, or call drc_cae_forward with a workspace). */
+size_t drc_cae_static_scratch_bytes(void);
+drc_status drc_cae_forward_static(drc_cae* h, const float* d_x, float* d_y, int n, int H, int W, void* stream);
+
 /* Sampling the predicted map R as an environment map (Sec. 3: the indirect
  * term alternates samples drawn from R, as from an environment map with
  * perfect visibility, with samples from the BRDF, combined by multiple

@@ -60,6 +60,8 @@ _SIGS = {
     "drc_cae_backward": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I, _VP, _SZ, _VP]),
     "drc_cae_step": (_I, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.POINTER(drc_adam_cfg), _VP, _VP,
                           _VP, _VP, _I, _I, _I, _VP, _SZ, _VP]),
+    "drc_cae_static_scratch_bytes": (_SZ, []),
+    "drc_cae_forward_static": (_I, [_VP, _VP, _VP, _I, _I, _I, _VP]),
     "drc_cae_calibrate_fp8": (_I, [_VP, _VP, _I, _I, _I, _VP, _SZ, _VP]),
     "drc_cae_get_fp8_scales": (_I, [_VP, ctypes.POINTER(ctypes.c_float), _VP]),
     "drc_cae_plan_create": (_I, [_VP, ctypes.POINTER(drc_map_desc), _I, ctypes.c_char_p,
@@ -203,6 +205,15 @@ def drc_cae_step(h, params, m, v, t, adam, x, target, loss, dparams=None, ws=Non
     _check(lib().drc_cae_step(h, _ptr(params), _ptr(m), _ptr(v), int(t), ctypes.byref(adam), _ptr(x),
                               _ptr(target), _ptr(loss), _ptr(dparams), n, H, W, _ptr(ws), _nbytes(ws),
                               _stream(stream)))
+
+
+def drc_cae_static_scratch_bytes():
+    return int(lib().drc_cae_static_scratch_bytes())
+
+
+def drc_cae_forward_static(h, x, y, stream=None):
+    n, H, W = _nhw(x, 7)
+    _check(lib().drc_cae_forward_static(h, _ptr(x), _ptr(y), n, H, W, _stream(stream)))
 
 
 def drc_cae_calibrate_fp8(h, x, ws=None, stream=None):

@@ -169,6 +169,11 @@ extern "C" drc_status drc_cae_create(const drc_cae_desc* desc, drc_cae** out) {
         return drc_fail(DRC_ERR_HIP, "create: device allocation failed");
     }
     for (int i = 0; i < 16; ++i) h->host_scales[i] = 1.0f;
+    const drc_status st = static_scratch_setup(h->device);
+    if (st != DRC_OK) {
+        drc_cae_destroy(h);
+        return st;
+    }
     *out = h;
     return DRC_OK;
 }

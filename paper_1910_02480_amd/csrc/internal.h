@@ -120,6 +120,9 @@ struct WgradPlan {
     int QR, NW;
 };
 WgradPlan wgrad_plan(int l, int n, int H, int W, int prec);
+// Device address of the file-scope scratch array of drc_cae_forward_static
+// on the current device (static_ws.hip); called once per device at create.
+drc_status static_scratch_setup(int device);
 void colsum_split(long npix, int* nblocks, long* per_block);
 BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed);
 StepLayout step_layout(int prec, int n, int H, int W, int recompute);
