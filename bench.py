@@ -202,8 +202,41 @@ def read_profile(B, h):
     return B.drc_cae_profile_read(h)
 
 
-def cpu_baseline(x_sample_fn, H, budget_s, len_x):
-    """FP64 oracle forward on the host, on a bounded sample of the workload."""
+def host_cpu():
+    """CPU model name, current clock (MHz) and logical CPUs of this host."""
+    model, mhz = "unknown", None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name") and model == "unknown":
+                model = line.split(":", 1)[1].strip()
+            if line.startswith("cpu MHz") and mhz is None:
+                mhz = float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    return {"model": model, "mhz": mhz, "logical_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+_SINGLE_CORE = """
+import sys, time
+sys.path.insert(0, {root!r})
+from oracle import oracle as O
+from paper_1910_02480_amd import synth
+p = synth.init_params(0)
+x = synth.radiance_maps({n}, {H}, {H})
+O.forward(p, x[:1])
+t0 = time.perf_counter()
+O.forward(p, x)
+print({n} / (time.perf_counter() - t0))
+"""
+
+
+def cpu_baseline(x_sample_fn, H, budget_s, len_x, train_maps):
+    """FP64 oracle on the host, on bounded samples of the workloads: the
+    forward over a prefix of the benchmark batch (about budget_s of work),
+    the training step (forward, L1 loss and gradient, backward, Adam) over
+    the training batch, and the forward on one core."""
+    import subprocess
     import numpy as np
     from oracle import oracle as O
     from paper_1910_02480_amd import synth
@@ -216,7 +249,7 @@ def cpu_baseline(x_sample_fn, H, budget_s, len_x):
     n = int(max(1, min(len_x, budget_s / max(t1, 1e-3))))
     xs = x_sample_fn(n)
     t0 = time.perf_counter()
-    acts = O.forward(params, xs)
+    O.forward(params, xs)
     passes = 1
     # the whole batch may take less than the budget on many cores: repeat it
     while time.perf_counter() - t0 < 0.5 * budget_s and passes < 16:
@@ -224,9 +257,50 @@ def cpu_baseline(x_sample_fn, H, budget_s, len_x):
         passes += 1
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
-    return {"value": n * passes / dt, "unit": "maps/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle forward of maps 0..{n - 1} of the {H}x{H} workload, {passes} pass(es) "
-                      f"({dt:.1f} s, {threads} OpenMP threads)"}, acts["y"], n
+    out = {"value": n * passes / dt, "unit": "maps/s", "cores": threads, "kind": "oracle",
+           "sample": f"FP64 oracle forward of maps 0..{n - 1} of the {H}x{H} workload, {passes} pass(es) "
+                     f"({dt:.1f} s, {threads} OpenMP threads)", "host": host_cpu()}
+    # training step of the training batch (the oracle's plain Adam in float64)
+    xt, tg = synth.training_batch(train_maps, H)
+    t0 = time.perf_counter()
+    a = O.forward(params, xt)
+    loss, dy = O.l1(a["y"], tg)
+    g, _ = O.backward(params, xt, a, dy)
+    O.adam(params, np.zeros_like(params), np.zeros_like(params), g, 1)
+    ts = time.perf_counter() - t0
+    out["train_step"] = {"maps": train_maps, "s_per_step": ts, "maps_per_s": train_maps / ts,
+                         "sample": f"one FP64 oracle training step (forward, L1, backward, Adam) on the "
+                                   f"{train_maps}-map {H}x{H} training batch, {threads} OpenMP threads"}
+    # one core: a child process with one OpenMP thread
+    n1 = max(1, min(64, int(round(2.0 / max(t1, 1e-3)))))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    root = os.path.dirname(os.path.abspath(__file__))
+    r = subprocess.run([sys.executable, "-c", _SINGLE_CORE.format(root=root, n=n1, H=H)], env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode == 0:
+        out["single_core"] = {"maps_per_s": float(r.stdout.strip().splitlines()[-1]), "maps": n1,
+                              "sample": f"FP64 oracle forward of maps 0..{n1 - 1}, OMP_NUM_THREADS=1"}
+    return out
+
+
+def accuracy(outputs, x_host, params_np, k):
+    """C16 error metrics of each precision's outputs over maps 0..k-1 of the
+    benchmark batch against the FP64 oracle: per map max_rel = max|y - r| /
+    max|r| and mean_rel = sum|y - r| / sum|r|; reported as max, mean and
+    p99 over the maps."""
+    import numpy as np
+    from oracle import oracle as O
+    ref = O.forward(params_np, x_host[:k].numpy())["y"].reshape(k, -1)
+    res = {"maps_checked": k, "subset": f"maps 0..{k - 1} of the benchmark batch"}
+    for name, y in outputs.items():
+        y = y[:k].reshape(k, -1).astype(np.float64)
+        d = np.abs(y - ref)
+        mx = d.max(1) / np.abs(ref).max(1)
+        mn = d.sum(1) / np.abs(ref).sum(1)
+        res[name] = {"max_rel_max": float(mx.max()), "max_rel_p99": float(np.percentile(mx, 99)),
+                     "max_rel_mean": float(mx.mean()), "mean_rel_mean": float(mn.mean()),
+                     "mean_rel_max": float(mn.max())}
+    return res
 
 
 def mixed_frame_leg(cae, tune_path, args):
@@ -350,7 +424,8 @@ def main():
     t = timed(fwd, args.steps, 0, do_settle=False)
     ms_l, calls_l = read_profile(B, cae.h)
     B.drc_cae_profile(cae.h, 0)
-    y_bf16 = y[:8].cpu().numpy()
+    ACC_MAPS = min(512, n)  # maps checked against the oracle
+    y_bf16 = y[:ACC_MAPS].cpu().numpy()
     value = n / t
     kernels = []
     tot_ms = max(sum(ms_l[:6]) + ms_l[FUSED_SLOT], 1e-30)
@@ -384,6 +459,12 @@ def main():
     traffic = None
     if tr and dom["kernel"] in tr["kernels"]:
         traffic = tr["kernels"][dom["kernel"]]["bytes_per_launch"]
+    # rocprof MFMA-busy fraction (padding lanes counted) and LDS bank-conflict
+    # share of the same kernel, from the committed SQ counter runs while fresh
+    sq = prof_summary.read_counters(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                                 f"cae_forward_bf16_{n}x{H}x{H}_counters.md"))
+    sqk = sq["kernels"].get(dom["kernel"], {}) if sq else {}
+    roof.update({"mfma_busy_rocprof": sqk.get("mfma_busy"), "lds_bank_conflict_share": sqk.get("lds_conflict")})
     roof.update({"kernel": dom["kernel"], "traffic": traffic, "traffic_unit": "bytes per launch",
                  "avg_ms": dom["avg_ms"],
                  "alg_bytes_per_launch": dom["alg_bytes"], "alg_flops_per_launch": dom["alg_flops"]})
@@ -423,9 +504,9 @@ def main():
             legs[f"{comp}_fwd"] = {"maps_per_s": n / tt, "ms": tt * 1e3,
                                    "mfma_frac_flop_based": total_flops / tt / (PEAK_TFLOPS[comp] * 1e12)}
             if comp == "f32":
-                y_f32 = y[:8].cpu().numpy()
+                y_f32 = y[:ACC_MAPS].cpu().numpy()
             if comp == "fp8":
-                y_fp8 = y[:8].cpu().numpy()
+                y_fp8 = y[:ACC_MAPS].cpu().numpy()
             log(f"{comp} forward: {n / tt:,.0f} maps/s")
             del c, w
         # ---------------- forward + backward (activations saved, no optimizer)
@@ -510,18 +591,16 @@ def main():
 
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
-        cb, y_ref, ns = cpu_baseline(lambda k: x_host[:k].numpy(), H, args.cpu_seconds, n)
+        cb = cpu_baseline(lambda k: x_host[:k].numpy(), H, args.cpu_seconds, n, args.train_maps)
         out["cpu_baseline"] = cb
-        k = min(ns, 8)
-        def mr(yg):
-            a = np.abs(yg[:k] - y_ref[:k]).reshape(k, -1).max(1)
-            return float((a / np.abs(y_ref[:k]).reshape(k, -1).max(1)).max())
-        acc = {"bf16_max_rel": mr(y_bf16), "maps_checked": k}
+        outs = {"bf16": y_bf16}
         if not args.main_only:
-            acc["f32_max_rel"] = mr(y_f32)
-            acc["fp8_max_rel"] = mr(y_fp8)
+            outs.update({"f32": y_f32, "fp8": y_fp8})
+        acc = accuracy(outs, x_host, synth.init_params(0), ACC_MAPS)
         out["accuracy_vs_fp64_oracle"] = acc
-        log(f"oracle: {cb['value']:.2f} maps/s on {cb['cores']} threads; accuracy {acc}")
+        log(f"oracle: {cb['value']:.2f} maps/s on {cb['cores']} threads; accuracy "
+            + ", ".join(f"{k} max_rel {v['max_rel_max']:.2e} mean_rel {v['mean_rel_mean']:.2e}"
+                        for k, v in acc.items() if isinstance(v, dict)))
     print(json.dumps(out), flush=True)
 
 

@@ -3,6 +3,8 @@
     python -m paper_1910_02480_amd.prof_summary stats <run_kernel_stats.csv> --cmd "..." --out X.md
     python -m paper_1910_02480_amd.prof_summary traffic <fetch counter csv> <write counter csv> \
         --cmd "..." --out X.md
+    python -m paper_1910_02480_amd.prof_summary counters <pass1 csv> <pass2 csv> --agent <agent csv> \
+        --cmd "..." --cmd "..." --out X.md
 
 `stats` turns a `--kernel-trace --stats` kernel table into a markdown table
 with the layer each kernel instantiation serves. `traffic` turns two `--pmc`
@@ -178,6 +180,73 @@ def traffic(fetch_csv: str, write_csv: str, cmd_fetch: str, cmd_write: str, titl
     return "\n".join(out)
 
 
+def _agent(info_csv: str):
+    """(XCDs, SIMDs, CUs) of the GPU from rocprofv3's agent table."""
+    for r in csv.DictReader(open(info_csv)):
+        if r.get("Agent_Type") == "GPU":
+            return int(r["Num_Xcc"]), int(r["Simd_Count"]), int(r["Cu_Count"])
+    raise SystemExit(f"no GPU agent in {info_csv}")
+
+
+def counters(csv_paths, info_csv: str, cmds, title: str) -> str:
+    """SQ counters per dispatch of each labelled kernel (one or more --pmc
+    passes), and the derived figures:
+      mfma_busy   = sum over SIMDs of SQ_VALU_MFMA_BUSY_CYCLES / (cycles x SIMDs),
+                    cycles = GRBM_GUI_ACTIVE / XCDs (the counter sums the XCDs);
+      mfma_flops  = SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512 (FLOPs the MFMAs executed,
+                    padding lanes included);
+      lds_conflict = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE (share of the
+                    LDS's active cycles stalled by bank conflicts)."""
+    nx, simds, cus = _agent(info_csv)
+    vals = collections.defaultdict(dict)
+    names = {}
+    for path in csv_paths:
+        acc = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            lab = label(r["Kernel_Name"])
+            if lab:
+                acc[(lab, r["Counter_Name"])].append(float(r["Counter_Value"]))
+                names.setdefault(lab, collections.Counter())[r["Kernel_Name"]] += 1
+        for (lab, c), v in acc.items():
+            vals[lab][c] = sum(v) / len(v)
+    kernels = {}
+    for lab, v in vals.items():
+        d = {"name": names[lab].most_common(1)[0][0], "counters": v, "source_hash": source_hash(lab)}
+        for grbm in ("GRBM_GUI_ACTIVE",):
+            if grbm in v:
+                cyc = v[grbm] / nx
+                d["cycles"] = cyc
+                if "SQ_VALU_MFMA_BUSY_CYCLES" in v:
+                    d["mfma_busy"] = v["SQ_VALU_MFMA_BUSY_CYCLES"] / (cyc * simds)
+        if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in v:
+            d["mfma_flops"] = v["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512.0
+        if "SQ_LDS_IDX_ACTIVE" in v and "SQ_LDS_BANK_CONFLICT" in v and v["SQ_LDS_IDX_ACTIVE"] > 0:
+            d["lds_conflict"] = v["SQ_LDS_BANK_CONFLICT"] / v["SQ_LDS_IDX_ACTIVE"]
+        kernels[lab] = d
+    doc = {"source_hash": source_hash(), "xcds": nx, "simds": simds, "cus": cus, "kernels": kernels}
+    out = [f"# {title}", "", "Commands (run from /tmp with TMPDIR=/tmp; $R = repository root):", ""]
+    out += [f"    {c}" for c in cmds]
+    out += ["", f"GPU: {cus} CUs, {simds} SIMDs, {nx} XCDs. Values are per dispatch (mean over the dispatches "
+                "of the kernel). mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / XCDs x SIMDs); "
+                "lds_conflict = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE. "
+                f"Source hash of the kernels: `{doc['source_hash']}`.", ""]
+    allc = sorted({c for d in kernels.values() for c in d["counters"]})
+    out.append("| Kernel | Serves | " + " | ".join(allc) + " | mfma_busy | lds_conflict |")
+    out.append("|---|---|" + "--:|" * (len(allc) + 2))
+    for lab, d in sorted(kernels.items()):
+        cells = [f"{d['counters'][c]:.4g}" if c in d["counters"] else "" for c in allc]
+        mb = f"{100 * d['mfma_busy']:.1f} %" if "mfma_busy" in d else ""
+        lc = f"{100 * d['lds_conflict']:.1f} %" if "lds_conflict" in d else ""
+        out.append(f"| `{_short(d['name'], 60)}` | {lab} | " + " | ".join(cells) + f" | {mb} | {lc} |")
+    out += ["", "Machine-readable copy:", "", "```json", json.dumps(doc, indent=1), "```", ""]
+    return "\n".join(out)
+
+
+def read_counters(md_path: str):
+    """The json block of a counter summary without its stale kernels (or None)."""
+    return read_traffic(md_path)
+
+
 def read_traffic(md_path: str):
     """The json block of a traffic summary without its stale kernels, or None
     when absent or when every kernel is stale."""
@@ -211,9 +280,17 @@ def main():
     t.add_argument("--cmd-write", required=True)
     t.add_argument("--title", default="HBM traffic")
     t.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csv", nargs="+", help="counter_collection.csv of each --pmc pass")
+    c.add_argument("--agent", required=True, help="agent_info.csv of one of the passes")
+    c.add_argument("--cmd", action="append", required=True, help="the command of each pass")
+    c.add_argument("--title", default="SQ counters")
+    c.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd_name == "stats":
         text = stats(a.csv, a.cmd, a.title, a.top)
+    elif a.cmd_name == "counters":
+        text = counters(a.csv, a.agent, a.cmd, a.title)
     else:
         text = traffic(a.fetch_csv, a.write_csv, a.cmd_fetch, a.cmd_write, a.title)
     with open(a.out, "w") as fh:
