@@ -218,6 +218,30 @@ drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, float* d_v, int
                         float* d_loss, float* d_dparams, int n, int H, int W, void* d_ws,
                         size_t ws_bytes, void* stream);
 
+/* The training step of drc_cae_step recorded once as a HIP graph and
+ * replayed, for training loops whose steps are short enough that launching
+ * the step's kernels one by one costs a noticeable share of the step (the
+ * paper trains with small batches, Sec. 5). create checks its arguments as
+ * drc_cae_step does (same buffers, layout and errors; t is given per launch)
+ * and records the step on the given non-null stream (it allocates the
+ * graph). launch replays it on that stream for step count t (>= 1): every
+ * buffer, pointer and shape is the one given to create, and the results are
+ * bitwise those of drc_cae_step(..., t, ...) on the same state. If a call
+ * has changed the handle since the recording (set_params from another
+ * buffer, set_fused, set_recompute does not count), launch records the step
+ * again first. Errors: create as drc_cae_step, DRC_ERR_INVALID_ARG for a
+ * NULL out or the null stream, DRC_ERR_HIP if the recording fails; launch:
+ * DRC_ERR_INVALID_ARG for NULL or t < 1, DRC_ERR_STATE on another device.
+ * captures reports how often the step was recorded. The graph must be
+ * destroyed before its handle. */
+typedef struct drc_step_graph drc_step_graph;
+drc_status drc_cae_step_graph_create(drc_cae* h, float* d_params, float* d_m, float* d_v, const drc_adam_cfg* adam,
+                                     const float* d_x, const float* d_target, float* d_loss, float* d_dparams, int n,
+                                     int H, int W, void* d_ws, size_t ws_bytes, void* stream, drc_step_graph** out);
+drc_status drc_cae_step_graph_launch(drc_step_graph* g, int64_t t);
+drc_status drc_cae_step_graph_captures(const drc_step_graph* g, int64_t* count);
+void drc_cae_step_graph_destroy(drc_step_graph* g);
+
 /* FP8 handles: static per-tensor activation scales (448 / max |value|) from
  * a float32 forward over the calibration batch d_x. Must follow set_params.
  * The scales of x, [u2|h1], [u3|h2] and h3 are kept in the handle. This is

@@ -62,6 +62,11 @@ _SIGS = {
                           _VP, _VP, _I, _I, _I, _VP, _SZ, _VP]),
     "drc_cae_static_scratch_bytes": (_SZ, []),
     "drc_cae_forward_static": (_I, [_VP, _VP, _VP, _I, _I, _I, _VP]),
+    "drc_cae_step_graph_create": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(drc_adam_cfg), _VP, _VP, _VP, _VP,
+                                       _I, _I, _I, _VP, _SZ, _VP, ctypes.POINTER(_VP)]),
+    "drc_cae_step_graph_launch": (_I, [_VP, ctypes.c_int64]),
+    "drc_cae_step_graph_captures": (_I, [_VP, ctypes.POINTER(ctypes.c_int64)]),
+    "drc_cae_step_graph_destroy": (None, [_VP]),
     "drc_cae_calibrate_fp8": (_I, [_VP, _VP, _I, _I, _I, _VP, _SZ, _VP]),
     "drc_cae_get_fp8_scales": (_I, [_VP, ctypes.POINTER(ctypes.c_float), _VP]),
     "drc_cae_plan_create": (_I, [_VP, ctypes.POINTER(drc_map_desc), _I, ctypes.c_char_p,
@@ -214,6 +219,30 @@ def drc_cae_static_scratch_bytes():
 def drc_cae_forward_static(h, x, y, stream=None):
     n, H, W = _nhw(x, 7)
     _check(lib().drc_cae_forward_static(h, _ptr(x), _ptr(y), n, H, W, _stream(stream)))
+
+
+def drc_cae_step_graph_create(h, params, m, v, adam, x, target, loss, dparams=None, ws=None, stream=None):
+    """Record one training step as a graph on a non-null stream."""
+    n, H, W = _nhw(x, 7)
+    g = _VP()
+    _check(lib().drc_cae_step_graph_create(h, _ptr(params), _ptr(m), _ptr(v), ctypes.byref(adam), _ptr(x),
+                                           _ptr(target), _ptr(loss), _ptr(dparams), n, H, W, _ptr(ws), _nbytes(ws),
+                                           _stream(stream), ctypes.byref(g)))
+    return g.value
+
+
+def drc_cae_step_graph_launch(g, t):
+    _check(lib().drc_cae_step_graph_launch(g, int(t)))
+
+
+def drc_cae_step_graph_captures(g):
+    c = ctypes.c_int64()
+    _check(lib().drc_cae_step_graph_captures(g, ctypes.byref(c)))
+    return int(c.value)
+
+
+def drc_cae_step_graph_destroy(g):
+    lib().drc_cae_step_graph_destroy(g)
 
 
 def drc_cae_calibrate_fp8(h, x, ws=None, stream=None):

@@ -132,6 +132,42 @@ class Trainer:
         return self.loss
 
 
+class GraphTrainer(Trainer):
+    """Trainer whose step is recorded once as a HIP graph on its own stream
+    (drc_cae_step_graph_*) and replayed; the batch tensors are fixed at the
+    first step (fill them in place for the next batch)."""
+
+    def __init__(self, cae: CAE, params: torch.Tensor, **kw):
+        super().__init__(cae, params, **kw)
+        self.stream = torch.cuda.Stream(device=params.device)
+        self.g = None
+        self._key = None
+
+    def step(self, x, target, dparams=None):
+        n, H, W, _ = x.shape
+        key = (x.data_ptr(), target.data_ptr(), None if dparams is None else dparams.data_ptr(), n, H, W)
+        if self.g is None or key != self._key:
+            self.close()
+            ws = self.cae.workspace(n, H, W, B.DRC_WS_STEP)
+            self.stream.wait_stream(torch.cuda.current_stream(self.params.device))
+            self.g = B.drc_cae_step_graph_create(self.cae.h, self.params, self.m, self.v, self.adam, x, target,
+                                                 self.loss, dparams, ws, stream=self.stream)
+            self._key = key
+        self.t += 1
+        self.stream.wait_stream(torch.cuda.current_stream(self.params.device))
+        B.drc_cae_step_graph_launch(self.g, self.t)
+        torch.cuda.current_stream(self.params.device).wait_stream(self.stream)
+        return self.loss
+
+    def close(self):
+        if self.g is not None:
+            B.drc_cae_step_graph_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        self.close()
+
+
 class CAEFunction(torch.autograd.Function):
     """y = CAE(x; params) with the library's forward and backward kernels.
 

@@ -704,33 +704,50 @@ extern "C" drc_status drc_cae_backward(drc_cae* h, const float* d_x, const float
 }
 
 // ------------------------------------------------------------------ training step
-extern "C" drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, float* d_v, int64_t t,
-                                   const drc_adam_cfg* adam, const float* d_x, const float* d_target,
-                                   float* d_loss, float* d_dparams, int n, int H, int W, void* d_ws,
-                                   size_t ws_bytes, void* stream) {
-    if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "step: handle is NULL");
-    if (h->prec == P_FP8) return drc_fail(DRC_ERR_UNSUPPORTED, "step: FP8 handles are inference only");
-    if (h->desc.final_relu) return drc_fail(DRC_ERR_UNSUPPORTED, "step: final_relu = 1 is inference only");
-    TRY(check_shape("step", n, H, W));
-    TRY(check_ptr("step", "d_params", d_params, 16, false));
-    TRY(check_ptr("step", "d_m", d_m, 16, false));
-    TRY(check_ptr("step", "d_v", d_v, 16, false));
-    TRY(check_ptr("step", "d_x", d_x, 16, false));
-    TRY(check_ptr("step", "d_target", d_target, 16, false));
-    TRY(check_ptr("step", "d_loss", d_loss, 4, false));
-    TRY(check_ptr("step", "d_dparams", d_dparams, 16, true));
-    TRY(check_ptr("step", "d_ws", d_ws, 256, false));
-    if (!adam) return drc_fail(DRC_ERR_INVALID_ARG, "step: adam is NULL");
-    if (t < 1) return drc_fail(DRC_ERR_INVALID_ARG, "step: t = %lld (must be >= 1)", (long long)t);
+// Host-side checks of a training step (nothing is enqueued).
+static drc_status check_step(drc_cae* h, const float* d_params, const float* d_m, const float* d_v,
+                             const drc_adam_cfg* adam, const float* d_x, const float* d_target, const float* d_loss,
+                             const float* d_dparams, int n, int H, int W, const void* d_ws, size_t ws_bytes,
+                             const char* who) {
+    if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "%s: handle is NULL", who);
+    if (h->prec == P_FP8) return drc_fail(DRC_ERR_UNSUPPORTED, "%s: FP8 handles are inference only", who);
+    if (h->desc.final_relu) return drc_fail(DRC_ERR_UNSUPPORTED, "%s: final_relu = 1 is inference only", who);
+    TRY(check_shape(who, n, H, W));
+    TRY(check_ptr(who, "d_params", d_params, 16, false));
+    TRY(check_ptr(who, "d_m", d_m, 16, false));
+    TRY(check_ptr(who, "d_v", d_v, 16, false));
+    TRY(check_ptr(who, "d_x", d_x, 16, false));
+    TRY(check_ptr(who, "d_target", d_target, 16, false));
+    TRY(check_ptr(who, "d_loss", d_loss, 4, false));
+    TRY(check_ptr(who, "d_dparams", d_dparams, 16, true));
+    TRY(check_ptr(who, "d_ws", d_ws, 256, false));
+    if (!adam) return drc_fail(DRC_ERR_INVALID_ARG, "%s: adam is NULL", who);
     if (!(adam->lr > 0) || !(adam->beta1 >= 0 && adam->beta1 < 1) || !(adam->beta2 >= 0 && adam->beta2 < 1) ||
         !(adam->eps >= 0))
-        return drc_fail(DRC_ERR_INVALID_ARG, "step: bad Adam hyper-parameters");
+        return drc_fail(DRC_ERR_INVALID_ARG, "%s: bad Adam hyper-parameters", who);
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != h->device)
-        return drc_fail(DRC_ERR_STATE, "step: current device is not the handle's device");
+        return drc_fail(DRC_ERR_STATE, "%s: current device is not the handle's device", who);
     const StepLayout S = step_layout(h->prec, n, H, W, h->recompute);
     if (ws_bytes < S.total)
-        return drc_fail(DRC_ERR_WORKSPACE, "step: workspace %zu < %zu bytes", ws_bytes, S.total);
+        return drc_fail(DRC_ERR_WORKSPACE, "%s: workspace %zu < %zu bytes", who, ws_bytes, S.total);
+    return DRC_OK;
+}
+
+// Adam's step-dependent factors, formed in double precision as PyTorch does
+// and rounded once to float32: lr / (1 - beta1^t) and 1 / sqrt(1 - beta2^t).
+static void adam_factors(const drc_adam_cfg* adam, int64_t t, float* step_size, float* inv_sqrt_bc2) {
+    const double bc1 = 1.0 - std::pow(adam->beta1, (double)t);
+    const double bc2 = 1.0 - std::pow(adam->beta2, (double)t);
+    *step_size = (float)(adam->lr / bc1);
+    *inv_sqrt_bc2 = (float)(1.0 / std::sqrt(bc2));
+}
+
+// Enqueue one training step (arguments already checked).
+static drc_status step_enqueue(drc_cae* h, float* d_params, float* d_m, float* d_v, int64_t t,
+                               const drc_adam_cfg* adam, const float* d_x, const float* d_target, float* d_loss,
+                               float* d_dparams, int n, int H, int W, void* d_ws, void* stream) {
+    const StepLayout S = step_layout(h->prec, n, H, W, h->recompute);
     hipStream_t s = (hipStream_t)stream;
     char* ws = (char*)d_ws;
 
@@ -791,18 +808,193 @@ extern "C" drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, floa
     TRY(backward_dispatch(h, b, n, H, W, (float)(1.0 / (double)M), s));
 
     // Adam (PyTorch form), then repack the weights from the new masters.
-    const double bc1 = 1.0 - std::pow(adam->beta1, (double)t);
-    const double bc2 = 1.0 - std::pow(adam->beta2, (double)t);
+    float step_size, inv_sqrt_bc2;
+    adam_factors(adam, t, &step_size, &inv_sqrt_bc2);
     const long P = (long)drc_cae_num_params(h);
     const long atok = prof_begin(h, PROF_ADAM, s);
     hipLaunchKernelGGL(adam_kernel, dim3((int)((P + 255) / 256)), dim3(256), 0, s, d_params, d_m, d_v,
                        (const float*)b.dparams, P, (float)adam->beta1, (float)(1.0 - adam->beta1),
-                       (float)adam->beta2, (float)(1.0 - adam->beta2), (float)(adam->lr / bc1),
-                       (float)(1.0 / std::sqrt(bc2)), (float)adam->eps);
+                       (float)adam->beta2, (float)(1.0 - adam->beta2), step_size, inv_sqrt_bc2,
+                       (float)adam->eps);
     TRY(check_launch("step/adam"));
     const drc_status st = drc_cae_set_params(h, d_params, stream);
     prof_end(h, atok, s);
     return st;
+}
+
+extern "C" drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, float* d_v, int64_t t,
+                                   const drc_adam_cfg* adam, const float* d_x, const float* d_target,
+                                   float* d_loss, float* d_dparams, int n, int H, int W, void* d_ws,
+                                   size_t ws_bytes, void* stream) {
+    TRY(check_step(h, d_params, d_m, d_v, adam, d_x, d_target, d_loss, d_dparams, n, H, W, d_ws, ws_bytes,
+                   "step"));
+    if (t < 1) return drc_fail(DRC_ERR_INVALID_ARG, "step: t = %lld (must be >= 1)", (long long)t);
+    return step_enqueue(h, d_params, d_m, d_v, t, adam, d_x, d_target, d_loss, d_dparams, n, H, W, d_ws, stream);
+}
+
+// ------------------------------------------------------------------ captured training step
+// One training step recorded once as a HIP graph and replayed per step. The
+// only argument that changes from step to step, the step count t, enters
+// through Adam's two bias-correction factors: the replay rewrites the
+// arguments of the graph's Adam kernel node (same values as drc_cae_step
+// computes), so a replayed step is the eager step bit for bit.
+struct drc_step_graph {
+    drc_cae* h = nullptr;
+    float *params = nullptr, *m = nullptr, *v = nullptr, *loss = nullptr, *dparams = nullptr;
+    const float *x = nullptr, *target = nullptr;
+    drc_adam_cfg adam{};
+    int n = 0, H = 0, W = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t adam_node = nullptr;
+    hipKernelNodeParams adam_params{};
+    // the Adam node's arguments, in adam_kernel's parameter order, owned here
+    struct {
+        float* theta;
+        float* m;
+        float* v;
+        const float* g;
+        long count;
+        float b1, omb1, b2, omb2, step_size, inv_sqrt_bc2, eps;
+    } adam_args{};
+    void* adam_argv[12] = {};
+    unsigned long gen = 0;  // handle generation the graph was recorded at
+    long captures = 0;
+};
+
+static void step_graph_release(drc_step_graph* g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    g->exec = nullptr;
+    g->graph = nullptr;
+    g->adam_node = nullptr;
+}
+
+// Record the step on g->stream and find the Adam kernel node.
+static drc_status step_graph_record(drc_step_graph* g) {
+    step_graph_release(g);
+    drc_cae* h = g->h;
+    const bool prof = h->prof;
+    h->prof = false;  // no timing events inside the graph
+    HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+    const drc_status st = step_enqueue(h, g->params, g->m, g->v, 1, &g->adam, g->x, g->target, g->loss,
+                                       g->dparams, g->n, g->H, g->W, g->ws, g->stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(g->stream, &graph);
+    h->prof = prof;
+    if (st != DRC_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return drc_fail(DRC_ERR_HIP, "step_graph: capture failed: %s", hipGetErrorString(e));
+    g->graph = graph;
+    size_t nn = 0;
+    HIPCHK(hipGraphGetNodes(graph, nullptr, &nn));
+    std::vector<hipGraphNode_t> nodes(nn);
+    HIPCHK(hipGraphGetNodes(graph, nodes.data(), &nn));
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp;
+        if (hipGraphKernelNodeGetParams(nd, &kp) != hipSuccess) continue;
+        if (kp.func == reinterpret_cast<void*>(&adam_kernel)) {
+            if (g->adam_node) return drc_fail(DRC_ERR_HIP, "step_graph: two Adam nodes in the recorded step");
+            if (!kp.kernelParams) return drc_fail(DRC_ERR_HIP, "step_graph: Adam node without arguments");
+            g->adam_node = nd;
+            auto& A = g->adam_args;
+            void** in = kp.kernelParams;
+            A.theta = *(float**)in[0];
+            A.m = *(float**)in[1];
+            A.v = *(float**)in[2];
+            A.g = *(const float**)in[3];
+            A.count = *(long*)in[4];
+            float* fl[7] = {&A.b1, &A.omb1, &A.b2, &A.omb2, &A.step_size, &A.inv_sqrt_bc2, &A.eps};
+            for (int i = 0; i < 7; ++i) *fl[i] = *(float*)in[5 + i];
+            void* argv[12] = {&A.theta, &A.m, &A.v, &A.g, &A.count, &A.b1, &A.omb1, &A.b2, &A.omb2,
+                              &A.step_size, &A.inv_sqrt_bc2, &A.eps};
+            memcpy(g->adam_argv, argv, sizeof argv);
+            g->adam_params = kp;
+            g->adam_params.kernelParams = g->adam_argv;
+            g->adam_params.extra = nullptr;
+        }
+    }
+    if (!g->adam_node) return drc_fail(DRC_ERR_HIP, "step_graph: the recorded step has no Adam node");
+    if (g->adam_args.theta != g->params || g->adam_args.m != g->m || g->adam_args.v != g->v)
+        return drc_fail(DRC_ERR_HIP, "step_graph: unexpected Adam node arguments");
+    HIPCHK(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0));
+    g->gen = h->gen;
+    g->captures++;
+    return DRC_OK;
+}
+
+extern "C" drc_status drc_cae_step_graph_create(drc_cae* h, float* d_params, float* d_m, float* d_v,
+                                                const drc_adam_cfg* adam, const float* d_x, const float* d_target,
+                                                float* d_loss, float* d_dparams, int n, int H, int W, void* d_ws,
+                                                size_t ws_bytes, void* stream, drc_step_graph** out) {
+    if (!out) return drc_fail(DRC_ERR_INVALID_ARG, "step_graph_create: out is NULL");
+    *out = nullptr;
+    TRY(check_step(h, d_params, d_m, d_v, adam, d_x, d_target, d_loss, d_dparams, n, H, W, d_ws, ws_bytes,
+                   "step_graph_create"));
+    if (!stream) return drc_fail(DRC_ERR_INVALID_ARG, "step_graph_create: the null stream cannot be captured");
+    drc_step_graph* g = new drc_step_graph();
+    g->h = h;
+    g->params = d_params;
+    g->m = d_m;
+    g->v = d_v;
+    g->adam = *adam;
+    g->x = d_x;
+    g->target = d_target;
+    g->loss = d_loss;
+    g->dparams = d_dparams;
+    g->n = n;
+    g->H = H;
+    g->W = W;
+    g->ws = d_ws;
+    g->ws_bytes = ws_bytes;
+    g->stream = (hipStream_t)stream;
+    const drc_status st = step_graph_record(g);
+    if (st != DRC_OK) {
+        drc_cae_step_graph_destroy(g);
+        return st;
+    }
+    *out = g;
+    return DRC_OK;
+}
+
+extern "C" drc_status drc_cae_step_graph_launch(drc_step_graph* g, int64_t t) {
+    if (!g) return drc_fail(DRC_ERR_INVALID_ARG, "step_graph_launch: graph is NULL");
+    if (t < 1) return drc_fail(DRC_ERR_INVALID_ARG, "step_graph_launch: t = %lld (must be >= 1)", (long long)t);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != g->h->device)
+        return drc_fail(DRC_ERR_STATE, "step_graph_launch: current device is not the handle's device");
+    // a call that changed the handle since the recording (set_params from
+    // another buffer, set_fused, ...) changes what the step enqueues
+    if (g->h->gen != g->gen) TRY(step_graph_record(g));
+    float step_size, inv_sqrt_bc2;
+    adam_factors(&g->adam, t, &step_size, &inv_sqrt_bc2);
+    g->adam_args.step_size = step_size;
+    g->adam_args.inv_sqrt_bc2 = inv_sqrt_bc2;
+    HIPCHK(hipGraphExecKernelNodeSetParams(g->exec, g->adam_node, &g->adam_params));
+    HIPCHK(hipGraphLaunch(g->exec, g->stream));
+    // the step leaves the handle packed from d_params, as drc_cae_step does
+    g->h->params_set = true;
+    g->h->packed_from = g->params;
+    return DRC_OK;
+}
+
+extern "C" drc_status drc_cae_step_graph_captures(const drc_step_graph* g, int64_t* count) {
+    if (!g || !count) return drc_fail(DRC_ERR_INVALID_ARG, "step_graph_captures: NULL argument");
+    *count = g->captures;
+    return DRC_OK;
+}
+
+extern "C" void drc_cae_step_graph_destroy(drc_step_graph* g) {
+    if (!g) return;
+    step_graph_release(g);
+    delete g;
 }
 
 // ------------------------------------------------------------------ FP8 calibration
