@@ -558,6 +558,14 @@ def main():
             legs[f"{comp}_train_step"]["breakdown_ms"] = {names[k]: round(ms_s[k], 4) for k in range(23)
                                                           if calls_s[k]}
             log(f"{comp} train step (batch {nt}): {nt / tt:,.0f} maps/s, {tt * 1e3:.3f} ms")
+            # the same step recorded once as a HIP graph and replayed
+            from paper_1910_02480_amd.cae import GraphTrainer
+            gtr = GraphTrainer(CAE(comp, device=dev, recompute=True), params.clone())
+            tg_ = timed(lambda: gtr.step(xt, tg), args.steps, args.warmup)
+            gtr.close()
+            legs[f"{comp}_train_step"]["graph_ms"] = tg_ * 1e3
+            legs[f"{comp}_train_step"]["graph_maps_per_s"] = nt / tg_
+            log(f"{comp} train step as a replayed graph: {tg_ * 1e3:.3f} ms")
             if comp == "bf16":
                 # augmentation of the step's batch (rotations and mirrors), before the step
                 gen = torch.Generator(device=dev)

@@ -156,6 +156,50 @@ __device__ __forceinline__ void stage_x(char* smem, int xs, const float* xm) {
     }
 }
 
+// The next map's input, staged while the decoder runs. After D2 band b has
+// read them, rows [4b, 4b + 4) of h2 (region R1) and of u3 (region R2) are
+// dead; the x staging region R1 + R2 holds x row r at 16 W r bytes, so those
+// rows free x rows [8b, 8b + 8) and [H/2 + 8b, H/2 + 8b + 8). A piece is
+// those 16 rows; each thread carries a pair of pixels (56 bytes of float32)
+// from before D2 band b until its rows are free.
+struct XPiece {
+    float2 v[7];
+};
+template <int H, int W>
+__device__ __forceinline__ bool x_piece_pair(int band, int& row, int& col) {
+    constexpr int NPAIR = 8 * W;  // pixel pairs of a piece (16 rows of W)
+    const int t = opaque_tid();
+    const int q = 2 * t, r = q / W;
+    col = q % W;
+    row = r < 8 ? 8 * band + r : H / 2 + 8 * band + (r - 8);
+    return NPAIR % FT == 0 || t < NPAIR;
+}
+template <int H, int W>
+__device__ __forceinline__ void x_piece_load(XPiece& xp, const float* xm, int band) {
+    int row, col;
+    if (x_piece_pair<H, W>(band, row, col)) {
+        const float2* src = (const float2*)(xm + ((long)row * W + col) * 7);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) xp.v[k] = src[k];
+    }
+}
+template <int H, int W>
+__device__ __forceinline__ void x_piece_store(char* smem, int xs, const XPiece& xp, int band) {
+    int row, col;
+    if (x_piece_pair<H, W>(band, row, col)) {
+        const float* f = (const float*)xp.v;
+#pragma unroll
+        for (int px = 0; px < 2; ++px) {
+            uint4 o;
+            o.x = (uint32_t)bf16_bits(f[7 * px + 0]) | ((uint32_t)bf16_bits(f[7 * px + 1]) << 16);
+            o.y = (uint32_t)bf16_bits(f[7 * px + 2]) | ((uint32_t)bf16_bits(f[7 * px + 3]) << 16);
+            o.z = (uint32_t)bf16_bits(f[7 * px + 4]) | ((uint32_t)bf16_bits(f[7 * px + 5]) << 16);
+            o.w = (uint32_t)bf16_bits(f[7 * px + 6]);
+            *(uint4*)(smem + xs + (row * W + col + px) * 16) = o;
+        }
+    }
+}
+
 // Stride-2 3x3 convolution, LDS -> LDS, bias + ReLU (E1, E2, E3). Weights:
 // the layer pack [COUT][KSTEPS*32] (k = tap * CIN + c) in fragment order. Wave w owns the row blocks of group
 // w % TR for the whole layer and loads their weights (its A panel) into
@@ -580,11 +624,14 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
     constexpr long B1 = 16L * HW, B2 = 8L * HW, B3 = 4L * HW, B4 = 8L * HW, B5 = 16L * HW;
     static_assert((H / 4) % L::BAND == 0, "whole bands");
     if (threadIdx.x < kZeroBytes / 16) *(uint4*)(smem + ZO + 16 * threadIdx.x) = uint4{0u, 0u, 0u, 0u};
+    bool staged = false;  // x of map m already in LDS (staged during the previous map's decoder)
     for (int m = blockIdx.x; m < a.nmaps; m += gridDim.x) {
         if constexpr (!MID) {
             const float* xm = a.x + (a.x_off ? a.x_off[m] : (long)m * HW * 7);
             float* ym = a.y + (a.y_off ? a.y_off[m] : (long)m * HW * 3);
-            stage_x<H, W>(smem, R1, xm);
+            const int mn = m + gridDim.x;  // this workgroup's next map
+            const float* xn = mn < a.nmaps ? a.x + (a.x_off ? a.x_off[mn] : (long)mn * HW * 7) : nullptr;
+            if (!staged) stage_x<H, W>(smem, R1, xm);
             __syncthreads();
             conv_phase<H, W, 8, 32, 2, E1N>(smem, R1, ZO, a.w[0], a.b[0], LdsOut<32, W / 2>{smem, R0});
             __syncthreads();
@@ -608,9 +655,12 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
                 pairs_panel_load<32, 128, 1>(P2, a.w[4], a.b[4], tr, set);
                 D1Panel P1;
                 d1_panel_load(P1, a.w[5], a.b[5]);
+                static_assert(NBAND * 16 == H, "the x pieces of the bands cover the next map's input");
                 for (int band = 0; band < NBAND; ++band) {
                     const int pix0 = band * L::BAND * (W / 4);
                     const LdsOut<32, W / 2> ring{smem, R3};
+                    XPiece xp;
+                    if (xn) x_piece_load<H, W>(xp, xn, band);  // in flight during D2's MFMAs
                     if (set == 0)
                         pairs_tiles<H / 4, W / 4, 64, 64, 32, 1, D2BN, 0, D2BPB, L::RING>(
                             P2, smem, R2, R1, ZO, tr, wave / NG, FW / NG, pix0, ring);
@@ -618,6 +668,7 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
                         pairs_tiles<H / 4, W / 4, 64, 64, 32, 1, D2BN, 1, D2BPB, L::RING>(
                             P2, smem, R2, R1, ZO, tr, wave / NG, FW / NG, pix0, ring);
                     __syncthreads();
+                    if (xn) x_piece_store<H, W>(smem, R1, xp, band);
                     const int u0 = 2 * L::BAND * band;  // first u2 row of the band
                     if (a.save[4]) copy_rows_out<32, WU, L::RING>(a.save[4] + m * B5, smem, R3, u0, 2 * L::BAND);
                     // u2 rows [r0, r1): all rows of the band whose lower neighbour is
@@ -628,6 +679,7 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
                     __syncthreads();
                 }
             }
+            staged = xn != nullptr;
         } else {
             copy_in<64, H / 4, W / 4>(smem, R1, a.save[1] + m * B2);
             __syncthreads();
