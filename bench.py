@@ -561,7 +561,8 @@ def main():
             # the same step recorded once as a HIP graph and replayed
             from paper_1910_02480_amd.cae import GraphTrainer
             gtr = GraphTrainer(CAE(comp, device=dev, recompute=True), params.clone())
-            tg_ = timed(lambda: gtr.step(xt, tg), args.steps, args.warmup)
+            with torch.cuda.stream(torch.cuda.Stream(device=dev)):  # capture and replay on this stream
+                tg_ = timed(lambda: gtr.step(xt, tg), args.steps, args.warmup)
             gtr.close()
             legs[f"{comp}_train_step"]["graph_ms"] = tg_ * 1e3
             legs[f"{comp}_train_step"]["graph_maps_per_s"] = nt / tg_

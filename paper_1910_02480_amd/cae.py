@@ -139,24 +139,36 @@ class GraphTrainer(Trainer):
 
     def __init__(self, cae: CAE, params: torch.Tensor, **kw):
         super().__init__(cae, params, **kw)
-        self.stream = torch.cuda.Stream(device=params.device)
+        self._own = torch.cuda.Stream(device=params.device)
         self.g = None
         self._key = None
 
+    def _stream(self):
+        """The current stream if it can be captured (not the null stream),
+        else the trainer's own stream (joined to the current one per step)."""
+        cur = torch.cuda.current_stream(self.params.device)
+        return (cur, False) if cur.cuda_stream != 0 else (self._own, True)
+
     def step(self, x, target, dparams=None):
         n, H, W, _ = x.shape
-        key = (x.data_ptr(), target.data_ptr(), None if dparams is None else dparams.data_ptr(), n, H, W)
+        stream, join = self._stream()
+        key = (x.data_ptr(), target.data_ptr(), None if dparams is None else dparams.data_ptr(), n, H, W,
+               stream.cuda_stream)
+        cur = torch.cuda.current_stream(self.params.device)
         if self.g is None or key != self._key:
             self.close()
             ws = self.cae.workspace(n, H, W, B.DRC_WS_STEP)
-            self.stream.wait_stream(torch.cuda.current_stream(self.params.device))
+            if join:
+                stream.wait_stream(cur)
             self.g = B.drc_cae_step_graph_create(self.cae.h, self.params, self.m, self.v, self.adam, x, target,
-                                                 self.loss, dparams, ws, stream=self.stream)
+                                                 self.loss, dparams, ws, stream=stream)
             self._key = key
         self.t += 1
-        self.stream.wait_stream(torch.cuda.current_stream(self.params.device))
+        if join:
+            stream.wait_stream(cur)
         B.drc_cae_step_graph_launch(self.g, self.t)
-        torch.cuda.current_stream(self.params.device).wait_stream(self.stream)
+        if join:
+            cur.wait_stream(stream)
         return self.loss
 
     def close(self):

@@ -161,6 +161,10 @@ extern "C" drc_status drc_cae_create(const drc_cae_desc* desc, drc_cae** out) {
             ok = alloc(&h->wcal[l], (size_t)gc.nblk * gc.rows_pad * gc.kstride * 4);
         }
     }
+    for (int k = 0; k < drc_cae::kSide && ok; ++k)
+        ok = hipStreamCreateWithFlags(&h->side[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&h->ev_join[k], hipEventDisableTiming) == hipSuccess;
+    for (int l = 0; l < 6 && ok; ++l) ok = hipEventCreateWithFlags(&h->ev_fork[l], hipEventDisableTiming) == hipSuccess;
     ok = ok && alloc((void**)&h->bias, 512 * sizeof(float));
     ok = ok && alloc((void**)&h->scales, 16 * sizeof(float));
     ok = ok && alloc((void**)&h->amax, 16 * sizeof(unsigned));
@@ -181,6 +185,12 @@ extern "C" drc_status drc_cae_create(const drc_cae_desc* desc, drc_cae** out) {
 extern "C" void drc_cae_destroy(drc_cae* h) {
     if (!h) return;
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    for (int k = 0; k < drc_cae::kSide; ++k) {
+        if (h->side[k]) (void)hipStreamDestroy(h->side[k]);
+        if (h->ev_join[k]) (void)hipEventDestroy(h->ev_join[k]);
+    }
+    for (int l = 0; l < 6; ++l)
+        if (h->ev_fork[l]) (void)hipEventDestroy(h->ev_fork[l]);
     for (int l = 0; l < 6; ++l) {
         if (h->wf[l]) (void)hipFree(h->wf[l]);
         if (h->wb[l]) (void)hipFree(h->wb[l]);
@@ -492,9 +502,10 @@ BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed) {
     b.dz_h3 = cur; cur += align256(a.p3 * 128 * es);
     b.dz_h2 = cur; cur += align256(a.p2 * 64 * es);
     b.dz_h1 = cur; cur += align256(a.p1 * 32 * es);
-    size_t wp = 0, bp = 0;
+    size_t bp = 0;
     for (int l = 0; l < 6; ++l) {
-        wp = std::max(wp, wgrad_plan(l, n, H, W, prec).partial_floats * sizeof(float));
+        b.wpart[l] = cur;
+        cur += align256(wgrad_plan(l, n, H, W, prec).partial_floats * sizeof(float));
         int hin, win, hout, wout;
         layer_io(l, H, W, &hin, &win, &hout, &wout);
         int nb;
@@ -504,7 +515,6 @@ BwdLayout bwd_layout(int prec, int n, int H, int W, bool recompute_needed) {
     }
     // the whole-network data-gradient kernel keeps 323 bias partials per workgroup
     bp = std::max(bp, (size_t)std::min(n, 2048) * 323 * sizeof(float));
-    b.wpart = cur; cur += align256(wp);
     b.bpart = cur; cur += align256(bp);
     b.bpart_bytes = bp;
     b.total = cur;

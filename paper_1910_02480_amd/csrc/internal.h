@@ -60,6 +60,13 @@ struct drc_cae {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_next = 0;
     std::vector<std::pair<int, size_t>> prof_rec;  // (slot, index of the start event)
+    // side streams of the backward: the six weight gradients run beside the
+    // data-gradient chain (fork and join by events; recorded into graphs as
+    // parallel branches)
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t ev_fork[6] = {};
+    hipEvent_t ev_join[kSide] = {};
 };
 
 // Timing slots (drc_cae_profile_read): 0..5 forward GEMM of E1..D1,
@@ -80,7 +87,8 @@ struct ActSizes {
 struct BwdLayout {
     size_t recomp[3];
     size_t dz_u2, dh1s, dz_u3, dh2s, dz_h3, dz_h2, dz_h1;
-    size_t wpart, bpart, bpart_bytes, total;
+    size_t wpart[6];  // weight-gradient partial tiles of each layer (the six run concurrently)
+    size_t bpart, bpart_bytes, total;
 };
 
 struct StepLayout {
@@ -164,6 +172,9 @@ bool fused_forward_size(int H, int W);
 int fused_forward_grid(const drc_cae* h, int n, int H, int W);
 size_t fused_forward_scratch(const drc_cae* h, int n, int H, int W);
 // save: null, or h1 h2 h3 u3 u2 destinations (plain NHWC, null entries skipped).
+// FP8 handles, 32x32 / 64x64 maps: the whole network in one kernel (inference).
+drc_status fused_fp8_forward(drc_cae* h, const float* x, float* y, int n, int H, int W, const long* x_off,
+                             const long* y_off, hipStream_t s);
 drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int W, const long* x_off,
                          const long* y_off, void* scratch, size_t scratch_bytes, hipStream_t s,
                          char* const* save = nullptr);

@@ -285,6 +285,8 @@ extern "C" drc_status drc_cae_forward(drc_cae* h, const float* d_x, float* d_y, 
     TRY(drc_cae_workspace_size(h, n, H, W, DRC_WS_FORWARD, &need));
     if (ws_bytes < need)
         return drc_fail(DRC_ERR_WORKSPACE, "forward: workspace %zu < %zu bytes", ws_bytes, need);
+    if (h->fused && h->prec == P_FP8 && fused_forward_size(H, W) && !d_saved)
+        return fused_fp8_forward(h, d_x, d_y, n, H, W, nullptr, nullptr, (hipStream_t)stream);
     if (h->fused && h->prec == P_BF16 && fused_forward_size(H, W)) {
         char* save[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
         if (d_saved) {
@@ -497,8 +499,25 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
     void* dz_h3 = ws + L.dz_h3;
     void* dz_h2 = ws + L.dz_h2;
     void* dz_h1 = ws + L.dz_h1;
-    float* wpart = (float*)(ws + L.wpart);
     float* bpart = (float*)(ws + L.bpart);
+    // FP32: the weight gradients run on the handle's side streams, each
+    // forked after the data gradient it reads and joined before the call
+    // returns (each layer has its own partial tiles); 4096 maps of 64x64:
+    // forward + backward 9 % faster. BF16 keeps them on the stream: there
+    // the large-LDS weight-gradient kernels do not share CUs and the forks
+    // made the 256-map training step 7 % slower.
+    constexpr bool kFork = P == P_F32;
+    auto wgrad_on = [&](int l, auto&& launch) -> drc_status {
+        hipStream_t ss = kFork ? h->side[l % drc_cae::kSide] : s;
+        if (kFork) {
+            HIPCHK(hipEventRecord(h->ev_fork[l], s));
+            HIPCHK(hipStreamWaitEvent(ss, h->ev_fork[l], 0));
+        }
+        const long tok = prof_begin(h, PROF_WGRAD + l, ss);
+        TRY(launch((float*)(ws + L.wpart[l]), ss));
+        prof_end(h, tok, ss);
+        return DRC_OK;
+    };
     ActSizes as = act_sizes(P, n, H, W);
     float* dp = b.dparams;
     // BF16 32x32 / 64x64: all data gradients of D1..E2 in one kernel first
@@ -522,10 +541,10 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         if (!fdg) { const long tok = prof_begin(h, PROF_BWD + 5, s);
         TRY(run_gemm<P>(5, true, a, fit_npw(default_npw(P, 5, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
-        { const long tok = prof_begin(h, PROF_WGRAD + 5, s);
-        TRY(weight_grad<T>(5, n, H, W, b.dy, true, Src{b.u2, 32, 32}, Src{b.h1, 32, 32}, 0, wpart,
-                           dp + layer_w_offset(5), gscale, s));
-        prof_end(h, tok, s); }
+        TRY(wgrad_on(5, [&](float* wpart, hipStream_t ss) {
+            return weight_grad<T>(5, n, H, W, b.dy, true, Src{b.u2, 32, 32}, Src{b.h1, 32, 32}, 0, wpart,
+                                  dp + layer_w_offset(5), gscale, ss);
+        }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(b.dy, true, 3, as.p0, bpart, dp + layer_b_offset(5), gscale, s));
         prof_end(h, tok, s); }
@@ -544,10 +563,10 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         if (!fdg) { const long tok = prof_begin(h, PROF_BWD + 4, s);
         TRY(run_gemm<P>(4, true, a, fit_npw(default_npw(P, 4, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
-        { const long tok = prof_begin(h, PROF_WGRAD + 4, s);
-        TRY(weight_grad<T>(4, n, H, W, dz_u2, false, Src{b.u3, 64, 64}, Src{b.h2, 64, 64}, 0, wpart,
-                           dp + layer_w_offset(4), gscale, s));
-        prof_end(h, tok, s); }
+        TRY(wgrad_on(4, [&](float* wpart, hipStream_t ss) {
+            return weight_grad<T>(4, n, H, W, dz_u2, false, Src{b.u3, 64, 64}, Src{b.h2, 64, 64}, 0, wpart,
+                                  dp + layer_w_offset(4), gscale, ss);
+        }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_u2, false, 32, as.p1, bpart, dp + layer_b_offset(4), gscale, s));
         prof_end(h, tok, s); }
@@ -565,10 +584,10 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         if (!fdg) { const long tok = prof_begin(h, PROF_BWD + 3, s);
         TRY(run_gemm<P>(3, true, a, fit_npw(default_npw(P, 3, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
-        { const long tok = prof_begin(h, PROF_WGRAD + 3, s);
-        TRY(weight_grad<T>(3, n, H, W, dz_u3, false, Src{b.h3, 128, 128}, Src{nullptr, 0, 0}, 0, wpart,
-                           dp + layer_w_offset(3), gscale, s));
-        prof_end(h, tok, s); }
+        TRY(wgrad_on(3, [&](float* wpart, hipStream_t ss) {
+            return weight_grad<T>(3, n, H, W, dz_u3, false, Src{b.h3, 128, 128}, Src{nullptr, 0, 0}, 0, wpart,
+                                  dp + layer_w_offset(3), gscale, ss);
+        }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_u3, false, 64, as.p2, bpart, dp + layer_b_offset(3), gscale, s));
         prof_end(h, tok, s); }
@@ -588,10 +607,10 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         if (!fdg) { const long tok = prof_begin(h, PROF_BWD + 2, s);
         TRY(run_gemm<P>(2, true, a, fit_npw(default_npw(P, 2, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
-        { const long tok = prof_begin(h, PROF_WGRAD + 2, s);
-        TRY(weight_grad<T>(2, n, H, W, dz_h3, false, Src{b.h2, 64, 64}, Src{nullptr, 0, 0}, 0, wpart,
-                           dp + layer_w_offset(2), gscale, s));
-        prof_end(h, tok, s); }
+        TRY(wgrad_on(2, [&](float* wpart, hipStream_t ss) {
+            return weight_grad<T>(2, n, H, W, dz_h3, false, Src{b.h2, 64, 64}, Src{nullptr, 0, 0}, 0, wpart,
+                                  dp + layer_w_offset(2), gscale, ss);
+        }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_h3, false, 128, as.p3, bpart, dp + layer_b_offset(2), gscale, s));
         prof_end(h, tok, s); }
@@ -611,20 +630,20 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         if (!fdg) { const long tok = prof_begin(h, PROF_BWD + 1, s);
         TRY(run_gemm<P>(1, true, a, fit_npw(default_npw(P, 1, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
         prof_end(h, tok, s); }
-        { const long tok = prof_begin(h, PROF_WGRAD + 1, s);
-        TRY(weight_grad<T>(1, n, H, W, dz_h2, false, Src{b.h1, 32, 32}, Src{nullptr, 0, 0}, 0, wpart,
-                           dp + layer_w_offset(1), gscale, s));
-        prof_end(h, tok, s); }
+        TRY(wgrad_on(1, [&](float* wpart, hipStream_t ss) {
+            return weight_grad<T>(1, n, H, W, dz_h2, false, Src{b.h1, 32, 32}, Src{nullptr, 0, 0}, 0, wpart,
+                                  dp + layer_w_offset(1), gscale, ss);
+        }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_h2, false, 64, as.p2, bpart, dp + layer_b_offset(1), gscale, s));
         prof_end(h, tok, s); }
     }
     // E1: h1 = relu(conv(x))
     {
-        { const long tok = prof_begin(h, PROF_WGRAD + 0, s);
-        TRY(weight_grad<T>(0, n, H, W, dz_h1, false, Src{b.x, 7, 7}, Src{nullptr, 0, 0}, 7, wpart,
-                           dp + layer_w_offset(0), gscale, s));
-        prof_end(h, tok, s); }
+        TRY(wgrad_on(0, [&](float* wpart, hipStream_t ss) {
+            return weight_grad<T>(0, n, H, W, dz_h1, false, Src{b.x, 7, 7}, Src{nullptr, 0, 0}, 7, wpart,
+                                  dp + layer_w_offset(0), gscale, ss);
+        }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_h1, false, 32, as.p1, bpart, dp + layer_b_offset(0), gscale, s));
         prof_end(h, tok, s); }
@@ -640,6 +659,11 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
             TRY(run_gemm<P>(0, true, a, fit_npw(default_npw(P, 0, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
             prof_end(h, tok, s); }
         }
+    }
+    // join the side streams
+    for (int k = 0; k < drc_cae::kSide && kFork; ++k) {
+        HIPCHK(hipEventRecord(h->ev_join[k], h->side[k]));
+        HIPCHK(hipStreamWaitEvent(s, h->ev_join[k], 0));
     }
     return DRC_OK;
 }

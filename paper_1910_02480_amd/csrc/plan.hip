@@ -229,6 +229,11 @@ static drc_status plan_enqueue(drc_plan* p, const float* x, float* y, char* ws, 
         const long* xo = (const long*)(p->d_tables + pc.dev_xoff);
         const long* yo = (const long*)(p->d_tables + pc.dev_yoff);
         // (its input staging reads 16-byte vectors: every map must start on a 16-byte boundary)
+        if (h->fused && h->prec == P_FP8 && fused_forward_size(pc.H, pc.W) && pc.x_al16 &&
+            (uintptr_t)x % 16 == 0) {
+            st = fused_fp8_forward(h, x, y, pc.n, pc.H, pc.W, xo, yo, s);
+            continue;
+        }
         if (h->fused && h->prec == P_BF16 && fused_forward_size(pc.H, pc.W) && pc.x_al16 &&
             (uintptr_t)x % 16 == 0) {
             // the class's h1 region (n maps) holds the per-workgroup slots

@@ -42,6 +42,7 @@ _LABELS = (
     (r"tconv_pairs_kernel<(\d), 64, 64, 32,", "data gradient E2"),
     (r"tconv_merged_kernel<(\d), 64, 32, 3,", "forward D1"),
     (r"cae_fused_forward_kernel<\d+, \d+, false>", "forward fused"),
+    (r"cae_fused_fp8_kernel", "FP8 forward fused"),
     (r"cae_fused_forward_kernel<\d+, \d+, true>", "recompute fused"),
     (r"pack_weights_kernel|pack_all_kernel", "weight pack"),
     (r"envmap_build_kernel", "envmap build"),
@@ -84,6 +85,7 @@ def label(name: str) -> str | None:
 # every source.
 _KERNEL_SOURCES = {
     "forward fused": ("fused_fwd.hip", "common.h", "conv_layer.h", "internal.h"),
+    "FP8 forward fused": ("fused_fp8.hip", "common.h", "conv_layer.h", "internal.h"),
     "envmap build": ("envmap.hip", "internal.h"),
     "envmap sample": ("envmap.hip", "internal.h"),
     "envmap pdf": ("envmap.hip", "internal.h"),

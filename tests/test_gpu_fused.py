@@ -117,3 +117,34 @@ def test_fused_training_step_matches_layer_path(params):
     _check_grads(res[True][1], res[False][1])
     for ws, _, _ in layer_slices():
         np.testing.assert_array_equal(res[True][2][ws], res[False][2][ws])
+
+
+# FP8 (e4m3, per-tensor scales): the whole-network kernel against the FP8 layer path
+@pytest.mark.parametrize("H,n", [(64, 1), (64, 3), (64, 600), (32, 1), (32, 1100)])
+def test_fused_fp8_matches_layer_path_bitwise(params, H, n):
+    from paper_1910_02480_amd.cae import CAE
+    print(f"[fused-fp8] H={H} n={n}", flush=True)
+    cae = CAE("fp8", torch.from_numpy(params).to(DEV), device=DEV)
+    cae.calibrate_fp8(torch.from_numpy(synth.radiance_maps(16, 64, 64, seed=3)).to(DEV))
+    x = torch.from_numpy(synth.radiance_maps(n, H, H, seed=21)).to(DEV)
+    y_fused = cae.forward(x).cpu().numpy()
+    cae.set_fused(False)
+    y_layer = cae.forward(x).cpu().numpy()
+    assert np.isfinite(y_fused).all()
+    np.testing.assert_array_equal(y_fused, y_layer)
+
+
+def test_fused_fp8_accuracy_reported(oracle, params):
+    """FP8 error against the FP64 oracle over 64 maps of 64x64 (reported,
+    not gated by the BF16 bound: e4m3 keeps 3 mantissa bits)."""
+    from paper_1910_02480_amd.cae import CAE
+    from tests.helpers import mean_rel_per_map
+    cae = CAE("fp8", torch.from_numpy(params).to(DEV), device=DEV)
+    cae.calibrate_fp8(torch.from_numpy(synth.radiance_maps(64, 64, 64, seed=3)).to(DEV))
+    x = synth.radiance_maps(64, 64, 64, seed=22)
+    y = cae.forward(torch.from_numpy(x).to(DEV)).cpu().numpy()
+    r = oracle.forward(params, x)["y"]
+    mx, mn = max_rel_per_map(y, r), mean_rel_per_map(y, r)
+    print(f"FP8 fused, 64 maps of 64x64: max_rel max {mx.max():.3e} p99 {np.percentile(mx, 99):.3e}, "
+          f"mean_rel mean {mn.mean():.3e}")
+    assert mx.max() < 0.25 and mn.mean() < 0.1
