@@ -23,7 +23,7 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
 
 // float -> OCP FP8 E4M3 ("e4m3fn": bias 7, no infinities, 0x7f = NaN),
 // round to nearest even, saturating at +-448 (infinities saturate too).
-// The value is clamped to +-448 and converted by the hardware's
+// The value is clamped to +-448 (med3) and converted by the hardware's
 // round-to-nearest-even e4m3 conversion (v_cvt_pk_fp8_f32); on gfx950 that
 // gives the same byte as the definition above for every finite input
 // (checked over all floats of magnitude 2^-27 .. 2^14 with 2^19 mantissa
@@ -31,9 +31,36 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
 // subnormal grid); NaN is mapped to 0x7f with its sign by the select.
 __device__ __forceinline__ uint8_t f32_to_e4m3(float f) {
     const uint8_t nan = (uint8_t)(((__float_as_uint(f) >> 24) & 0x80u) | 0x7fu);
-    const float c = fminf(fmaxf(f, -448.0f), 448.0f);
+    const float c = __builtin_amdgcn_fmed3f(f, -448.0f, 448.0f);
     const uint8_t v = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(c, c, 0, false) & 0xff);
     return f != f ? nan : v;
+}
+
+// The FP8 store of an activation: e4m3(v * q) (q > 0, the output tensor's
+// scale), after a ReLU when `relu`. The ReLU is the lower bound of the clamp
+// (med3(v q, 0, 448)); without it the clamp is [-448, 448]. A NaN keeps its
+// encoding (0x7f with its sign). Every FP8 activation store of the library
+// goes through these two, so both give the same byte for the same value.
+__device__ __forceinline__ uint8_t e4m3_act(float v, float q, bool relu) {
+    const float u = v * q;
+    const float c = __builtin_amdgcn_fmed3f(u, relu ? 0.0f : -448.0f, 448.0f);
+    const uint8_t b = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(c, c, 0, false) & 0xff);
+    return u != u ? (uint8_t)(((__float_as_uint(u) >> 24) & 0x80u) | 0x7fu) : b;
+}
+// Four values, bytes in order in one word: two conversions of two values
+// each; a NaN among them (its sum is NaN) takes the per-value encoder.
+__device__ __forceinline__ uint32_t e4m3_act4(float v0, float v1, float v2, float v3, float q, bool relu) {
+    const float u0 = v0 * q, u1 = v1 * q, u2 = v2 * q, u3 = v3 * q;
+    const float s = (u0 + u1) + (u2 + u3);
+    if (__builtin_expect(s != s, 0))
+        return (uint32_t)e4m3_act(v0, q, relu) | ((uint32_t)e4m3_act(v1, q, relu) << 8) |
+               ((uint32_t)e4m3_act(v2, q, relu) << 16) | ((uint32_t)e4m3_act(v3, q, relu) << 24);
+    const float lo = relu ? 0.0f : -448.0f;
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(u0, lo, 448.0f),
+                                            __builtin_amdgcn_fmed3f(u1, lo, 448.0f), 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(u2, lo, 448.0f),
+                                        __builtin_amdgcn_fmed3f(u3, lo, 448.0f), w, true);
+    return (uint32_t)w;
 }
 __device__ __forceinline__ float e4m3_to_f32(uint8_t v) {
     const uint32_t s = (v & 0x80u) << 24;

@@ -177,6 +177,17 @@ __device__ __forceinline__ void store_seg(const Seg& s, long doff, long opix, in
 #pragma unroll
             for (int e = 0; e < 4; ++e) v[e] += ad[e];
         }
+        if constexpr (P == P_FP8 && !OUT_F32) {
+            // the ReLU is folded into the store's clamp
+            if (s.mask) {
+                float mk[4];
+                load4<T>((const T*)s.mask + opix * s.ldm + lc, mk);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = (mk[e] > 0.0f) ? v[e] : 0.0f;
+            }
+            *(uint32_t*)((T*)s.dst + doff + lc) = e4m3_act4(v[0], v[1], v[2], v[3], s.qscale, s.relu);
+            return;
+        }
         if (s.relu) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) v[e] = (v[e] < 0.0f) ? 0.0f : v[e];
@@ -214,6 +225,11 @@ __device__ __forceinline__ void store_seg(const Seg& s, long doff, long opix, in
         if (c >= s.c) break;
         float x = v[e];
         if (s.add) x += to_float<T>(((const T*)s.add)[opix * s.lda + c]);
+        if constexpr (P == P_FP8 && !OUT_F32) {
+            if (s.mask && !(to_float<T>(((const T*)s.mask)[opix * s.ldm + c]) > 0.0f)) x = 0.0f;
+            ((T*)s.dst)[doff + c] = e4m3_act(x, s.qscale, s.relu);
+            continue;
+        }
         if (s.relu) x = (x < 0.0f) ? 0.0f : x;
         if (s.mask && !(to_float<T>(((const T*)s.mask)[opix * s.ldm + c]) > 0.0f)) x = 0.0f;
         if constexpr (OUT_F32)
@@ -714,6 +730,10 @@ __global__ __launch_bounds__(256) void tconv_merged_kernel(const LayerArgs a) {
                         if constexpr (OUT_F32)
                             if (G.out_off) doff = G.out_off[ps[p].n] + (ps[p].oloc + dpix) * G.seg0.ld;
                         float v = acc[m][p][e] * a.acc_scale + bias[m][e];
+                        if constexpr (P == P_FP8 && !OUT_F32) {
+                            ((T*)G.seg0.dst)[doff + co] = e4m3_act(v, G.seg0.qscale, G.seg0.relu);
+                            continue;
+                        }
                         if (G.seg0.relu) v = (v < 0.0f) ? 0.0f : v;
                         if constexpr (OUT_F32)
                             ((float*)G.seg0.dst)[doff + co] = v;

@@ -100,14 +100,8 @@ __device__ __forceinline__ void mma8(f4& acc, const V& a, const V& b) { TR::mma(
 // Stores channels [ch, ch+4) of an output pixel: v = acc * scale + bias, ReLU,
 // e4m3(v * qout), 4 bytes at `off`.
 __device__ __forceinline__ void st4(char* smem, int off, const f4& acc, float scale, const float* bias, float qout) {
-    float v[4] = {acc.x * scale + bias[0], acc.y * scale + bias[1], acc.z * scale + bias[2], acc.w * scale + bias[3]};
-    uint32_t w = 0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const float r = (v[e] < 0.0f) ? 0.0f : v[e];
-        w |= (uint32_t)TR::from_f32(r, qout) << (8 * e);
-    }
-    *(uint32_t*)(smem + off) = w;
+    *(uint32_t*)(smem + off) = e4m3_act4(acc.x * scale + bias[0], acc.y * scale + bias[1], acc.z * scale + bias[2],
+                                         acc.w * scale + bias[3], qout, true);
 }
 
 // x (float32, 7 channels) -> e4m3(x * s) with 8 channels (channel 7 = 0), 8
@@ -124,11 +118,10 @@ __device__ __forceinline__ void stage_x8(char* smem, int xs, const float* xm, fl
         const float* f = (const float*)v;
 #pragma unroll
         for (int px = 0; px < 4; ++px) {
+            const float* c = f + 7 * px;
             uint2 o;
-            o.x = (uint32_t)TR::from_f32(f[7 * px + 0], s) | ((uint32_t)TR::from_f32(f[7 * px + 1], s) << 8) |
-                  ((uint32_t)TR::from_f32(f[7 * px + 2], s) << 16) | ((uint32_t)TR::from_f32(f[7 * px + 3], s) << 24);
-            o.y = (uint32_t)TR::from_f32(f[7 * px + 4], s) | ((uint32_t)TR::from_f32(f[7 * px + 5], s) << 8) |
-                  ((uint32_t)TR::from_f32(f[7 * px + 6], s) << 16);
+            o.x = e4m3_act4(c[0], c[1], c[2], c[3], s, false);
+            o.y = e4m3_act4(c[4], c[5], c[6], 0.0f, s, false);
             *(uint2*)(smem + xs + (4 * q + px) * 8) = o;
         }
     }
