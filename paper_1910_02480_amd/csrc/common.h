@@ -17,6 +17,16 @@ typedef int i8v __attribute__((ext_vector_type(8)));
 // float -> bfloat16, round to nearest even (the hardware conversion,
 // v_cvt_pk_bf16_f32; a NaN stays a NaN).
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+// Two floats -> two bfloat16 (RNE) in one word, a first: one v_cvt_pk_bf16_f32.
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+    const f2v f = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, b2v));
+}
+// ReLU as the IEEE 754-2019 maximum(v, +0) (one v_maximum3_f32): a NaN
+// stays NaN, -0 becomes +0. Every ReLU of the library uses it.
+__device__ __forceinline__ float relu(float v) { return __builtin_elementwise_maximum(v, 0.0f); }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
     return __uint_as_float((uint32_t)h << 16);
 }

@@ -190,7 +190,7 @@ __device__ __forceinline__ void store_seg(const Seg& s, long doff, long opix, in
         }
         if (s.relu) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = (v[e] < 0.0f) ? 0.0f : v[e];
+            for (int e = 0; e < 4; ++e) v[e] = relu(v[e]);
         }
         if (s.mask) {
             float mk[4];
@@ -201,17 +201,16 @@ __device__ __forceinline__ void store_seg(const Seg& s, long doff, long opix, in
         if constexpr (OUT_F32) {
             *(float4*)((float*)s.dst + doff + lc) = make_float4(v[0], v[1], v[2], v[3]);
         } else {
+            T* d = (T*)s.dst + doff + lc;
+            if constexpr (sizeof(T) == 2) {
+                *(uint2*)d = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                return;
+            }
             T o[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) o[e] = to_store<P>(v[e], s.qscale);
-            T* d = (T*)s.dst + doff + lc;
             if constexpr (sizeof(T) == 4) {
                 *(float4*)d = make_float4(o[0], o[1], o[2], o[3]);
-            } else if constexpr (sizeof(T) == 2) {
-                uint2 w;
-                w.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
-                w.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
-                *(uint2*)d = w;
             } else {
                 *(uint32_t*)d = (uint32_t)o[0] | ((uint32_t)o[1] << 8) | ((uint32_t)o[2] << 16) |
                                 ((uint32_t)o[3] << 24);
@@ -230,7 +229,7 @@ __device__ __forceinline__ void store_seg(const Seg& s, long doff, long opix, in
             ((T*)s.dst)[doff + c] = e4m3_act(x, s.qscale, s.relu);
             continue;
         }
-        if (s.relu) x = (x < 0.0f) ? 0.0f : x;
+        if (s.relu) x = relu(x);
         if (s.mask && !(to_float<T>(((const T*)s.mask)[opix * s.ldm + c]) > 0.0f)) x = 0.0f;
         if constexpr (OUT_F32)
             ((float*)s.dst)[doff + c] = x;
@@ -734,7 +733,7 @@ __global__ __launch_bounds__(256) void tconv_merged_kernel(const LayerArgs a) {
                             ((T*)G.seg0.dst)[doff + co] = e4m3_act(v, G.seg0.qscale, G.seg0.relu);
                             continue;
                         }
-                        if (G.seg0.relu) v = (v < 0.0f) ? 0.0f : v;
+                        if (G.seg0.relu) v = relu(v);
                         if constexpr (OUT_F32)
                             ((float*)G.seg0.dst)[doff + co] = v;
                         else

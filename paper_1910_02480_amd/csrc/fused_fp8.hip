@@ -150,8 +150,8 @@ __device__ __forceinline__ void e1_phase(char* smem, int xs, int h1, const F8Arg
 #pragma unroll
         for (int p = 0; p < NPW; ++p) {
             const int pix = (tp * NPW + p) * 16 + r16;
-            oy[p] = pix / WO;
-            ox[p] = pix % WO;
+            oy[p] = (int)((unsigned)pix / WO);
+            ox[p] = (int)((unsigned)pix % WO);
             uint2 hh[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
@@ -206,8 +206,8 @@ __device__ __forceinline__ void conv_phase8(char* smem, int in, int out, int zo,
 #pragma unroll
         for (int p = 0; p < NPW; ++p) {
             const int pix = (tp * NPW + p) * 16 + r16;
-            oy[p] = pix / WO;
-            ox[p] = pix % WO;
+            oy[p] = (int)((unsigned)pix / WO);
+            ox[p] = (int)((unsigned)pix % WO);
         }
         f4 acc[MT][NPW];
 #pragma unroll
@@ -293,8 +293,8 @@ __device__ __forceinline__ void pairs8(const Panel8<MT>& P, char* smem, int in0,
 #pragma unroll
         for (int p = 0; p < NPW; ++p) {
             const int pix = pix0 + (tp * NPW + p) * 16 + r16;
-            ia[p] = pix / WI;
-            ib[p] = pix % WI;
+            ia[p] = (int)((unsigned)pix / WI);
+            ib[p] = (int)((unsigned)pix % WI);
 #pragma unroll
             for (int nb = 0; nb < NNB; ++nb) {
                 const int di = nb >> 1, dj = nb & 1;
@@ -363,8 +363,8 @@ __device__ __forceinline__ void d1_phase8(const D1P8& P, char* smem, int u2, int
 #pragma unroll
         for (int p = 0; p < NPW; ++p) {
             const int pix = row0 * WI + (tp * NPW + p) * 16 + r16;
-            ia[p] = pix / WI;
-            ib[p] = pix % WI;
+            ia[p] = (int)((unsigned)pix / WI);
+            ib[p] = (int)((unsigned)pix % WI);
             acc[p] = f4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
@@ -395,7 +395,7 @@ __device__ __forceinline__ void d1_phase8(const D1P8& P, char* smem, int u2, int
                 const int ph = r / 3;
                 const int opix = (2 * ia[p] + (ph >> 1)) * WO + 2 * ib[p] + (ph & 1);
                 float v = acc[p][e] * scale + P.bias[e];
-                if (relu) v = (v < 0.0f) ? 0.0f : v;
+                if (relu) v = drc::relu(v);
                 ym[opix * 3 + (r - ph * 3)] = v;
             }
     }
@@ -417,7 +417,8 @@ struct F8Lds {
 
 template <int H, int W>
 __global__ __launch_bounds__(NT, 2) void cae_fused_fp8_kernel(const F8Args a) {
-    extern __shared__ __align__(16) char smem[];
+    // static LDS: LDS offsets fold into the instructions' immediate fields
+    __shared__ __align__(16) char smem[F8Lds<H, W>::BYTES];
     typedef F8Lds<H, W> L;
     constexpr int HW = H * W;
     constexpr int E1N = (HW / 64) >= 4 * 4 * 4 ? 4 : 2;     // E1: PB = HW/64
@@ -498,13 +499,7 @@ __global__ __launch_bounds__(NT, 2) void cae_fused_fp8_kernel(const F8Args a) {
 
 template <int H, int W>
 drc_status launch_fp8(const F8Args& a, int grid, hipStream_t s) {
-    const int lds = F8Lds<H, W>::BYTES;
-    auto kern = cae_fused_fp8_kernel<H, W>;
-    if (lds > 64 * 1024) {
-        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-            return drc_fail(DRC_ERR_HIP, "fused fp8 forward: cannot raise the LDS limit to %d bytes", lds);
-    }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((cae_fused_fp8_kernel<H, W>), dim3(grid), dim3(NT), 0, s, a);
     return check_launch("fused fp8 forward");
 }
 

@@ -49,8 +49,6 @@ struct FusedArgs {
     int final_relu;
 };
 
-__device__ __forceinline__ uint16_t bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
-
 // Byte offset of 16-byte chunk `chunk` of pixel (y, x) in an LDS tensor of C
 // channels and row length WI. The chunk index is XORed with bits of the
 // column x, so that the 16 lanes of an MFMA operand, which read the same
@@ -77,11 +75,11 @@ __device__ __forceinline__ void lds_store4(char* smem, int region, int y, int x,
     float v[4] = {acc.x + bias[0], acc.y + bias[1], acc.z + bias[2], acc.w + bias[3]};
     if (relu) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = (v[e] < 0.0f) ? 0.0f : v[e];
+        for (int e = 0; e < 4; ++e) v[e] = drc::relu(v[e]);
     }
     uint2 w;
-    w.x = (uint32_t)bf16_bits(v[0]) | ((uint32_t)bf16_bits(v[1]) << 16);
-    w.y = (uint32_t)bf16_bits(v[2]) | ((uint32_t)bf16_bits(v[3]) << 16);
+    w.x = pack_bf16x2(v[0], v[1]);
+    w.y = pack_bf16x2(v[2], v[3]);
     *(uint2*)(smem + region + loff<C, WI>(y, x, ch >> 3) + ((ch >> 2) & 1) * 8) = w;
 }
 
@@ -146,10 +144,10 @@ __device__ __forceinline__ void stage_x(char* smem, int xs, const float* xm) {
 #pragma unroll
             for (int px = 0; px < 4; ++px) {
                 uint4 o;
-                o.x = (uint32_t)bf16_bits(f[7 * px + 0]) | ((uint32_t)bf16_bits(f[7 * px + 1]) << 16);
-                o.y = (uint32_t)bf16_bits(f[7 * px + 2]) | ((uint32_t)bf16_bits(f[7 * px + 3]) << 16);
-                o.z = (uint32_t)bf16_bits(f[7 * px + 4]) | ((uint32_t)bf16_bits(f[7 * px + 5]) << 16);
-                o.w = (uint32_t)bf16_bits(f[7 * px + 6]);
+                o.x = pack_bf16x2(f[7 * px + 0], f[7 * px + 1]);
+                o.y = pack_bf16x2(f[7 * px + 2], f[7 * px + 3]);
+                o.z = pack_bf16x2(f[7 * px + 4], f[7 * px + 5]);
+                o.w = pack_bf16x2(f[7 * px + 6], 0.0f);
                 *(uint4*)(smem + xs + (4 * q + px) * 16) = o;
             }
         }
@@ -191,10 +189,10 @@ __device__ __forceinline__ void x_piece_store(char* smem, int xs, const XPiece& 
 #pragma unroll
         for (int px = 0; px < 2; ++px) {
             uint4 o;
-            o.x = (uint32_t)bf16_bits(f[7 * px + 0]) | ((uint32_t)bf16_bits(f[7 * px + 1]) << 16);
-            o.y = (uint32_t)bf16_bits(f[7 * px + 2]) | ((uint32_t)bf16_bits(f[7 * px + 3]) << 16);
-            o.z = (uint32_t)bf16_bits(f[7 * px + 4]) | ((uint32_t)bf16_bits(f[7 * px + 5]) << 16);
-            o.w = (uint32_t)bf16_bits(f[7 * px + 6]);
+            o.x = pack_bf16x2(f[7 * px + 0], f[7 * px + 1]);
+            o.y = pack_bf16x2(f[7 * px + 2], f[7 * px + 3]);
+            o.z = pack_bf16x2(f[7 * px + 4], f[7 * px + 5]);
+            o.w = pack_bf16x2(f[7 * px + 6], 0.0f);
             *(uint4*)(smem + xs + (row * W + col + px) * 16) = o;
         }
     }
@@ -250,8 +248,8 @@ __device__ __forceinline__ void conv_phase(char* smem, int in, int zoff, const u
 #pragma unroll
         for (int p = 0; p < NPW; ++p) {
             const int pix = (tp * NPW + p) * 16 + r16;
-            oy[p] = pix / WO;
-            ox[p] = pix % WO;
+            oy[p] = (int)((unsigned)pix / WO);
+            ox[p] = (int)((unsigned)pix % WO);
         }
         // byte offsets of the 9 taps (CIN >= 32) or of the lane's tap per K step (CIN == 8)
         int off[NPW][CIN == 8 ? KSTEPS : 9];
@@ -377,8 +375,8 @@ __device__ __forceinline__ void pairs_tiles(const PairsPanel<(C0 + C1) / 32, MT>
 #pragma unroll
         for (int p = 0; p < NPW; ++p) {
             const int pix = pix0 + (tp * NPW + p) * 16 + r16;
-            ia[p] = pix / WI;
-            ib[p] = pix % WI;
+            ia[p] = (int)((unsigned)pix / WI);
+            ib[p] = (int)((unsigned)pix % WI);
             const bool down = ia[p] + 1 < HI, right = ib[p] + 1 < WI;
 #pragma unroll
             for (int s = 0; s < NSRC; ++s)
@@ -507,8 +505,8 @@ __device__ __forceinline__ void d1_phase(const D1Panel& P, char* smem, int u2, i
 #pragma unroll
         for (int p = 0; p < NPW; ++p) {
             const int pix = row0 * WI + (tp * NPW + p) * 16 + r16;
-            ia[p] = pix / WI;
-            ib[p] = pix % WI;
+            ia[p] = (int)((unsigned)pix / WI);
+            ib[p] = (int)((unsigned)pix % WI);
             const bool down = ia[p] + 1 < HI, right = ib[p] + 1 < WI;
             const int ru0 = RING ? ia[p] % (RING > 0 ? RING : 1) : ia[p];
             const int ru1 = RING ? (ia[p] + 1) % (RING > 0 ? RING : 1) : ia[p] + 1;
@@ -542,7 +540,7 @@ __device__ __forceinline__ void d1_phase(const D1Panel& P, char* smem, int u2, i
                 const int ph = r / 3;
                 const int opix = (2 * ia[p] + (ph >> 1)) * WO + 2 * ib[p] + (ph & 1);
                 float v = acc[p][e] + P.bias[e];
-                if (relu) v = (v < 0.0f) ? 0.0f : v;
+                if (relu) v = drc::relu(v);
                 ym[opix * 3 + (r - ph * 3)] = v;
             }
     }
@@ -556,7 +554,7 @@ __device__ __forceinline__ void copy_out(char* dst, const char* smem, int region
     constexpr int CH = C / 8, N = HI * WI * CH;
     for (int i = threadIdx.x; i < N; i += FT) {
         const int pix = i / CH, j = i - pix * CH;
-        ((uint4*)dst)[i] = *(const uint4*)(smem + region + loff<C, WI>(pix / WI, pix % WI, j));
+        ((uint4*)dst)[i] = *(const uint4*)(smem + region + loff<C, WI>((int)((unsigned)pix / WI), (int)((unsigned)pix % WI), j));
     }
 }
 // Rows [row0, row0 + nrows) of a ring of RING rows (C channels, WI wide) to
@@ -577,7 +575,7 @@ __device__ __forceinline__ void copy_in(char* smem, int region, const char* src)
     constexpr int CH = C / 8, N = HI * WI * CH;
     for (int i = threadIdx.x; i < N; i += FT) {
         const int pix = i / CH, j = i - pix * CH;
-        *(uint4*)(smem + region + loff<C, WI>(pix / WI, pix % WI, j)) = ((const uint4*)src)[i];
+        *(uint4*)(smem + region + loff<C, WI>((int)((unsigned)pix / WI), (int)((unsigned)pix % WI), j)) = ((const uint4*)src)[i];
     }
 }
 
@@ -603,7 +601,10 @@ struct FusedLds {
 // -> h3, u3, u2 (written to save[2..4]); E1, E2 and D1 are skipped.
 template <int H, int W, bool MID>
 __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a) {
-    extern __shared__ __align__(16) char smem[];
+    // static LDS: its address is a compile-time constant, so LDS offsets fold
+    // into the instructions' immediate fields (a dynamic array's base is added
+    // to every address at run time)
+    __shared__ __align__(16) char smem[FusedLds<H, W>::BYTES];
     typedef FusedLds<H, W> L;
     constexpr int HW = H * W;
     constexpr int R0 = L::R0, R1 = L::R1, R2 = L::R2, R3 = L::R3, ZO = L::ZO;
@@ -765,8 +766,8 @@ __device__ __forceinline__ void grad_store(char* smem, const GSeg& sg, const Gra
         for (int e = 0; e < 4; ++e) v[e] = (mk[e] > 0.0f) ? v[e] : 0.0f;
     }
     uint2 w;
-    w.x = (uint32_t)bf16_bits(v[0]) | ((uint32_t)bf16_bits(v[1]) << 16);
-    w.y = (uint32_t)bf16_bits(v[2]) | ((uint32_t)bf16_bits(v[3]) << 16);
+    w.x = pack_bf16x2(v[0], v[1]);
+    w.y = pack_bf16x2(v[2], v[3]);
     if (sg.region >= 0) *(uint2*)(smem + sg.region + loffs) = w;
     if (sg.gdst) *(uint2*)(sg.gdst + pix * C + lc) = w;
     if (bsum) {  // bias gradient: column sums of the stored (rounded) values
@@ -849,8 +850,8 @@ __device__ __forceinline__ void stage_dy(char* smem, int xs, const float* dm, fl
 #pragma unroll
         for (int px = 0; px < 4; ++px) {
             uint4 o;
-            o.x = (uint32_t)bf16_bits(f[3 * px + 0]) | ((uint32_t)bf16_bits(f[3 * px + 1]) << 16);
-            o.y = (uint32_t)bf16_bits(f[3 * px + 2]);
+            o.x = pack_bf16x2(f[3 * px + 0], f[3 * px + 1]);
+            o.y = pack_bf16x2(f[3 * px + 2], 0.0f);
             o.z = 0u;
             o.w = 0u;
             *(uint4*)(smem + xs + (4 * q + px) * 16) = o;
@@ -860,7 +861,7 @@ __device__ __forceinline__ void stage_dy(char* smem, int xs, const float* dm, fl
 
 template <int H, int W>
 __global__ __launch_bounds__(FT) void cae_fused_dgrad_kernel(const DgradArgs a) {
-    extern __shared__ __align__(16) char smem[];
+    __shared__ __align__(16) char smem[32 * H * W + kZeroBytes];  // static: see the forward kernel
     constexpr int HW = H * W;
     constexpr int RA = 0, RB = 16 * HW, ZO = 32 * HW;
     constexpr long S1 = 8L * HW, S2 = 4L * HW, S3 = 2L * HW;  // elements per map at H/2, H/4, H/8
@@ -962,25 +963,13 @@ __global__ __launch_bounds__(256) void bias_final_kernel(const BiasFinalArgs a) 
 
 template <int H, int W>
 drc_status launch_dgrad(const DgradArgs& a, int grid, hipStream_t s) {
-    const int lds = 32 * H * W + kZeroBytes;
-    auto kern = cae_fused_dgrad_kernel<H, W>;
-    if (lds > 64 * 1024) {
-        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-            return drc_fail(DRC_ERR_HIP, "fused dgrad: cannot raise the LDS limit to %d bytes", lds);
-    }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(FT), lds, s, a);
+    hipLaunchKernelGGL((cae_fused_dgrad_kernel<H, W>), dim3(grid), dim3(FT), 0, s, a);
     return check_launch("fused dgrad");
 }
 
 template <int H, int W, bool MID>
 drc_status launch_fused(const FusedArgs& a, int grid, hipStream_t s) {
-    const int lds = FusedLds<H, W>::BYTES;
-    auto kern = cae_fused_forward_kernel<H, W, MID>;
-    if (lds > 64 * 1024) {
-        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-            return drc_fail(DRC_ERR_HIP, "fused forward: cannot raise the LDS limit to %d bytes", lds);
-    }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(FT), lds, s, a);
+    hipLaunchKernelGGL((cae_fused_forward_kernel<H, W, MID>), dim3(grid), dim3(FT), 0, s, a);
     return check_launch("fused forward");
 }
 

@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kThreads) void d1_band_kernel(const E1Args e) {
                 if (g * 4 + r >= 12) continue;
                 const int ph = rph[r], co = rco[r];
                 float v = acc[p][r] * a.acc_scale + bias[r];
-                if (G.seg0.relu) v = (v < 0.0f) ? 0.0f : v;
+                if (G.seg0.relu) v = relu(v);
                 ys[((2 * al[p] + (ph >> 1)) * Wout + 2 * bj[p] + (ph & 1)) * 3 + co] = v;
             }
         __syncthreads();
