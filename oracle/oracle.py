@@ -53,14 +53,22 @@ def lib():
                _D, _D, ctypes.c_long, _D]
         L.orc_conv_s2.argtypes = sig
         L.orc_tconv_s2.argtypes = sig
+        L.orc_conv_s2_pad.argtypes = sig + [ctypes.c_int]
+        L.orc_tconv_s2_pad.argtypes = sig + [ctypes.c_int]
         bsig = [_D, ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_long,
                 _D, ctypes.c_long, _D, _D, _D, _D]
         L.orc_conv_s2_bwd.argtypes = bsig
         L.orc_tconv_s2_bwd.argtypes = bsig
-        L.orc_forward.argtypes = [_D, _D, ctypes.c_long, ctypes.c_long, ctypes.c_long,
-                                  ctypes.c_int, _U8PP, _D, _D, _D, _D, _D, _D]
-        L.orc_backward.argtypes = [_D, _D, ctypes.c_long, ctypes.c_long, ctypes.c_long,
-                                   ctypes.c_int, _U8PP, _D, _D, _D, _D, _D, _D, _D, _D, _D]
+        L.orc_conv_s2_bwd_pad.argtypes = bsig + [ctypes.c_int]
+        L.orc_tconv_s2_bwd_pad.argtypes = bsig + [ctypes.c_int]
+        fsig = [_D, _D, ctypes.c_long, ctypes.c_long, ctypes.c_long,
+                ctypes.c_int, _U8PP, _D, _D, _D, _D, _D, _D]
+        L.orc_forward.argtypes = fsig
+        L.orc_forward_pad.argtypes = fsig + [ctypes.c_int]
+        bwsig = [_D, _D, ctypes.c_long, ctypes.c_long, ctypes.c_long,
+                 ctypes.c_int, _U8PP, _D, _D, _D, _D, _D, _D, _D, _D, _D]
+        L.orc_backward.argtypes = bwsig
+        L.orc_backward_pad.argtypes = bwsig + [ctypes.c_int]
         L.orc_l1.restype = ctypes.c_double
         L.orc_l1.argtypes = [_D, _D, ctypes.c_long, _D]
         L.orc_adam.argtypes = [_D, _D, _D, _D, ctypes.c_long, ctypes.c_long,
@@ -92,49 +100,51 @@ def layer_slices():
     return out
 
 
-def conv_s2(x, wt, b=None):
-    """Stride-2 3x3 convolution, x [N,H,W,Cin], wt [Cout,3,3,Cin] -> [N,H/2,W/2,Cout]."""
+def conv_s2(x, wt, b=None, circular=False):
+    """Stride-2 3x3 convolution, x [N,H,W,Cin], wt [Cout,3,3,Cin] -> [N,H/2,W/2,Cout].
+    circular: the width is periodic (columns taken mod W) instead of zero-padded."""
     x, wt = _f64(x), _f64(wt)
     n, h, w, ci = x.shape
     co = wt.shape[0]
     assert wt.shape == (co, 3, 3, ci)
     b = None if b is None else _f64(b)
     y = np.empty((n, h // 2, w // 2, co))
-    lib().orc_conv_s2(_p(x), n, h, w, ci, _p(wt), _p(b), co, _p(y))
+    lib().orc_conv_s2_pad(_p(x), n, h, w, ci, _p(wt), _p(b), co, _p(y), int(circular))
     return y
 
 
-def tconv_s2(x, wt, b=None):
-    """Stride-2 3x3 transposed convolution -> [N,2H,2W,Cout]."""
+def tconv_s2(x, wt, b=None, circular=False):
+    """Stride-2 3x3 transposed convolution -> [N,2H,2W,Cout] (circular: output
+    columns taken mod 2W)."""
     x, wt = _f64(x), _f64(wt)
     n, h, w, ci = x.shape
     co = wt.shape[0]
     assert wt.shape == (co, 3, 3, ci)
     b = None if b is None else _f64(b)
     y = np.empty((n, 2 * h, 2 * w, co))
-    lib().orc_tconv_s2(_p(x), n, h, w, ci, _p(wt), _p(b), co, _p(y))
+    lib().orc_tconv_s2_pad(_p(x), n, h, w, ci, _p(wt), _p(b), co, _p(y), int(circular))
     return y
 
 
-def conv_s2_bwd(x, wt, g, want_dx=True):
+def conv_s2_bwd(x, wt, g, want_dx=True, circular=False):
     x, wt, g = _f64(x), _f64(wt), _f64(g)
     n, h, w, ci = x.shape
     co = wt.shape[0]
     dw = np.empty_like(wt)
     db = np.empty(co)
     dx = np.empty_like(x) if want_dx else None
-    lib().orc_conv_s2_bwd(_p(x), n, h, w, ci, _p(wt), co, _p(g), _p(dw), _p(db), _p(dx))
+    lib().orc_conv_s2_bwd_pad(_p(x), n, h, w, ci, _p(wt), co, _p(g), _p(dw), _p(db), _p(dx), int(circular))
     return dw, db, dx
 
 
-def tconv_s2_bwd(x, wt, g, want_dx=True):
+def tconv_s2_bwd(x, wt, g, want_dx=True, circular=False):
     x, wt, g = _f64(x), _f64(wt), _f64(g)
     n, h, w, ci = x.shape
     co = wt.shape[0]
     dw = np.empty_like(wt)
     db = np.empty(co)
     dx = np.empty_like(x) if want_dx else None
-    lib().orc_tconv_s2_bwd(_p(x), n, h, w, ci, _p(wt), co, _p(g), _p(dw), _p(db), _p(dx))
+    lib().orc_tconv_s2_bwd_pad(_p(x), n, h, w, ci, _p(wt), co, _p(g), _p(dw), _p(db), _p(dx), int(circular))
     return dw, db, dx
 
 
@@ -157,8 +167,9 @@ def _mask_array(masks, keep):
     return ctypes.cast(arr, _U8PP)
 
 
-def forward(params, x, final_relu=False, masks=None):
-    """Whole autoencoder in FP64. Returns dict of h1,h2,h3,u3,u2,y."""
+def forward(params, x, final_relu=False, masks=None, circular=False):
+    """Whole autoencoder in FP64. Returns dict of h1,h2,h3,u3,u2,y.
+    circular: every layer's width is periodic (circular azimuth padding)."""
     params, x = _f64(params), _f64(x)
     n, h, w, c = x.shape
     assert c == 7 and h % 8 == 0 and w % 8 == 0
@@ -173,8 +184,8 @@ def forward(params, x, final_relu=False, masks=None):
     }
     keep = []
     mp = _mask_array(masks, keep)
-    lib().orc_forward(_p(params), _p(x), n, h, w, int(final_relu), mp,
-                      *[_p(acts[k]) for k in ACT_NAMES])
+    lib().orc_forward_pad(_p(params), _p(x), n, h, w, int(final_relu), mp,
+                          *[_p(acts[k]) for k in ACT_NAMES], int(circular))
     return acts
 
 
@@ -186,7 +197,7 @@ def l1(y, t):
     return float(loss), dy
 
 
-def backward(params, x, acts, dy, final_relu=False, masks=None, want_dx=False):
+def backward(params, x, acts, dy, final_relu=False, masks=None, want_dx=False, circular=False):
     """dL/dparams (flat) and optionally dL/dx, from a forward's activations."""
     params, x, dy = _f64(params), _f64(x), _f64(dy)
     n, h, w, _ = x.shape
@@ -195,15 +206,15 @@ def backward(params, x, acts, dy, final_relu=False, masks=None, want_dx=False):
     dx = np.empty_like(x) if want_dx else None
     keep = []
     mp = _mask_array(masks, keep)
-    lib().orc_backward(_p(params), _p(x), n, h, w, int(final_relu), mp,
-                       *[_p(a[k]) for k in ACT_NAMES], _p(dy), _p(dparams), _p(dx))
+    lib().orc_backward_pad(_p(params), _p(x), n, h, w, int(final_relu), mp,
+                           *[_p(a[k]) for k in ACT_NAMES], _p(dy), _p(dparams), _p(dx), int(circular))
     return dparams, dx
 
 
-def loss_and_grad(params, x, t, final_relu=False, masks=None, want_dx=False):
-    acts = forward(params, x, final_relu, masks)
+def loss_and_grad(params, x, t, final_relu=False, masks=None, want_dx=False, circular=False):
+    acts = forward(params, x, final_relu, masks, circular)
     loss, dy = l1(acts["y"], t)
-    dp, dx = backward(params, x, acts, dy, final_relu, masks, want_dx)
+    dp, dx = backward(params, x, acts, dy, final_relu, masks, want_dx, circular)
     return loss, dp, dx, acts
 
 
