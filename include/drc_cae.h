@@ -73,13 +73,25 @@ typedef enum { DRC_F32 = 0, DRC_BF16 = 1, DRC_FP8_E4M3 = 2 } drc_dtype;
  *                float32 accumulation; see drc_cae_calibrate_fp8.
  * final_relu = 1 applies relu to y (the paper's output stage has a ReLU,
  * Sec. 4.3); the default 0 keeps the output linear. Training calls require
- * final_relu = 0. */
+ * final_relu = 0.
+ * pad_w selects the padding of every layer along the width (azimuth):
+ *   DRC_PAD_ZERO     (default) zero padding 1, as along the height;
+ *   DRC_PAD_CIRCULAR the width is periodic, since a lat-long map of the
+ *                    hemisphere (Sec. 4.3) wraps around in azimuth: the
+ *                    convolution reads column (2q + kw - 1) mod W and the
+ *                    transposed convolution adds into column (2j + kw - 1)
+ *                    mod 2W; rows keep zero padding. Forward, backward and
+ *                    step run layer by layer (the whole-network kernels are
+ *                    zero-padding only). */
+typedef enum { DRC_PAD_ZERO = 0, DRC_PAD_CIRCULAR = 1 } drc_pad;
+
 typedef struct {
     int in_ch;
     int out_ch;
     int widths[3];
     int compute; /* drc_dtype */
     int final_relu;
+    int pad_w;   /* drc_pad */
 } drc_cae_desc;
 
 /* Adam hyper-parameters (PyTorch's Adam, Sec. 5: lr = 6e-5). Doubles, as
@@ -143,15 +155,17 @@ drc_status drc_cae_set_recompute(drc_cae* h, int on);
 drc_status drc_cae_saved_size(const drc_cae* h, int n, int H, int W, size_t* bytes,
                               int64_t offsets[5]);
 
-/* Forward path of BF16 handles on 32x32 and 64x64 maps (default 1).
+/* Forward path of BF16 and FP8 handles on 32x32 and 64x64 maps (default 1).
  * 1: one kernel runs the whole network per map with its activations in LDS
- * (HBM traffic is the FP32 input and output, one 64 KB staging copy of h1
- * at 64x64, and the activations a saving forward must keep); the
- * recompute of a training backward (h2 -> h3, u3, u2) runs the same way.
+ * (HBM traffic is the FP32 input and output, and for BF16 the activations
+ * a saving forward must keep); the recompute of a BF16 training backward
+ * (h2 -> h3, u3, u2) and its data gradients run the same way.
  * 0: one kernel per layer with activations in HBM. Both give bitwise equal
- * outputs and saved activations (same packs, K order and rounding). Other
- * precisions and sizes always run layer by layer. Errors:
- * DRC_ERR_INVALID_ARG for a NULL handle or on not in {0, 1}. */
+ * outputs and saved activations (same packs, K order and rounding). FP32
+ * and other sizes always run layer by layer, and so do handles with
+ * pad_w = DRC_PAD_CIRCULAR (created with 0). Errors: DRC_ERR_INVALID_ARG
+ * for a NULL handle or on not in {0, 1}; DRC_ERR_UNSUPPORTED for on = 1 on
+ * a circular-padding handle. */
 drc_status drc_cae_set_fused(drc_cae* h, int on);
 
 enum { DRC_WS_FORWARD = 1, DRC_WS_BACKWARD = 2, DRC_WS_STEP = 4, DRC_WS_CALIBRATE = 8, DRC_WS_AUTOTUNE = 16 };
@@ -217,6 +231,23 @@ drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, float* d_v, int
                         const drc_adam_cfg* adam, const float* d_x, const float* d_target,
                         float* d_loss, float* d_dparams, int n, int H, int W, void* d_ws,
                         size_t ws_bytes, void* stream);
+
+/* The training step on augmented maps (Sec. 5: the data loader rotates and
+ * flips the training maps; see drc_augment for the transformation): the
+ * result (loss, gradient, parameters, moments) is that of drc_cae_step on
+ * the maps drc_augment(d_x, d_target, d_roll, d_flip) would write, bit for
+ * bit, but no augmented copy is made: the first layer's input loaders (the
+ * forward's staging of x and the E1 weight gradient's) and the loss read
+ * x and the target through the rotation / mirror. d_roll, d_flip: int32
+ * [n] on the device. Implemented for the whole-network BF16 path (32x32
+ * and 64x64 maps, drc_cae_set_fused on, zero padding): other handles get
+ * DRC_ERR_UNSUPPORTED (use drc_augment and drc_cae_step). Other errors as
+ * drc_cae_step, and DRC_ERR_INVALID_ARG for a NULL or misaligned d_roll /
+ * d_flip. */
+drc_status drc_cae_step_aug(drc_cae* h, float* d_params, float* d_m, float* d_v, int64_t t,
+                            const drc_adam_cfg* adam, const float* d_x, const float* d_target,
+                            const int32_t* d_roll, const int32_t* d_flip, float* d_loss, float* d_dparams,
+                            int n, int H, int W, void* d_ws, size_t ws_bytes, void* stream);
 
 /* The training step of drc_cae_step recorded once as a HIP graph and
  * replayed, for training loops whose steps are short enough that launching

@@ -30,7 +30,10 @@ class DrcError(RuntimeError):
 
 class drc_cae_desc(ctypes.Structure):
     _fields_ = [("in_ch", ctypes.c_int), ("out_ch", ctypes.c_int), ("widths", ctypes.c_int * 3),
-                ("compute", ctypes.c_int), ("final_relu", ctypes.c_int)]
+                ("compute", ctypes.c_int), ("final_relu", ctypes.c_int), ("pad_w", ctypes.c_int)]
+
+
+DRC_PAD_ZERO, DRC_PAD_CIRCULAR = 0, 1
 
 
 class drc_adam_cfg(ctypes.Structure):
@@ -60,6 +63,8 @@ _SIGS = {
     "drc_cae_backward": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I, _VP, _SZ, _VP]),
     "drc_cae_step": (_I, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.POINTER(drc_adam_cfg), _VP, _VP,
                           _VP, _VP, _I, _I, _I, _VP, _SZ, _VP]),
+    "drc_cae_step_aug": (_I, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.POINTER(drc_adam_cfg), _VP, _VP,
+                              _VP, _VP, _VP, _VP, _I, _I, _I, _VP, _SZ, _VP]),
     "drc_cae_static_scratch_bytes": (_SZ, []),
     "drc_cae_forward_static": (_I, [_VP, _VP, _VP, _I, _I, _I, _VP]),
     "drc_cae_step_graph_create": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(drc_adam_cfg), _VP, _VP, _VP, _VP,
@@ -210,6 +215,13 @@ def drc_cae_step(h, params, m, v, t, adam, x, target, loss, dparams=None, ws=Non
     _check(lib().drc_cae_step(h, _ptr(params), _ptr(m), _ptr(v), int(t), ctypes.byref(adam), _ptr(x),
                               _ptr(target), _ptr(loss), _ptr(dparams), n, H, W, _ptr(ws), _nbytes(ws),
                               _stream(stream)))
+
+
+def drc_cae_step_aug(h, params, m, v, t, adam, x, target, roll, flip, loss, dparams=None, ws=None, stream=None):
+    n, H, W = _nhw(x, 7)
+    _check(lib().drc_cae_step_aug(h, _ptr(params), _ptr(m), _ptr(v), int(t), ctypes.byref(adam), _ptr(x),
+                                  _ptr(target), _ptr(roll), _ptr(flip), _ptr(loss), _ptr(dparams), n, H, W,
+                                  _ptr(ws), _nbytes(ws), _stream(stream)))
 
 
 def drc_cae_static_scratch_bytes():

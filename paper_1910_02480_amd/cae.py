@@ -17,14 +17,16 @@ def _aligned_bytes(nbytes: int, device) -> torch.Tensor:
 
 
 class CAE:
-    """One autoencoder handle (compute dtype 'f32', 'bf16' or 'fp8')."""
+    """One autoencoder handle (compute dtype 'f32', 'bf16' or 'fp8'; circular:
+    the width wraps around, circular azimuth padding)."""
 
     def __init__(self, compute: str = "bf16", params: torch.Tensor | None = None, device="cuda",
-                 final_relu: bool = False, recompute: bool = False):
+                 final_relu: bool = False, recompute: bool = False, circular: bool = False):
         self.device = torch.device(device)
         self.compute = compute
         desc = B.drc_cae_default_desc(B.DTYPES[compute])
         desc.final_relu = int(final_relu)
+        desc.pad_w = B.DRC_PAD_CIRCULAR if circular else B.DRC_PAD_ZERO
         with torch.cuda.device(self.device):
             self.h = B.drc_cae_create(desc)
         self.num_params = B.drc_cae_num_params(self.h)
@@ -123,12 +125,18 @@ class Trainer:
         self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
         cae.set_params(params)
 
-    def step(self, x, target, dparams=None):
+    def step(self, x, target, dparams=None, roll=None, flip=None):
+        """One step; with roll and flip (int32 [n] device tensors) on the
+        maps augmented by them, read through the loaders (drc_cae_step_aug)."""
         n, H, W, _ = x.shape
         ws = self.cae.workspace(n, H, W, B.DRC_WS_STEP)
         self.t += 1
-        B.drc_cae_step(self.cae.h, self.params, self.m, self.v, self.t, self.adam, x, target, self.loss,
-                       dparams, ws)
+        if roll is None:
+            B.drc_cae_step(self.cae.h, self.params, self.m, self.v, self.t, self.adam, x, target, self.loss,
+                           dparams, ws)
+        else:
+            B.drc_cae_step_aug(self.cae.h, self.params, self.m, self.v, self.t, self.adam, x, target, roll, flip,
+                               self.loss, dparams, ws)
         return self.loss
 
 

@@ -15,12 +15,12 @@
 #include <cmath>
 
 #include "drc_cae.h"
+#include "common.h"
 #include "internal.h"
 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr float kTwoPi = 6.28318530717958648f;
 
 struct AugArgs {
     const float* x;   // [n, H, W, 7]
@@ -38,22 +38,13 @@ __global__ __launch_bounds__(kThreads) void augment_kernel(AugArgs a) {
         const long row = i / a.W;                 // (map, row) index
         const int u = (int)(i - row * a.W);
         const long m = row / a.H;
-        int k = a.roll[m] % a.W;
-        if (k < 0) k += a.W;
-        const bool fl = a.flip[m] != 0;
-        int src = fl ? k - 1 - u : u - k;         // in (-2W, W)
-        if (src < 0) src += a.W;
-        if (src < 0) src += a.W;
-        const long j = row * a.W + src;
+        const drc::AugMap am = drc::aug_map(a.roll, a.flip, m, a.W);
+        const long j = row * a.W + drc::aug_src_col(am, u, a.W);
         const float* p = a.x + 7 * j;
         float v[7];
 #pragma unroll
         for (int c = 0; c < 7; ++c) v[c] = p[c];
-        float sn, cs;
-        sincosf(kTwoPi * (float)k / (float)a.W, &sn, &cs);
-        const float nx = v[3], ny = fl ? -v[4] : v[4];
-        v[3] = cs * nx - sn * ny;
-        v[4] = sn * nx + cs * ny;
+        drc::aug_normal(am, v[3], v[4]);
         float* q = a.xo + 7 * i;
 #pragma unroll
         for (int c = 0; c < 7; ++c) q[c] = v[c];

@@ -136,10 +136,12 @@ static __global__ void fp8_scale_kernel(const unsigned int* amax, float* scale, 
 
 // ------------------------------------------------------------------ L1 loss
 // dy = sign(y - t) * dscale (sign(0) = 0); partial[b] = sum |y - t| over the
-// block's fixed range, in double.
+// block's fixed range, in double. With roll / flip the target is read as
+// its augmented map (AugMap; maps of H x W x 3).
 static __global__ __launch_bounds__(256) void l1_partial_kernel(const float* y, const float* t, long count,
                                                          long per_block, float dscale, float* dy,
-                                                         double* partial) {
+                                                         double* partial, const int32_t* roll,
+                                                         const int32_t* flip, int H, int W) {
     // per_block = 16 elements per thread: four 16-byte loads of y and of t per
     // thread, all issued before the arithmetic (count is a multiple of 4)
     __shared__ double red[256];
@@ -151,7 +153,19 @@ static __global__ __launch_bounds__(256) void l1_partial_kernel(const float* y, 
         const long e = b0 + 4 * (threadIdx.x + 256 * k);
         const bool ok = e < count;
         yv[k] = ok ? *(const float4*)(y + e) : make_float4(0.f, 0.f, 0.f, 0.f);
-        tv[k] = ok ? *(const float4*)(t + e) : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (roll) {
+            float tt[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const long q = ok ? e + j : 0, p = q / 3, hw = (long)H * W;
+                const long m = p / hw, rem = p - m * hw, row = rem / W;
+                const int u = (int)(rem - row * W);
+                tt[j] = ok ? t[((m * H + row) * W + aug_src_col(roll, flip, m, u, W)) * 3 + (q - 3 * p)] : 0.0f;
+            }
+            tv[k] = make_float4(tt[0], tt[1], tt[2], tt[3]);
+        } else {
+            tv[k] = ok ? *(const float4*)(t + e) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -290,6 +304,7 @@ struct WgradArgs {
     const void* q;                  // gathered operand
     int q_raw, qc, qld;
     int nmaps, Hr, Wr, Hq, Wq;
+    int circ;                       // 1: gathered columns wrap (circular width), 0: zero outside
     long per_block;                 // reduction pixels per workgroup
     int jtiles;                     // tiles along j (blockIdx.y = jt + jtiles * pt)
     float* partial;                 // [slot = 4*chunk + wave][9*qc][pc]
@@ -386,7 +401,9 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
             }
 #pragma unroll
             for (int b = 0; b < JG; ++b) {
-                const int i = 2 * uu + tkh[b] - 1, jj = 2 * vv + tkw[b] - 1;
+                const int i = 2 * uu + tkh[b] - 1;
+                int jj = 2 * vv + tkw[b] - 1;
+                if (a.circ && jj < 0) jj += a.Wq;  // only column -1 falls outside
                 const bool in = ok && (unsigned)i < (unsigned)a.Hq && (unsigned)jj < (unsigned)a.Wq;
                 ld_vec<T, VEC>(a.q, a.q_raw, (((long)n * a.Hq + (in ? i : 0)) * a.Wq + (in ? jj : 0)) * a.qld + tch[b],
                                in ? jav[b] : 0, qv[buf][u][b]);
@@ -469,6 +486,7 @@ struct WgradBArgs {
     const void* q;                  // gathered operand: bf16, or float32 when q_raw
     int q_raw, qc, qld;
     int nmaps, Hr, Wr, Hq, Wq;
+    int circ;                       // 1: gathered column -1 is column Wq - 1 (circular width)
     int R, strips_per_map, total_strips, strips_per_chunk;
     int qcs;                        // LDS elements per staged channel (padded)
     float* partial;                 // [chunk][9*qc][pc]
@@ -521,11 +539,12 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradBArgs a) {
                 const int rest = e / CG;
                 const int colp = rest % ncols, row = rest / ncols;
                 const int qi = 2 * u0 - 1 + row, qj = colp - 1;
+                const int qs = (a.circ && qj < 0) ? qj + a.Wq : qj;  // column read
                 float v8[8];
 #pragma unroll
                 for (int k = 0; k < 8; ++k) v8[k] = 0.0f;
-                if ((unsigned)qi < (unsigned)a.Hq && (unsigned)qj < (unsigned)a.Wq) {
-                    const long base = (((long)n * a.Hq + qi) * a.Wq + qj) * a.qld + cg * 8;
+                if ((unsigned)qi < (unsigned)a.Hq && (unsigned)qs < (unsigned)a.Wq) {
+                    const long base = (((long)n * a.Hq + qi) * a.Wq + qs) * a.qld + cg * 8;
                     if (a.q_raw) {
 #pragma unroll
                         for (int k = 0; k < 8; ++k)
@@ -571,7 +590,8 @@ __global__ __launch_bounds__(256) void wgrad_bf16_kernel(WgradBArgs a) {
                 uint4 col[17];
 #pragma unroll
                 for (int t = 0; t < 17; ++t) {
-                    const int qj = 16 * cb - 1 + t;
+                    int qj = 16 * cb - 1 + t;
+                    if (a.circ && qj < 0) qj += a.Wq;
                     col[t] = make_uint4(0, 0, 0, 0);
                     if (row_ok && (unsigned)qj < (unsigned)a.Wq) {
                         const long base = (((long)n * a.Hq + qi) * a.Wq + qj) * a.qld + cg * 8;
@@ -679,8 +699,11 @@ struct WgradTArgs {
     const void* q;                  // gathered operand: bf16, or float32 with QR channels
     int qc, qld;                    // channels (QC, or QR when float32), elements per pixel
     int Hr, Wr, Hq, Wq;
+    int circ;                       // 1: column -1 is column Wq - 1 of the same row (circular width)
     int R, strips_per_map, total_strips, strips_per_chunk;
     float* partial;                 // [chunk][9*qc][pc]
+    const int32_t* roll;            // float32 x read augmented (AugMap of each map), or null
+    const int32_t* flip;
 };
 
 typedef short v4i16 __attribute__((ext_vector_type(4)));
@@ -757,7 +780,39 @@ __global__ __launch_bounds__(64 * NW) void wgrad_tr_kernel(WgradTArgs a) {
         const int n = s / a.strips_per_map;
         const int u0 = (s - n * a.strips_per_map) * R;
         const long base = ((long)n * a.Hq + 2 * u0 - 1) * Wq * a.qld;
-        if constexpr (QR > 0) {
+        bool gathered = false;
+        if constexpr (QR == 7) {
+            if (a.roll) {
+                // augmented x: float f of a gathered row is channel f % 7 of
+                // augmented column f / 7, read from its source column; the
+                // normal's channels are turned (both read, one kept)
+                const AugMap am = aug_map(a.roll, a.flip, n, Wq);
+#pragma unroll
+                for (int t = 0; t < TG; ++t) {
+                    const int e = threadIdx.x + NT * t;
+                    const int r = (4 * e) / rowf;
+                    const int qi = 2 * u0 - 1 + r;
+                    const bool ok = e < ntq && (unsigned)qi < (unsigned)a.Hq;
+                    const float* xrow = (const float*)a.q + ((long)n * a.Hq + (ok ? qi : 0)) * rowf;
+                    float f[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int fi = ok ? 4 * e + j - r * rowf : 0;
+                        const int u = fi / 7, c = fi - 7 * (fi / 7);
+                        const float* px = xrow + aug_src_col(am, u, Wq) * 7;
+                        float nx = px[3], ny = px[4];
+                        aug_normal(am, nx, ny);
+                        const float v = px[c];
+                        f[j] = ok ? (c == 3 ? nx : (c == 4 ? ny : v)) : 0.0f;
+                    }
+                    vf[t] = make_float4(f[0], f[1], f[2], f[3]);
+                }
+                gathered = true;
+            }
+        }
+        if (gathered) {
+            // (the augmented gather above)
+        } else if constexpr (QR > 0) {
             // every lane loads (rows outside the map read the operand's first
             // chunk and are zeroed): a load under a per-lane condition would
             // make the compiler wait for all loads in flight
@@ -842,13 +897,17 @@ __global__ __launch_bounds__(64 * NW) void wgrad_tr_kernel(WgradTArgs a) {
             }
             const uint16_t* gb = Gs + (2 * ul * Wq + 2 * (v0 + jq)) * GS;
             const bool left = v0 + jq == 0;  // column -1 for kw == 0
+            // (circular width: column -1 is the last column of the same staged row)
             // every owned row block's fragment is read before the first MFMA so
             // that the LDS latencies overlap; blocks past the last (tap,
             // channel) row read the zero block and their sums are never stored
             uint4 afr[JBW];
 #pragma unroll
             for (int i = 0; i < JBW; ++i) {
-                const uint2 lo = lds_read_tr16(!alane[i] || (left && akw0[i]) ? zero + 4 * qq : gb + aoff[i]);
+                const uint16_t* lo_p = !alane[i] ? zero + 4 * qq
+                                                 : (left && akw0[i] ? (a.circ ? gb + aoff[i] + Wq * GS : zero + 4 * qq)
+                                                                    : gb + aoff[i]);
+                const uint2 lo = lds_read_tr16(lo_p);
                 const uint2 hi = lds_read_tr16(alane[i] ? gb + aoff[i] + 8 * GS : zero + 4 * qq);
                 afr[i] = make_uint4(lo.x, lo.y, hi.x, hi.y);
             }

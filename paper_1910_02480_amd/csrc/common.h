@@ -136,4 +136,52 @@ template <typename V> __device__ __forceinline__ V vzero() {
     return v;
 }
 
+// ---------------------------------------------------------------- training augmentation
+// A symmetry of the hemispherical lat-long map (Sec. 5: the loader rotates
+// and flips the training maps; read as rotations about the normal by whole
+// columns and mirror images through a plane containing it). Map m is turned
+// by k = roll[m] mod W columns and mirrored when flip[m] != 0: augmented
+// column u holds source column (u - k) mod W, or (k - 1 - u) mod W when
+// mirrored, with the normal's (Nx, Ny) reflected (Ny -> -Ny) when mirrored
+// and then rotated by 2 pi k / W; the other channels and the target keep
+// their values. Every reader of augmented maps (the augmentation kernel and
+// the loaders that apply it on the fly) uses these helpers, so they agree
+// bit for bit.
+struct AugMap {
+    int k;
+    bool flip;
+    float cs, sn;
+};
+__device__ __forceinline__ AugMap aug_map(const int32_t* roll, const int32_t* flip, long m, int W) {
+    AugMap a;
+    int k = roll[m] % W;
+    if (k < 0) k += W;
+    a.k = k;
+    a.flip = flip[m] != 0;
+    sincosf(6.28318530717958648f * (float)k / (float)W, &a.sn, &a.cs);
+    return a;
+}
+// Source column of augmented column u (0 <= u < W).
+__device__ __forceinline__ int aug_src_col(const AugMap& a, int u, int W) {
+    int s = a.flip ? a.k - 1 - u : u - a.k;  // in (-2W, W)
+    if (s < 0) s += W;
+    if (s < 0) s += W;
+    return s;
+}
+// Source column for channels that only move (the target map): no rotation.
+__device__ __forceinline__ int aug_src_col(const int32_t* roll, const int32_t* flip, long m, int u, int W) {
+    AugMap a;
+    int k = roll[m] % W;
+    if (k < 0) k += W;
+    a.k = k;
+    a.flip = flip[m] != 0;
+    return aug_src_col(a, u, W);
+}
+// Channels 3 and 4 (Nx, Ny) of a moved pixel, in place.
+__device__ __forceinline__ void aug_normal(const AugMap& a, float& nx, float& ny) {
+    const float x = nx, y = a.flip ? -ny : ny;
+    nx = fmaf(a.cs, x, -(a.sn * y));
+    ny = fmaf(a.sn, x, a.cs * y);
+}
+
 }  // namespace drc

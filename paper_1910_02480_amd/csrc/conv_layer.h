@@ -86,6 +86,7 @@ struct ClassGeom {
     const long* in_off;  // raw float input: element offset of each map (null: packed)
     Seg seg0, seg1;
     const long* out_off; // float32 output: element offset of each map (null: packed)
+    int circ;            // 1: the width is periodic (circular padding), 0: zero padding
 };
 
 constexpr int kMaxClasses = 4;
@@ -130,8 +131,12 @@ struct PixState {
     long opix;        // output pixel index (n, oi, oj) in the packed output
     long oloc;        // output pixel index inside its map (oi * Wout + oj)
     int n;
+    int jl, jr;       // column steps to the left / right neighbour (+-1, or across the seam when circular)
     bool v, up, down, left, right;
 };
+
+// Column step of tap offset dj in {-1, 0, 1}.
+__device__ __forceinline__ int col_step(const PixState& ps, int dj) { return dj < 0 ? ps.jl : (dj > 0 ? ps.jr : 0); }
 
 // float -> storage type with hardware RNE for bfloat16.
 template <int P>
@@ -251,8 +256,9 @@ __device__ __forceinline__ typename Traits<P>::V gather_nb(const ClassGeom& G, c
     typedef typename Traits<P>::V V;
     const int di = nb >> 1, dj = nb & 1;
     if (!ps.v || (di && !ps.down) || (dj && !ps.right)) return vzero<V>();
-    const T* src = (c < C0) ? (const T*)G.s0.p + ps.off0 + di * rowd0 + dj * G.s0.ld + c
-                            : (const T*)G.s1.p + ps.off1 + di * rowd1 + dj * G.s1.ld + (c - C0);
+    const int cj = dj ? ps.jr : 0;
+    const T* src = (c < C0) ? (const T*)G.s0.p + ps.off0 + di * rowd0 + cj * G.s0.ld + c
+                            : (const T*)G.s1.p + ps.off1 + di * rowd1 + cj * G.s1.ld + (c - C0);
     return *(const V*)src;
 }
 
@@ -270,9 +276,11 @@ __device__ __forceinline__ void pix_setup(const ClassGeom& G, long pix, long t0,
     const int bj = (MODE == M_CONV) ? 2 * Q_ : Q_;
     ps.n = n;
     ps.up = bi > 0;
-    ps.left = bj > 0;
+    ps.left = bj > 0 || G.circ;
     ps.down = bi + 1 < G.Hin;
-    ps.right = bj + 1 < G.Win;
+    ps.right = bj + 1 < G.Win || G.circ;
+    ps.jl = bj > 0 ? -1 : G.Win - 1;
+    ps.jr = bj + 1 < G.Win ? 1 : 1 - G.Win;
     const long ploc = (long)bi * G.Win + bj;
     if constexpr (RAW) {
         const long base = G.in_off ? G.in_off[n] : (long)n * G.Hin * G.Win * G.s0.ld;
@@ -343,7 +351,7 @@ __device__ __forceinline__ typename Traits<P>::V gather(const ClassGeom& G, int 
             }
         const bool ok = ps.v && t < NT && (di < 0 ? ps.up : (di > 0 ? ps.down : true)) &&
                         (dj < 0 ? ps.left : (dj > 0 ? ps.right : true));
-        const float* src = (const float*)G.s0.p + ps.off0 + (ok ? di * rowd0 + dj * G.s0.ld : 0);
+        const float* src = (const float*)G.s0.p + ps.off0 + (ok ? di * rowd0 + col_step(ps, dj) * G.s0.ld : 0);
         float f[VW];
 #pragma unroll
         for (int e = 0; e < VW; ++e) f[e] = src[min(c + e, raw_c - 1)];  // stays inside the pixel
@@ -369,10 +377,10 @@ __device__ __forceinline__ typename Traits<P>::V gather(const ClassGeom& G, int 
                         (dj < 0 ? ps.left : (dj > 0 ? ps.right : true));
         const T* src;
         if constexpr (C0 >= CIN) {
-            src = (const T*)G.s0.p + ps.off0 + (ok ? di * rowd0 + dj * G.s0.ld : 0) + c;
+            src = (const T*)G.s0.p + ps.off0 + (ok ? di * rowd0 + col_step(ps, dj) * G.s0.ld : 0) + c;
         } else {
-            src = (c < C0) ? (const T*)G.s0.p + ps.off0 + (ok ? di * rowd0 + dj * G.s0.ld : 0) + c
-                           : (const T*)G.s1.p + ps.off1 + (ok ? di * rowd1 + dj * G.s1.ld : 0) + (c - C0);
+            src = (c < C0) ? (const T*)G.s0.p + ps.off0 + (ok ? di * rowd0 + col_step(ps, dj) * G.s0.ld : 0) + c
+                           : (const T*)G.s1.p + ps.off1 + (ok ? di * rowd1 + col_step(ps, dj) * G.s1.ld : 0) + (c - C0);
         }
         const V val = *(const V*)src;
         return ok ? val : v;
@@ -399,13 +407,13 @@ __device__ __forceinline__ typename Traits<P>::V gather(const ClassGeom& G, int 
         const bool ok = (di < 0 ? ps.up : (di > 0 ? ps.down : true)) && (dj < 0 ? ps.left : (dj > 0 ? ps.right : true));
         if (!ok) continue;
         if constexpr (RAW) {
-            const float* src = (const float*)G.s0.p + ps.off0 + di * rowd0 + dj * G.s0.ld;
+            const float* src = (const float*)G.s0.p + ps.off0 + di * rowd0 + col_step(ps, dj) * G.s0.ld;
 #pragma unroll
             for (int e = 0; e < SUB; ++e)
                 if (c + e < raw_c) tmp[s * SUB + e] = to_store<P>(src[c + e], raw_qscale);
         } else {
-            const T* src = (c < C0) ? (const T*)G.s0.p + ps.off0 + di * rowd0 + dj * G.s0.ld + c
-                                    : (const T*)G.s1.p + ps.off1 + di * rowd1 + dj * G.s1.ld + (c - C0);
+            const T* src = (c < C0) ? (const T*)G.s0.p + ps.off0 + di * rowd0 + col_step(ps, dj) * G.s0.ld + c
+                                    : (const T*)G.s1.p + ps.off1 + di * rowd1 + col_step(ps, dj) * G.s1.ld + (c - C0);
             if constexpr (NSUB == 1) {
                 return *(const V*)src;
             } else {

@@ -115,6 +115,7 @@ extern "C" drc_cae_desc drc_cae_default_desc(int compute) {
     d.widths[2] = 128;
     d.compute = compute;
     d.final_relu = 0;
+    d.pad_w = DRC_PAD_ZERO;
     return d;
 }
 
@@ -129,8 +130,11 @@ extern "C" drc_status drc_cae_create(const drc_cae_desc* desc, drc_cae** out) {
         return drc_fail(DRC_ERR_INVALID_ARG, "create: unknown compute dtype %d", desc->compute);
     if (desc->final_relu != 0 && desc->final_relu != 1)
         return drc_fail(DRC_ERR_INVALID_ARG, "create: final_relu must be 0 or 1");
+    if (desc->pad_w != DRC_PAD_ZERO && desc->pad_w != DRC_PAD_CIRCULAR)
+        return drc_fail(DRC_ERR_INVALID_ARG, "create: pad_w must be DRC_PAD_ZERO or DRC_PAD_CIRCULAR");
     drc_cae* h = new drc_cae();
     h->desc = *desc;
+    h->fused = desc->pad_w == DRC_PAD_ZERO;  // the whole-network kernels pad with zeros
     h->prec = desc->compute;
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
@@ -216,6 +220,8 @@ extern "C" drc_status drc_cae_set_recompute(drc_cae* h, int on) {
 extern "C" drc_status drc_cae_set_fused(drc_cae* h, int on) {
     if (!h) return drc_fail(DRC_ERR_INVALID_ARG, "set_fused: handle is NULL");
     if (on != 0 && on != 1) return drc_fail(DRC_ERR_INVALID_ARG, "set_fused: on must be 0 or 1");
+    if (on && h->desc.pad_w != DRC_PAD_ZERO)
+        return drc_fail(DRC_ERR_UNSUPPORTED, "set_fused: the whole-network kernels use zero padding only");
     h->fused = on;
     h->gen++;
     return DRC_OK;

@@ -47,6 +47,8 @@ struct FusedArgs {
     const float* b[6];
     char* save[5];       // optional: h1 h2 h3 u3 u2 of every map, plain NHWC BF16 (null = not kept)
     int final_relu;
+    const int32_t* roll;  // augmentation of the input (AUG kernels): per-map column roll and mirror flag
+    const int32_t* flip;
 };
 
 // Byte offset of 16-byte chunk `chunk` of pixel (y, x) in an LDS tensor of C
@@ -154,6 +156,27 @@ __device__ __forceinline__ void stage_x(char* smem, int xs, const float* xm) {
     }
 }
 
+// stage_x for an augmented map (a rotation / mirror of the input, see
+// AugMap): each thread gathers whole source pixels of a row (7 floats) and
+// turns their normals; the BF16 packing is stage_x's.
+template <int H, int W>
+__device__ __forceinline__ void stage_x_aug(char* smem, int xs, const float* xm, const AugMap& am) {
+    for (int p = opaque_tid(); p < H * W; p += FT) {
+        const int row = (int)((unsigned)p / W), u = (int)((unsigned)p % W);
+        const float* src = xm + ((long)row * W + aug_src_col(am, u, W)) * 7;
+        float f[7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) f[c] = src[c];
+        aug_normal(am, f[3], f[4]);
+        uint4 o;
+        o.x = pack_bf16x2(f[0], f[1]);
+        o.y = pack_bf16x2(f[2], f[3]);
+        o.z = pack_bf16x2(f[4], f[5]);
+        o.w = pack_bf16x2(f[6], 0.0f);
+        *(uint4*)(smem + xs + p * 16) = o;
+    }
+}
+
 // The next map's input, staged while the decoder runs. After D2 band b has
 // read them, rows [4b, 4b + 4) of h2 (region R1) and of u3 (region R2) are
 // dead; the x staging region R1 + R2 holds x row r at 16 W r bytes, so those
@@ -196,6 +219,29 @@ __device__ __forceinline__ void x_piece_store(char* smem, int xs, const XPiece& 
             *(uint4*)(smem + xs + (row * W + col + px) * 16) = o;
         }
     }
+}
+
+// The x pieces of an augmented map: the two pixels' sources are gathered
+// separately; their normals are turned when the piece is stored.
+template <int H, int W>
+__device__ __forceinline__ void x_piece_load_aug(XPiece& xp, const float* xm, int band, const AugMap& am) {
+    int row, col;
+    if (x_piece_pair<H, W>(band, row, col)) {
+        float* f = (float*)xp.v;
+#pragma unroll
+        for (int px = 0; px < 2; ++px) {
+            const float* src = xm + ((long)row * W + aug_src_col(am, col + px, W)) * 7;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) f[7 * px + c] = src[c];
+        }
+    }
+}
+template <int H, int W>
+__device__ __forceinline__ void x_piece_store_aug(char* smem, int xs, XPiece& xp, int band, const AugMap& am) {
+    float* f = (float*)xp.v;
+    aug_normal(am, f[3], f[4]);
+    aug_normal(am, f[10], f[11]);
+    x_piece_store<H, W>(smem, xs, xp, band);
 }
 
 // Stride-2 3x3 convolution, LDS -> LDS, bias + ReLU (E1, E2, E3). Weights:
@@ -599,7 +645,7 @@ struct FusedLds {
 // throughout.
 // MID = true: the recompute of a training backward, h2 (read from save[1])
 // -> h3, u3, u2 (written to save[2..4]); E1, E2 and D1 are skipped.
-template <int H, int W, bool MID>
+template <int H, int W, bool MID, bool AUG>
 __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a) {
     // static LDS: its address is a compile-time constant, so LDS offsets fold
     // into the instructions' immediate fields (a dynamic array's base is added
@@ -632,7 +678,12 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
             float* ym = a.y + (a.y_off ? a.y_off[m] : (long)m * HW * 3);
             const int mn = m + gridDim.x;  // this workgroup's next map
             const float* xn = mn < a.nmaps ? a.x + (a.x_off ? a.x_off[mn] : (long)mn * HW * 7) : nullptr;
-            if (!staged) stage_x<H, W>(smem, R1, xm);
+            AugMap amn;  // augmentation of the next map
+            if constexpr (AUG) amn = aug_map(a.roll, a.flip, xn ? mn : m, W);
+            if (!staged) {
+                if constexpr (AUG) stage_x_aug<H, W>(smem, R1, xm, aug_map(a.roll, a.flip, m, W));
+                else stage_x<H, W>(smem, R1, xm);
+            }
             __syncthreads();
             conv_phase<H, W, 8, 32, 2, E1N>(smem, R1, ZO, a.w[0], a.b[0], LdsOut<32, W / 2>{smem, R0});
             __syncthreads();
@@ -661,7 +712,10 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
                     const int pix0 = band * L::BAND * (W / 4);
                     const LdsOut<32, W / 2> ring{smem, R3};
                     XPiece xp;
-                    if (xn) x_piece_load<H, W>(xp, xn, band);  // in flight during D2's MFMAs
+                    if (xn) {  // in flight during D2's MFMAs
+                        if constexpr (AUG) x_piece_load_aug<H, W>(xp, xn, band, amn);
+                        else x_piece_load<H, W>(xp, xn, band);
+                    }
                     if (set == 0)
                         pairs_tiles<H / 4, W / 4, 64, 64, 32, 1, D2BN, 0, D2BPB, L::RING>(
                             P2, smem, R2, R1, ZO, tr, wave / NG, FW / NG, pix0, ring);
@@ -669,7 +723,10 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
                         pairs_tiles<H / 4, W / 4, 64, 64, 32, 1, D2BN, 1, D2BPB, L::RING>(
                             P2, smem, R2, R1, ZO, tr, wave / NG, FW / NG, pix0, ring);
                     __syncthreads();
-                    if (xn) x_piece_store<H, W>(smem, R1, xp, band);
+                    if (xn) {
+                        if constexpr (AUG) x_piece_store_aug<H, W>(smem, R1, xp, band, amn);
+                        else x_piece_store<H, W>(smem, R1, xp, band);
+                    }
                     const int u0 = 2 * L::BAND * band;  // first u2 row of the band
                     if (a.save[4]) copy_rows_out<32, WU, L::RING>(a.save[4] + m * B5, smem, R3, u0, 2 * L::BAND);
                     // u2 rows [r0, r1): all rows of the band whose lower neighbour is
@@ -969,7 +1026,10 @@ drc_status launch_dgrad(const DgradArgs& a, int grid, hipStream_t s) {
 
 template <int H, int W, bool MID>
 drc_status launch_fused(const FusedArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((cae_fused_forward_kernel<H, W, MID>), dim3(grid), dim3(FT), 0, s, a);
+    if (!MID && a.roll)
+        hipLaunchKernelGGL((cae_fused_forward_kernel<H, W, false, true>), dim3(grid), dim3(FT), 0, s, a);
+    else
+        hipLaunchKernelGGL((cae_fused_forward_kernel<H, W, MID, false>), dim3(grid), dim3(FT), 0, s, a);
     return check_launch("fused forward");
 }
 
@@ -1002,11 +1062,15 @@ size_t fused_forward_scratch(const drc_cae*, int, int, int) { return 0; }
 
 drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int W, const long* x_off,
                          const long* y_off, void* scratch, size_t scratch_bytes, hipStream_t s,
-                         char* const* save) {
+                         char* const* save, const int32_t* roll, const int32_t* flip) {
     if (h->prec != P_BF16 || !fused_forward_size(H, W))
         return drc_fail(DRC_ERR_UNSUPPORTED, "fused forward: BF16 maps of 32x32 or 64x64 only");
+    if ((roll != nullptr) != (flip != nullptr) || (roll && x_off))
+        return drc_fail(DRC_ERR_INVALID_ARG, "fused forward: augmentation needs roll and flip and packed maps");
     if (n < 1) return DRC_OK;
     FusedArgs a = fused_args(h, n);
+    a.roll = roll;
+    a.flip = flip;
     if (save)
         for (int k = 0; k < 5; ++k) a.save[k] = save[k];
     (void)scratch_bytes;

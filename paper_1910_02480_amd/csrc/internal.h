@@ -177,7 +177,8 @@ drc_status fused_fp8_forward(drc_cae* h, const float* x, float* y, int n, int H,
                              const long* y_off, hipStream_t s);
 drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int W, const long* x_off,
                          const long* y_off, void* scratch, size_t scratch_bytes, hipStream_t s,
-                         char* const* save = nullptr);
+                         char* const* save = nullptr, const int32_t* roll = nullptr,
+                         const int32_t* flip = nullptr);
 // h2 -> h3, u3, u2 (the layers a recomputing backward rebuilds), all plain NHWC.
 drc_status fused_recompute(drc_cae* h, int n, int H, int W, const void* h2, void* h3, void* u3, void* u2,
                            hipStream_t s);

@@ -84,7 +84,7 @@ static Seg seg_out(void* dst, int c, int relu, float qscale) {
 }
 
 // Geometry of layer l's forward (or backward-data) GEMM for n maps of H x W.
-ClassGeom class_geom(int l, int n, int H, int W, bool bwd) {
+ClassGeom class_geom(int l, int n, int H, int W, bool bwd, int circ) {
     ClassGeom G;
     memset(&G, 0, sizeof G);
     int hin, win, hout, wout;
@@ -103,6 +103,7 @@ ClassGeom class_geom(int l, int n, int H, int W, bool bwd) {
     G.Wg = gemm_tconv ? win : wout;
     G.seg0 = seg_none();
     G.seg1 = seg_none();
+    G.circ = circ;
     return G;
 }
 
@@ -200,9 +201,9 @@ drc_status forward_classes(drc_cae* h, void* const* packs, const FwdClass* fc, i
         a.nclass = nclass;
         int npw = 0;
         // BF16 and FP8 E1 and D1: input rows staged in LDS by bands
-        bool band = P != P_F32 && (l == 0 || l == 5);
+        bool band = P != P_F32 && (l == 0 || l == 5) && h->desc.pad_w == DRC_PAD_ZERO;
         for (int c = 0; c < nclass; ++c) {
-            a.cls[c] = class_geom(l, fc[c].n, fc[c].H, fc[c].W, false);
+            a.cls[c] = class_geom(l, fc[c].n, fc[c].H, fc[c].W, false, h->desc.pad_w);
             fwd_tensors(l, fc[c].b, h->desc.final_relu, qout, a.cls[c]);
             a.cls[c].tile_px = fc[c].tile_px[l];
             if (a.cls[c].tile_px <= 0) {
@@ -340,11 +341,15 @@ static drc_status bias_grad(const void* g, bool g_raw, int C, long npix, float* 
 // for D2 and D1; float32 x with a_raw_c channels for E1).
 template <typename T>
 static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_raw, Src s0, Src s1,
-                              int a_raw_c, float* partial, float* out, float scale, hipStream_t s) {
+                              int a_raw_c, float* partial, float* out, float scale, int circ, hipStream_t s,
+                              const int32_t* roll = nullptr, const int32_t* flip = nullptr) {
     const LayerDef& L = kLayers[l];
     const WgradPlan wp = wgrad_plan(l, n, H, W, sizeof(T) == 2 ? P_BF16 : P_F32);
     int hin, win, hout, wout;
     layer_io(l, H, W, &hin, &win, &hout, &wout);
+    // an augmented x is read by the transposed-read kernel's float32 staging only
+    if (roll && !(l == 0 && wp.tr && wp.QR == 7))
+        return drc_fail(DRC_ERR_UNSUPPORTED, "weight_grad: no augmented loader for layer %d's plan", l);
     if (wp.tr) {
         WgradTArgs b;
         memset(&b, 0, sizeof b);
@@ -357,12 +362,15 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
         }
         b.Hr = wp.Hr;
         b.Wr = wp.Wr;
+        b.circ = circ;
         b.R = wp.R;
         b.strips_per_map = wp.strips_per_map;
         b.total_strips = wp.total_strips;
         b.strips_per_chunk = wp.strips_per_chunk;
         b.partial = partial;
         b.qc = wp.qc;
+        b.roll = roll;
+        b.flip = flip;
         const bool raw = wp.QR > 0;
         if (raw != (l == 0 ? a_raw_c > 0 : (l == 5 ? g_raw : false)))
             return drc_fail(DRC_ERR_STATE, "weight_grad: operand type does not fit the plan of layer %d", l);
@@ -406,6 +414,7 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
         b.nmaps = n;
         b.Hr = wp.Hr;
         b.Wr = wp.Wr;
+        b.circ = circ;
         b.R = wp.R;
         b.strips_per_map = wp.strips_per_map;
         b.total_strips = wp.total_strips;
@@ -458,6 +467,7 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
     a.nmaps = n;
     a.Hr = wp.Hr;
     a.Wr = wp.Wr;
+    a.circ = circ;
     a.per_block = wp.per_block;
     a.jtiles = wp.jtiles;
     a.partial = partial;
@@ -484,6 +494,8 @@ struct BwdBufs {
     float* dx;
     char* ws;
     BwdLayout L;
+    const int32_t* roll = nullptr;  // x is read augmented (AugMap) by E1's weight gradient
+    const int32_t* flip = nullptr;
 };
 
 template <int P>
@@ -507,6 +519,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
     // the large-LDS weight-gradient kernels do not share CUs and the forks
     // made the 256-map training step 7 % slower.
     constexpr bool kFork = P == P_F32;
+    const int circ = h->desc.pad_w;  // circular width: every gather wraps columns
     auto wgrad_on = [&](int l, auto&& launch) -> drc_status {
         hipStream_t ss = kFork ? h->side[l % drc_cae::kSide] : s;
         if (kFork) {
@@ -531,7 +544,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         const GemmGeom g = gemm_geom(5, true, P);
         LayerArgs a = layer_args(h->wb[5], g.kstride);
         ClassGeom& G = a.cls[0];
-        G = class_geom(5, n, H, W, true);
+        G = class_geom(5, n, H, W, true, circ);
         G.s0 = {b.dy, g.cin_eff, 3};
         a.raw_c = 3;
         G.seg0 = seg_out(dz_u2, 32, 0, 1.0f);
@@ -543,7 +556,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         prof_end(h, tok, s); }
         TRY(wgrad_on(5, [&](float* wpart, hipStream_t ss) {
             return weight_grad<T>(5, n, H, W, b.dy, true, Src{b.u2, 32, 32}, Src{b.h1, 32, 32}, 0, wpart,
-                                  dp + layer_w_offset(5), gscale, ss);
+                                  dp + layer_w_offset(5), gscale, circ, ss);
         }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(b.dy, true, 3, as.p0, bpart, dp + layer_b_offset(5), gscale, s));
@@ -554,7 +567,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         const GemmGeom g = gemm_geom(4, true, P);
         LayerArgs a = layer_args(h->wb[4], g.kstride);
         ClassGeom& G = a.cls[0];
-        G = class_geom(4, n, H, W, true);
+        G = class_geom(4, n, H, W, true, circ);
         G.s0 = {dz_u2, 32, 32};
         G.seg0 = seg_out(dz_u3, 64, 0, 1.0f);
         G.seg0.mask = b.u3;
@@ -565,7 +578,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         prof_end(h, tok, s); }
         TRY(wgrad_on(4, [&](float* wpart, hipStream_t ss) {
             return weight_grad<T>(4, n, H, W, dz_u2, false, Src{b.u3, 64, 64}, Src{b.h2, 64, 64}, 0, wpart,
-                                  dp + layer_w_offset(4), gscale, ss);
+                                  dp + layer_w_offset(4), gscale, circ, ss);
         }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_u2, false, 32, as.p1, bpart, dp + layer_b_offset(4), gscale, s));
@@ -576,7 +589,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         const GemmGeom g = gemm_geom(3, true, P);
         LayerArgs a = layer_args(h->wb[3], g.kstride);
         ClassGeom& G = a.cls[0];
-        G = class_geom(3, n, H, W, true);
+        G = class_geom(3, n, H, W, true, circ);
         G.s0 = {dz_u3, 64, 64};
         G.seg0 = seg_out(dz_h3, 128, 0, 1.0f);
         G.seg0.mask = b.h3;
@@ -586,7 +599,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         prof_end(h, tok, s); }
         TRY(wgrad_on(3, [&](float* wpart, hipStream_t ss) {
             return weight_grad<T>(3, n, H, W, dz_u3, false, Src{b.h3, 128, 128}, Src{nullptr, 0, 0}, 0, wpart,
-                                  dp + layer_w_offset(3), gscale, ss);
+                                  dp + layer_w_offset(3), gscale, circ, ss);
         }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_u3, false, 64, as.p2, bpart, dp + layer_b_offset(3), gscale, s));
@@ -597,7 +610,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         const GemmGeom g = gemm_geom(2, true, P);
         LayerArgs a = layer_args(h->wb[2], g.kstride);
         ClassGeom& G = a.cls[0];
-        G = class_geom(2, n, H, W, true);
+        G = class_geom(2, n, H, W, true, circ);
         G.s0 = {dz_h3, 128, 128};
         G.seg0 = seg_out(dz_h2, 64, 0, 1.0f);
         G.seg0.add = dh2s;
@@ -609,7 +622,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         prof_end(h, tok, s); }
         TRY(wgrad_on(2, [&](float* wpart, hipStream_t ss) {
             return weight_grad<T>(2, n, H, W, dz_h3, false, Src{b.h2, 64, 64}, Src{nullptr, 0, 0}, 0, wpart,
-                                  dp + layer_w_offset(2), gscale, ss);
+                                  dp + layer_w_offset(2), gscale, circ, ss);
         }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_h3, false, 128, as.p3, bpart, dp + layer_b_offset(2), gscale, s));
@@ -620,7 +633,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         const GemmGeom g = gemm_geom(1, true, P);
         LayerArgs a = layer_args(h->wb[1], g.kstride);
         ClassGeom& G = a.cls[0];
-        G = class_geom(1, n, H, W, true);
+        G = class_geom(1, n, H, W, true, circ);
         G.s0 = {dz_h2, 64, 64};
         G.seg0 = seg_out(dz_h1, 32, 0, 1.0f);
         G.seg0.add = dh1s;
@@ -632,7 +645,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         prof_end(h, tok, s); }
         TRY(wgrad_on(1, [&](float* wpart, hipStream_t ss) {
             return weight_grad<T>(1, n, H, W, dz_h2, false, Src{b.h1, 32, 32}, Src{nullptr, 0, 0}, 0, wpart,
-                                  dp + layer_w_offset(1), gscale, ss);
+                                  dp + layer_w_offset(1), gscale, circ, ss);
         }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_h2, false, 64, as.p2, bpart, dp + layer_b_offset(1), gscale, s));
@@ -642,7 +655,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
     {
         TRY(wgrad_on(0, [&](float* wpart, hipStream_t ss) {
             return weight_grad<T>(0, n, H, W, dz_h1, false, Src{b.x, 7, 7}, Src{nullptr, 0, 0}, 7, wpart,
-                                  dp + layer_w_offset(0), gscale, ss);
+                                  dp + layer_w_offset(0), gscale, circ, ss, b.roll, b.flip);
         }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_h1, false, 32, as.p1, bpart, dp + layer_b_offset(0), gscale, s));
@@ -651,7 +664,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
             const GemmGeom g = gemm_geom(0, true, P);
             LayerArgs a = layer_args(h->wb[0], g.kstride);
             ClassGeom& G = a.cls[0];
-            G = class_geom(0, n, H, W, true);
+            G = class_geom(0, n, H, W, true, circ);
             G.s0 = {dz_h1, 32, 32};
             a.acc_scale = gscale;
             G.seg0 = seg_out(b.dx, 7, 0, 1.0f);
@@ -770,7 +783,8 @@ static void adam_factors(const drc_adam_cfg* adam, int64_t t, float* step_size, 
 // Enqueue one training step (arguments already checked).
 static drc_status step_enqueue(drc_cae* h, float* d_params, float* d_m, float* d_v, int64_t t,
                                const drc_adam_cfg* adam, const float* d_x, const float* d_target, float* d_loss,
-                               float* d_dparams, int n, int H, int W, void* d_ws, void* stream) {
+                               float* d_dparams, int n, int H, int W, void* d_ws, void* stream,
+                               const int32_t* roll = nullptr, const int32_t* flip = nullptr) {
     const StepLayout S = step_layout(h->prec, n, H, W, h->recompute);
     hipStream_t s = (hipStream_t)stream;
     char* ws = (char*)d_ws;
@@ -799,8 +813,9 @@ static drc_status step_enqueue(drc_cae* h, float* d_params, float* d_m, float* d
         // one kernel; it writes the activations the backward reads
         char* save[5];
         for (int k = 0; k < 5; ++k) save[k] = off[k] >= 0 ? (char*)act[k] : nullptr;
-        TRY(fused_forward(h, d_x, y, n, H, W, nullptr, nullptr, nullptr, 0, s, save));
+        TRY(fused_forward(h, d_x, y, n, H, W, nullptr, nullptr, nullptr, 0, s, save, roll, flip));
     } else {
+        if (roll) return drc_fail(DRC_ERR_UNSUPPORTED, "step_aug: the layer path has no augmented loaders");
         TRY(forward_dispatch(h, fb, n, H, W, 0, 5, s));
     }
 
@@ -810,7 +825,7 @@ static drc_status step_enqueue(drc_cae* h, float* d_params, float* d_m, float* d
     const int nparts = (int)((M + kLossPerBlock - 1) / kLossPerBlock);
     const long ltok = prof_begin(h, PROF_LOSS, s);
     hipLaunchKernelGGL(l1_partial_kernel, dim3(nparts), dim3(256), 0, s, (const float*)y, d_target, M, kLossPerBlock,
-                       1.0f, dy, (double*)(ws + S.loss_part));
+                       1.0f, dy, (double*)(ws + S.loss_part), roll, flip, H, W);
     hipLaunchKernelGGL(l1_final_kernel, dim3(1), dim3(256), 0, s, (const double*)(ws + S.loss_part), nparts, M,
                        d_loss);
     prof_end(h, ltok, s);
@@ -828,6 +843,8 @@ static drc_status step_enqueue(drc_cae* h, float* d_params, float* d_m, float* d
     b.dx = nullptr;
     b.ws = ws + S.bwd;
     b.L = bwd_layout(h->prec, n, H, W, h->recompute != 0);
+    b.roll = roll;
+    b.flip = flip;
     if (h->recompute) TRY(recompute_acts(h, b, n, H, W, s));
     TRY(backward_dispatch(h, b, n, H, W, (float)(1.0 / (double)M), s));
 
@@ -854,6 +871,24 @@ extern "C" drc_status drc_cae_step(drc_cae* h, float* d_params, float* d_m, floa
                    "step"));
     if (t < 1) return drc_fail(DRC_ERR_INVALID_ARG, "step: t = %lld (must be >= 1)", (long long)t);
     return step_enqueue(h, d_params, d_m, d_v, t, adam, d_x, d_target, d_loss, d_dparams, n, H, W, d_ws, stream);
+}
+
+extern "C" drc_status drc_cae_step_aug(drc_cae* h, float* d_params, float* d_m, float* d_v, int64_t t,
+                                       const drc_adam_cfg* adam, const float* d_x, const float* d_target,
+                                       const int32_t* d_roll, const int32_t* d_flip, float* d_loss,
+                                       float* d_dparams, int n, int H, int W, void* d_ws, size_t ws_bytes,
+                                       void* stream) {
+    TRY(check_step(h, d_params, d_m, d_v, adam, d_x, d_target, d_loss, d_dparams, n, H, W, d_ws, ws_bytes,
+                   "step_aug"));
+    if (t < 1) return drc_fail(DRC_ERR_INVALID_ARG, "step_aug: t = %lld (must be >= 1)", (long long)t);
+    TRY(check_ptr("step_aug", "d_roll", d_roll, 4, false));
+    TRY(check_ptr("step_aug", "d_flip", d_flip, 4, false));
+    if (!(h->fused && h->prec == P_BF16 && fused_forward_size(H, W)))
+        return drc_fail(DRC_ERR_UNSUPPORTED,
+                        "step_aug: augmented loaders exist in the whole-network BF16 path (32x32, 64x64) only; "
+                        "use drc_augment and drc_cae_step");
+    return step_enqueue(h, d_params, d_m, d_v, t, adam, d_x, d_target, d_loss, d_dparams, n, H, W, d_ws, stream,
+                        d_roll, d_flip);
 }
 
 // ------------------------------------------------------------------ captured training step

@@ -43,7 +43,8 @@ def test_status_strings(B):
 
 def test_default_desc(B):
     d = B.drc_cae_default_desc(B.DRC_BF16)
-    assert (d.in_ch, d.out_ch, list(d.widths), d.compute, d.final_relu) == (7, 3, [32, 64, 128], 1, 0)
+    assert (d.in_ch, d.out_ch, list(d.widths), d.compute, d.final_relu, d.pad_w) == \
+        (7, 3, [32, 64, 128], 1, 0, B.DRC_PAD_ZERO)
 
 
 def _expect(B, status, fn, *args):
@@ -63,6 +64,9 @@ def test_create_rejects_bad_descriptions(B):
     _expect(B, 1, B.drc_cae_create, d)
     d = B.drc_cae_default_desc(B.DRC_F32)
     d.final_relu = 2
+    _expect(B, 1, B.drc_cae_create, d)
+    d = B.drc_cae_default_desc(B.DRC_F32)
+    d.pad_w = 2
     _expect(B, 1, B.drc_cae_create, d)
     L = B.lib()
     assert L.drc_cae_create(None, None) == 1
