@@ -31,6 +31,11 @@ The backward pass is written out layer by layer from the definitions
   dz = gamma / sqrt(var + eps) (dq - mean(dq) - xhat mean(dq xhat));
 * max-pool: the gradient goes to the first maximum of each window in
   row-major order;
+* branch conditioning (optional): the LeakyReLU branches, the max-pool
+  choices, the output ReLU and the loss signs can be taken from another
+  forward's activations (the GPU's), so that a lower-precision forward that
+  lands on the other side of a kink is compared with the derivative of the
+  same piece;
 * bilinear upsampling: the adjoint of the interpolation (every output pixel
   returns its gradient to the two-by-two sources it read, with the same
   weights);
@@ -73,18 +78,32 @@ def _conv3x3_bwd(x, w, dz):
     return dw, g.sum(axis=0), dxp[:, 1:H + 1, 1:W + 1]
 
 
-def _leaky(q):
-    return np.where(q > 0, q, SLOPE * q)
+def _leaky(q, on=None):
+    return np.where(q > 0 if on is None else on, q, SLOPE * q)
 
 
-def _leaky_grad(q):
-    return np.where(q > 0, 1.0, SLOPE)
+def _leaky_grad(q, on=None):
+    return np.where(q > 0 if on is None else on, 1.0, SLOPE)
+
+
+def _windows(x):
+    n, H, W, c = x.shape
+    return x.reshape(n, H // 2, 2, W // 2, 2, c).transpose(0, 1, 3, 5, 2, 4).reshape(n, H // 2, W // 2, c, 4)
+
+
+def _pool(x, by=None):
+    """2x2 max-pool; with by (an array of the same shape), the value of x at
+    the first maximum of by's window (the branch another forward took)."""
+    if by is None:
+        return max_pool2(x)
+    first = np.argmax(_windows(np.asarray(by)), axis=-1)
+    return np.take_along_axis(_windows(x), first[..., None], axis=-1)[..., 0]
 
 
 def _max_pool2_bwd(x, dy):
     """Routes dy to the first maximum (row-major) of each 2x2 window of x."""
     n, H, W, c = x.shape
-    win = x.reshape(n, H // 2, 2, W // 2, 2, c).transpose(0, 1, 3, 5, 2, 4).reshape(n, H // 2, W // 2, c, 4)
+    win = _windows(x)
     first = np.argmax(win, axis=-1)  # numpy's argmax takes the first maximum
     onehot = np.zeros_like(win)
     np.put_along_axis(onehot, first[..., None], 1.0, axis=-1)
@@ -114,12 +133,18 @@ def _upsample2_bwd(dy):
     return out
 
 
-def forward_train(params, x):
+def forward_train(params, x, cond=None):
     """Training forward. Returns (y, cache, running) where running is the
-    list of updated (mean, var) per batch-normalised layer (None elsewhere)."""
+    list of updated (mean, var) per batch-normalised layer (None elsewhere).
+
+    cond (optional): the branch decisions of another (lower-precision)
+    forward of the same network, so that both sides differentiate the same
+    piece of this piecewise-smooth function: {"a": the 14 activations of the
+    3x3 layers (LeakyReLU branch: a > 0; max-pool: the first maximum of a's
+    window), "y": its output (ReLU branch y > 0; loss sign sign(y - t))}."""
     x = np.asarray(x, dtype=np.float64)
     P = [{k: np.asarray(v, dtype=np.float64) for k, v in q.items()} for q in params]
-    cache = {"layers": [], "x": x}
+    cache = {"layers": [], "x": x, "cond": cond}
     running = []
     it = iter(range(len(P)))
 
@@ -142,15 +167,17 @@ def forward_train(params, x):
             pre = z
             running.append(None)
         rec["pre"] = pre
+        rec["on"] = None if cond is None else np.asarray(cond["a"][k]) > 0
         cache["layers"].append(rec)
-        return _leaky(pre)
+        return _leaky(pre, rec["on"])
 
+    by = (lambda k: None) if cond is None else (lambda k: cond["a"][k])
     s1 = block(block(x))
-    p1 = max_pool2(s1)
+    p1 = _pool(s1, by(1))
     s2 = block(block(p1))
-    p2 = max_pool2(s2)
+    p2 = _pool(s2, by(3))
     s3 = block(block(p2))
-    p3 = max_pool2(s3)
+    p3 = _pool(s3, by(5))
     m = block(block(p3))
     d3 = block(block(np.concatenate([upsample2(m), s3], axis=-1)))
     d2 = block(block(np.concatenate([upsample2(d3), s2], axis=-1)))
@@ -158,13 +185,17 @@ def forward_train(params, x):
     q = P[-1]
     ypre = d1 @ q["w"].T + q["b"]
     running.append(None)
-    cache.update(s1=s1, s2=s2, s3=s3, d1=d1, ypre=ypre)
-    return np.maximum(ypre, 0.0), cache, running
+    yon = ypre > 0 if cond is None else np.asarray(cond["y"]) > 0
+    cache.update(s1=s1, s2=s2, s3=s3, d1=d1, ypre=ypre, yon=yon)
+    return np.where(yon, ypre, 0.0), cache, running
 
 
-def l1(y, t):
+def l1(y, t, y_sign=None):
+    """(loss, dL/dy); y_sign: take sign(y_sign - t) for the gradient (the
+    side of each residual's kink another forward is on)."""
     d = y - np.asarray(t, dtype=np.float64)
-    return float(np.abs(d).mean()), np.sign(d) / d.size
+    sgn = np.sign(d if y_sign is None else np.asarray(y_sign, dtype=np.float64) - np.asarray(t, dtype=np.float64))
+    return float(np.abs(d).mean()), sgn / d.size
 
 
 def backward_train(params, cache, dy):
@@ -174,7 +205,7 @@ def backward_train(params, cache, dy):
     L = cache["layers"]
     grads = [None] * len(P)
     # output 1x1 convolution with ReLU
-    g = dy * (cache["ypre"] > 0)
+    g = dy * cache["yon"]
     q = P[-1]
     gf = g.reshape(-1, g.shape[-1])
     grads[-1] = {"w": gf.T @ cache["d1"].reshape(-1, cache["d1"].shape[-1]), "b": gf.sum(axis=0)}
@@ -182,7 +213,7 @@ def backward_train(params, cache, dy):
 
     def block_bwd(k, da):
         rec, q = L[k], P[k]
-        dq = da * _leaky_grad(rec["pre"])
+        dq = da * _leaky_grad(rec["pre"], rec["on"])
         gr = {}
         if rec["bn"]:
             xhat, rstd = rec["xhat"], rec["rstd"]
@@ -211,19 +242,21 @@ def backward_train(params, cache, dy):
     d = block_bwd(8, block_bwd(9, dd3))
     dup, ds3 = split(d, 256)
     dm = _upsample2_bwd(dup)
+    cond = cache["cond"]
+    sel = (lambda k, s: s) if cond is None else (lambda k, s: np.asarray(cond["a"][k], dtype=np.float64))
     dp3 = block_bwd(6, block_bwd(7, dm))
-    ds3 = ds3 + _max_pool2_bwd(cache["s3"], dp3)
+    ds3 = ds3 + _max_pool2_bwd(sel(5, cache["s3"]), dp3)
     dp2 = block_bwd(4, block_bwd(5, ds3))
-    ds2 = ds2 + _max_pool2_bwd(cache["s2"], dp2)
+    ds2 = ds2 + _max_pool2_bwd(sel(3, cache["s2"]), dp2)
     dp1 = block_bwd(2, block_bwd(3, ds2))
-    ds1 = ds1 + _max_pool2_bwd(cache["s1"], dp1)
+    ds1 = ds1 + _max_pool2_bwd(sel(1, cache["s1"]), dp1)
     dx = block_bwd(0, block_bwd(1, ds1))
     return grads, dx
 
 
-def loss_and_grad(params, x, t):
-    y, cache, running = forward_train(params, x)
-    loss, dy = l1(y, t)
+def loss_and_grad(params, x, t, cond=None):
+    y, cache, running = forward_train(params, x, cond)
+    loss, dy = l1(y, t, None if cond is None else cond["y"])
     grads, dx = backward_train(params, cache, dy)
     return loss, grads, dx, y, running
 

@@ -131,3 +131,24 @@ def test_inference_form_is_the_running_statistics_forward():
     """With the running statistics the training oracle's layer list and
     parameter dicts give the inference oracle's network (same LAYERS)."""
     assert UT.LAYERS == U.LAYERS
+
+
+def test_branch_conditioning_with_own_decisions_is_exact():
+    """Conditioned on its own forward's activations and output, the oracle
+    returns exactly its unconditioned loss, output and gradients (the
+    conditioning only fixes which piece is differentiated)."""
+    params = synth.unet_params(2)
+    x, t = synth.training_batch(2, 16)
+    l0, g0, dx0, y0, _ = UT.loss_and_grad(params, x, t)
+    _, cache, _ = UT.forward_train(params, x)
+    acts = [UT._leaky(r["pre"]) for r in cache["layers"]]
+    l1_, g1, dx1, y1, _ = UT.loss_and_grad(params, x, t, cond={"a": acts, "y": y0})
+    assert l1_ == l0
+    np.testing.assert_array_equal(y1, y0)
+    np.testing.assert_array_equal(UT.flat(g1), UT.flat(g0))
+    np.testing.assert_array_equal(dx1, dx0)
+    # a flipped branch changes the gradient (the conditioning is used)
+    acts[3] = acts[3].copy()
+    acts[3][0, 0, 0, 0] = -acts[3][0, 0, 0, 0]
+    _, g2, _, _, _ = UT.loss_and_grad(params, x, t, cond={"a": acts, "y": y0})
+    assert not np.array_equal(UT.flat(g2), UT.flat(g0))
