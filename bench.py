@@ -175,6 +175,35 @@ def interp_leg(B, dev, steps, warmup, Hi=1080, Wi=1920, r=16, eps=1e-4):
             "alg_bytes": by}
 
 
+def unet_train_leg(B, dev, steps, warmup, n=32, H=32):
+    """The paper's own network, one FP32 training step (batch statistics,
+    L1 loss, backward, Adam) on n maps of H x H: the paper's batch (32) and
+    map size. FLOPs nominal: 3x the forward's (forward, data and weight
+    gradients)."""
+    import torch
+    from paper_1910_02480_amd import synth
+    div = (1, 1, 2, 2, 4, 4, 8, 8, 4, 4, 2, 2, 1, 1, 1)
+    flops = 3 * sum(2.0 * co * ci * (1 if name == "out" else 9) * n * (H // d) ** 2
+                    for (name, ci, co, _), d in zip(synth.UNET_LAYERS, div))
+    p = torch.from_numpy(synth.unet_flat(synth.unet_params(0))).to(dev)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    xs, ts = synth.training_batch(n, H)
+    x, t = torch.from_numpy(xs).to(dev), torch.from_numpy(ts).to(dev)
+    ws = torch.empty(B.drc_unet_train_workspace_size(n, H, H) + 256, dtype=torch.uint8, device=dev)
+    ws = ws[(-ws.data_ptr()) % 256:]
+    loss = torch.zeros(1, device=dev)
+    adam = B.drc_adam_cfg(6e-5, 0.9, 0.999, 1e-8)
+    cnt = [0]
+
+    def step():
+        cnt[0] += 1
+        B.drc_unet_train_step(p, m, v, cnt[0], adam, x, t, loss, None, None, ws)
+    tm = event_timed(step, steps, warmup)
+    return {"maps": n, "H": H, "precision": "f32", "ms": tm * 1e3, "maps_per_s": n / tm,
+            "TFLOP/s": flops / tm / 1e12, "mfma_frac_flop_based": flops / tm / (PEAK_TFLOPS["f32"] * 1e12),
+            "loss_after": float(loss)}
+
+
 def unet_leg(B, dev, steps, warmup, n=4096, H=32):
     """The paper's own network (inference, BF16 activations) over n maps of
     H x H, the paper's map size. FLOPs are nominal: 2 * cout * cin * taps per
@@ -584,6 +613,9 @@ def main():
         legs["unet_bf16_fwd_4096x32x32"] = un = unet_leg(B, dev, max(3, args.steps // 4), 2)
         log(f"paper's U-Net forward, 4096 maps of 32x32: {un['maps_per_s']:,.0f} maps/s "
             f"({un['ms']:.3f} ms, {un['TFLOP/s']:.0f} TFLOP/s)")
+        legs["unet_f32_train_step_32x32x32"] = ut = unet_train_leg(B, dev, max(3, args.steps // 4), 2)
+        log(f"paper's U-Net training step, 32 maps of 32x32 (FP32): {ut['ms']:.3f} ms "
+            f"({ut['TFLOP/s']:.1f} TFLOP/s)")
         # ---------------- mixed-resolution frame: one graph replay per frame
         legs["bf16_mixed_frame"] = mixed_frame_leg(cae, tune_path, args)
         legs["speedup_bf16_vs_f32"] = {

@@ -447,6 +447,38 @@ drc_status drc_unet_workspace_size(int n, int H, int W, size_t* bytes);
 drc_status drc_unet_forward(drc_unet* u, const float* d_x, float* d_y, int n, int H, int W, void* d_ws,
                             size_t ws_bytes, void* stream);
 
+/* The same network's training step (Sec. 5: trained with Adam; Sec. 4.3:
+ * L1 loss), FP32 throughout: a forward with batch statistics (each batch-
+ * normalised layer normalises with the mean and biased variance of its
+ * convolution output over the batch's n x H x W pixels, and updates its
+ * running mean and variance in d_params in place with momentum 0.1, the
+ * variance unbiased, as PyTorch's BatchNorm2d in training mode), the mean L1
+ * loss against d_target [n,H,W,3] written to d_loss (one float), the
+ * gradient of every trainable parameter (all W and b, gamma and beta; the
+ * running-statistics entries get 0) written to d_dparams when it is not
+ * NULL (flat layout of d_params), and Adam (PyTorch's form, drc_adam_cfg,
+ * step count t >= 1) on the trainable entries; d_m and d_v have the flat
+ * layout too (their running-statistics entries are left alone). d_y, when
+ * not NULL, receives the forward's output [n,H,W,3]. Max-pool gradients go
+ * to the first maximum of each 2x2 window (row-major), as PyTorch's.
+ * Workspace: drc_unet_train_workspace_size bytes, 256-byte aligned. No
+ * handle: the weights are read from d_params in place. Errors (nothing is
+ * enqueued): DRC_ERR_SHAPE for n < 2 or H, W not multiples of 8 (>= 8);
+ * DRC_ERR_INVALID_ARG for NULL or misaligned buffers (16 bytes; d_x, d_loss
+ * and d_dparams 4), a NULL adam, bad Adam hyper-parameters or t < 1;
+ * DRC_ERR_WORKSPACE for a short workspace. */
+drc_status drc_unet_train_workspace_size(int n, int H, int W, size_t* bytes);
+/* Where a training step leaves the activations of the 14 3x3 layers in its
+ * workspace (byte offsets; float32 NHWC [n, H/d, W/d, cout] with d the
+ * layer's stage divisor), for inspection: the tests read the branch
+ * decisions of the GPU forward (LeakyReLU signs, max-pool choices) from
+ * them. Errors as drc_unet_train_workspace_size; DRC_ERR_INVALID_ARG for a
+ * NULL offsets. */
+drc_status drc_unet_train_act_offsets(int n, int H, int W, int64_t offsets[14]);
+drc_status drc_unet_train_step(float* d_params, float* d_m, float* d_v, int64_t t, const drc_adam_cfg* adam,
+                               const float* d_x, const float* d_target, float* d_loss, float* d_dparams,
+                               float* d_y, int n, int H, int W, void* d_ws, size_t ws_bytes, void* stream);
+
 /* Tile-shape tuning: time each implemented tile shape of every layer for
  * an n x H x W forward batch on the given stream and write the fastest to
  * the JSON cache file path (keyed by arch, precision, layer and

@@ -91,6 +91,10 @@ _SIGS = {
     "drc_unet_set_params": (_I, [_VP, _VP, _VP]),
     "drc_unet_workspace_size": (_I, [_I, _I, _I, ctypes.POINTER(_SZ)]),
     "drc_unet_forward": (_I, [_VP, _VP, _VP, _I, _I, _I, _VP, _SZ, _VP]),
+    "drc_unet_train_workspace_size": (_I, [_I, _I, _I, ctypes.POINTER(_SZ)]),
+    "drc_unet_train_act_offsets": (_I, [_I, _I, _I, ctypes.POINTER(ctypes.c_int64)]),
+    "drc_unet_train_step": (_I, [_VP, _VP, _VP, ctypes.c_int64, ctypes.POINTER(drc_adam_cfg), _VP, _VP, _VP, _VP,
+                                 _VP, _I, _I, _I, _VP, _SZ, _VP]),
     "drc_cae_autotune": (_I, [_VP, _I, _I, _I, _VP, _VP, _SZ, ctypes.c_char_p, _VP]),
     "drc_cae_set_tile": (_I, [_VP, _I, _I, _I]),
     "drc_cae_wgrad_schedule": (_I, [_I, _I, _I, _I, _I, ctypes.POINTER(ctypes.c_int64)]),
@@ -400,3 +404,22 @@ def drc_status_string(s):
 
 def drc_last_error():
     return lib().drc_last_error().decode()
+
+
+def drc_unet_train_workspace_size(n, H, W):
+    sz = _SZ()
+    _check(lib().drc_unet_train_workspace_size(n, H, W, ctypes.byref(sz)))
+    return sz.value
+
+
+def drc_unet_train_step(params, m, v, t, adam, x, target, loss, dparams=None, y=None, ws=None, stream=None):
+    n, H, W = _nhw(x, 7)
+    _check(lib().drc_unet_train_step(_ptr(params), _ptr(m), _ptr(v), int(t), ctypes.byref(adam), _ptr(x),
+                                     _ptr(target), _ptr(loss), _ptr(dparams), _ptr(y), n, H, W, _ptr(ws),
+                                     _nbytes(ws), _stream(stream)))
+
+
+def drc_unet_train_act_offsets(n, H, W):
+    off = (ctypes.c_int64 * 14)()
+    _check(lib().drc_unet_train_act_offsets(n, H, W, off))
+    return list(off)

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdrc_cae.so")
 SOURCES = ["drc_cae.hip", "net.hip", "plan.hip", "gemm_f32.hip", "gemm_bf16.hip", "gemm_fp8.hip", "fused_fwd.hip",
-           "envmap.hip", "interp.hip", "augment.hip", "unet.hip", "layer_bands.hip", "static_ws.hip", "fused_fp8.hip"]
+           "envmap.hip", "interp.hip", "augment.hip", "unet.hip", "layer_bands.hip", "static_ws.hip", "fused_fp8.hip", "unet_train.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 CFLAGS = [

@@ -277,10 +277,11 @@ static __global__ __launch_bounds__(256) void colsum_final_kernel(const float* p
 }
 
 // ------------------------------------------------------------------ weight gradient
-// dW of a stride-2 3x3 layer as one reduction over "reduction pixels"
-// (n,u,v) on an Hr x Wr grid, with two operands:
+// dW of a 3x3 layer (stride s = 2, or 1 for a stride-1 convolution) as one
+// reduction over "reduction pixels" (n,u,v) on an Hr x Wr grid, with two
+// operands:
 //   plain    P[n,u,v][cp]                       (tap independent)
-//   gathered Q[n, 2u+kh-1, 2v+kw-1][cq]          (zero outside Hq x Wq)
+//   gathered Q[n, s u+kh-1, s v+kw-1][cq]        (zero outside Hq x Wq)
 //   D[j = t*cq + c][cp] = sum_(n,u,v) Q_t[.][c] * P[.][cp],  t = 3 kh + kw.
 // Convolution layer: reduction over its output pixels, P = output gradient
 // (cp = Cout), Q = layer input (cq = Cin): dW[co][t][ci] = D[t*Cin+ci][co].
@@ -305,6 +306,7 @@ struct WgradArgs {
     int q_raw, qc, qld;
     int nmaps, Hr, Wr, Hq, Wq;
     int circ;                       // 1: gathered columns wrap (circular width), 0: zero outside
+    int stride;                     // of the layer (2: the autoencoder; 1: the paper's U-Net)
     long per_block;                 // reduction pixels per workgroup
     int jtiles;                     // tiles along j (blockIdx.y = jt + jtiles * pt)
     float* partial;                 // [slot = 4*chunk + wave][9*qc][pc]
@@ -401,8 +403,8 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
             }
 #pragma unroll
             for (int b = 0; b < JG; ++b) {
-                const int i = 2 * uu + tkh[b] - 1;
-                int jj = 2 * vv + tkw[b] - 1;
+                const int i = a.stride * uu + tkh[b] - 1;
+                int jj = a.stride * vv + tkw[b] - 1;
                 if (a.circ && jj < 0) jj += a.Wq;  // only column -1 falls outside
                 const bool in = ok && (unsigned)i < (unsigned)a.Hq && (unsigned)jj < (unsigned)a.Wq;
                 ld_vec<T, VEC>(a.q, a.q_raw, (((long)n * a.Hq + (in ? i : 0)) * a.Wq + (in ? jj : 0)) * a.qld + tch[b],

@@ -468,6 +468,7 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
     a.Hr = wp.Hr;
     a.Wr = wp.Wr;
     a.circ = circ;
+    a.stride = 2;
     a.per_block = wp.per_block;
     a.jtiles = wp.jtiles;
     a.partial = partial;
