@@ -41,9 +41,10 @@ _LABELS = (
     (r"tconv_pairs_kernel<(\d), 128, 64, 32,", "forward D2"),
     (r"tconv_pairs_kernel<(\d), 64, 64, 32,", "data gradient E2"),
     (r"tconv_merged_kernel<(\d), 64, 32, 3,", "forward D1"),
-    (r"cae_fused_forward_kernel<\d+, \d+, false>", "forward fused"),
+    (r"cae_fused_forward_kernel<\d+, \d+, false, false>", "forward fused"),
+    (r"cae_fused_forward_kernel<\d+, \d+, false, true>", "forward fused (augmented input)"),
     (r"cae_fused_fp8_kernel", "FP8 forward fused"),
-    (r"cae_fused_forward_kernel<\d+, \d+, true>", "recompute fused"),
+    (r"cae_fused_forward_kernel<\d+, \d+, true, false>", "recompute fused"),
     (r"pack_weights_kernel|pack_all_kernel", "weight pack"),
     (r"envmap_build_kernel", "envmap build"),
     (r"envmap_sample_kernel", "envmap sample"),
@@ -59,6 +60,13 @@ _LABELS = (
     (r"unet_pool_kernel", "U-Net max-pool"),
     (r"unet_cast_kernel", "U-Net input cast"),
     (r"unet_pack_kernel", "U-Net weight pack"),
+    (r"ut_conv_kernel", "U-Net training convolution (FP32)"),
+    (r"ut_reduce_kernel|ut_finish_kernel", "U-Net training batch-norm reductions"),
+    (r"ut_bn_act_kernel|ut_bn_bwd_kernel", "U-Net training batch norm + LeakyReLU"),
+    (r"ut_pool", "U-Net training max-pool"),
+    (r"ut_upcat", "U-Net training upsample + concat"),
+    (r"ut_out", "U-Net training output layer"),
+    (r"ut_flip_kernel|ut_pad_|ut_fill_kernel", "U-Net training copies"),
     (r"cae_fused_dgrad_kernel", "fused data gradients"),
     (r"wgrad_tr_kernel", "weight gradient (BF16, transpose reads)"),
     (r"wgrad_bf16_kernel", "weight gradient (BF16)"),

@@ -131,8 +131,8 @@ def _same_pattern(oracle, params, x, t, ref_masks, ref_sign):
 def test_finite_differences_2x8x8(oracle, params):
     """Analytic FP64 gradient vs central differences on N=2 maps of 8x8.
 
-    Covers every input coordinate, every bias, 48 seeded weights per layer
-    and 8 random directions. Kink detection: a step is used only if the ReLU
+    Covers every input coordinate, every bias, 1024 seeded weights per layer
+    (every weight of a smaller layer) and 8 random directions. Kink detection: a step is used only if the ReLU
     masks and the loss sign pattern at theta +- h equal those at theta; past
     a kink the step shrinks (1e-5, 1e-6, 1e-7 relative), and a coordinate
     that crosses a kink at every step is skipped and counted.
@@ -176,7 +176,8 @@ def test_finite_differences_2x8x8(oracle, params):
     coords = []
     for (ws, bs, _) in oracle.layer_slices():
         coords += list(range(bs.start, bs.stop))
-        coords += list(r.choice(np.arange(ws.start, ws.stop), size=48, replace=False))
+        nw = ws.stop - ws.start
+        coords += list(r.choice(np.arange(ws.start, ws.stop), size=min(1024, nw), replace=False))
     for k in coords:
         def gp(v, k=k):
             pp = params.copy()
@@ -192,7 +193,9 @@ def test_finite_differences_2x8x8(oracle, params):
             return params + s * dpv, x + s * dxv
         res = check(gd, 0.0, an)
         skipped += res is None
-    assert skipped <= 5
+    checks = flat.size + len(coords) + 8
+    print(f"finite differences: {checks} checks, {skipped} skipped at kinks")
+    assert skipped <= 5 + checks // 200
 
 
 def test_zero_channel_ablation_invariant(oracle, params):
