@@ -438,8 +438,11 @@ __global__ __launch_bounds__(NT, 2) void cae_fused_fp8_kernel(const F8Args a) {
         __syncthreads();
         e1_phase<H, W, E1N>(smem, L::R1, L::R0, a);
         __syncthreads();
-        // x is dead: the zero block at the end of R1 (after h2 and h3)
-        if (threadIdx.x < 16) *(uint4*)(smem + L::ZO + 16 * threadIdx.x) = uint4{0u, 0u, 0u, 0u};
+        // x is dead: the zero block at the end of R1 (after h2 and h3). Every
+        // wave clears it before its own first read (LDS operations of a wave
+        // complete in order), so no barrier is needed between this store and
+        // E2's taps outside the map; the other waves only write zeros there.
+        if ((threadIdx.x & 63) < 16) *(uint4*)(smem + L::ZO + 16 * (threadIdx.x & 63)) = uint4{0u, 0u, 0u, 0u};
         conv_phase8<1, H / 2, W / 2, 32, 64, 2, E2N>(smem, L::R0, L::H2, L::ZO, a);
         __syncthreads();
         conv_phase8<2, H / 4, W / 4, 64, 128, 2, E3N>(smem, L::H2, L::H3, L::ZO, a);
