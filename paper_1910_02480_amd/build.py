@@ -29,9 +29,19 @@ CFLAGS = [
 ]
 
 
+# Per-source flags. The whole-network BF16 kernels (fused_fwd.hip) are
+# scheduled for long LDS load clauses: their inner loops keep more operand
+# reads in flight that way (same instructions and results, about 2 % faster).
+# The FP8 kernel is left on the default schedule, which keeps it free of
+# register spills.
+SRC_FLAGS = {
+    "fused_fwd.hip": ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + CFLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + CFLAGS + SRC_FLAGS.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
