@@ -559,7 +559,7 @@ def main():
             ms_s, calls_s = B.drc_cae_profile_read(c.h)
             B.drc_cae_profile(c.h, 0)
             names = [f"fwd {LAYERS[l][0]}" for l in range(6)] + [f"dgrad {LAYERS[l][0]}" for l in range(6)] + \
-                    [f"wgrad {LAYERS[l][0]}" for l in range(6)] + ["bias grads", "loss", "adam", "fused forward",
+                    [f"wgrad {LAYERS[l][0]}" for l in range(6)] + ["gradient sums", "loss", "adam", "fused forward",
                                                                    "fused data gradients"]
             legs[f"{comp}_fwd_bwd"]["breakdown_ms"] = {names[k]: round(ms_s[k], 4) for k in range(23)
                                                        if calls_s[k]}
@@ -581,7 +581,7 @@ def main():
             ms_s, calls_s = B.drc_cae_profile_read(tr.cae.h)
             B.drc_cae_profile(tr.cae.h, 0)
             names = [f"fwd {LAYERS[l][0]}" for l in range(6)] + [f"dgrad {LAYERS[l][0]}" for l in range(6)] + \
-                    [f"wgrad {LAYERS[l][0]}" for l in range(6)] + ["bias grads", "loss", "adam+repack",
+                    [f"wgrad {LAYERS[l][0]}" for l in range(6)] + ["gradient sums", "loss", "adam+repack",
                                                                    "fused forward / recompute",
                                                                    "fused data gradients"]
             legs[f"{comp}_train_step"]["breakdown_ms"] = {names[k]: round(ms_s[k], 4) for k in range(23)

@@ -508,7 +508,10 @@ drc_status drc_cae_wgrad_schedule(int compute, int layer, int n, int H, int W, i
  * waits for the recorded events, adds their elapsed times per slot
  * (ms[24], calls[24]) and clears the record. Slots: 0..5 forward GEMM of
  * E1..D1, 6..11 backward-data GEMM of E1..D1, 12..17 weight gradient of
- * E1..D1, 18 bias gradients, 19 L1 loss, 20 Adam and repack. */
+ * E1..D1, 18 gradient sums (the bias gradients; in BF16 also the
+ * fixed-order sums of every layer's weight-gradient partial tiles and of the
+ * loss, run as one launch at the end of the backward), 19 L1 loss, 20 Adam
+ * and repack. */
 drc_status drc_cae_profile(drc_cae* h, int enable);
 drc_status drc_cae_profile_read(drc_cae* h, double ms[24], int64_t calls[24]);
 

@@ -1106,7 +1106,7 @@ drc_status fused_recompute(drc_cae* h, int n, int H, int W, const void* h2, void
 drc_status fused_dgrad(drc_cae* h, int n, int H, int W, const float* dy, const void* u2, const void* u3,
                        const void* h3, const void* h2, const void* h1, void* dz_u2, void* dh1s, void* dz_u3,
                        void* dz_h3, void* dz_h2, void* dz_h1, float* bias_part, size_t bias_part_bytes,
-                       float* dparams, float gscale, hipStream_t s) {
+                       float* dparams, float gscale, hipStream_t s, GradFinal* defer) {
     if (h->prec != P_BF16 || !fused_forward_size(H, W))
         return drc_fail(DRC_ERR_UNSUPPORTED, "fused dgrad: BF16 maps of 32x32 or 64x64 only");
     if (n < 1) return DRC_OK;
@@ -1135,6 +1135,17 @@ drc_status fused_dgrad(drc_cae* h, int n, int H, int W, const float* dy, const v
     drc_status st = (H == 64) ? launch_dgrad<64, 64>(a, grid, s) : launch_dgrad<32, 32>(a, grid, s);
     prof_end(h, tok, s);
     if (st != DRC_OK) return st;
+    if (defer) {
+        static const int s0[7] = {0, 32, 96, 224, 288, 320, kBiasSlots};
+        defer->bpart = bias_part;
+        defer->bnrows = grid;
+        defer->bslots = kBiasSlots;
+        defer->bscale = gscale;
+        defer->bdparams = dparams;
+        for (int l = 0; l < 6; ++l) defer->boff[l] = layer_b_offset(l);
+        for (int l = 0; l < 7; ++l) defer->bs0[l] = s0[l];
+        return DRC_OK;
+    }
     BiasFinalArgs b;
     b.part = bias_part;
     b.nrows = grid;

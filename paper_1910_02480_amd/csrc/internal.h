@@ -182,11 +182,40 @@ drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int
 // h2 -> h3, u3, u2 (the layers a recomputing backward rebuilds), all plain NHWC.
 drc_status fused_recompute(drc_cae* h, int n, int H, int W, const void* h2, void* h3, void* u3, void* u2,
                            hipStream_t s);
+// The fixed-order gradient sums of a backward pass, collected while its
+// kernels are enqueued and run as one launch at its end (grad_final_launch):
+// the weight gradient of each layer from its partial tiles (the sum of
+// wgrad_final_kernel), the bias gradients from the per-workgroup column sums
+// of the whole-network data-gradient chain (the sum of bias_final_kernel)
+// and a training step's mean L1 loss from its partial sums (the sum of
+// l1_final_kernel). Results are bitwise those of the separate kernels.
+struct GradFinal {
+    struct Wjob {
+        const float* partial;  // [nchunks][9 * qc][pc]
+        int nchunks, qc, pc, q_is_cout;
+        float scale;
+        float* dw;             // the layer's weights in dparams
+    } w[6];
+    int nw = 0;
+    const float* bpart = nullptr;  // [bnrows][bslots] (null: no bias job)
+    int bnrows = 0, bslots = 0;
+    float bscale = 0.0f;
+    float* bdparams = nullptr;
+    long boff[6] = {};             // offsets of the six bias vectors in dparams
+    int bs0[7] = {};               // first slot of each bias vector, and the slot count
+    const double* lpart = nullptr; // L1 loss: per-workgroup partial sums (the sum of l1_final_kernel)
+    int lnparts = 0;
+    long lcount = 0;
+    float* loss = nullptr;
+};
+drc_status grad_final_launch(const GradFinal& g, hipStream_t s);
+
 // dy -> dz_u2, dh1s, dz_u3, dz_h3, dz_h2, dz_h1 (the data gradients of D1..E2)
 // in one kernel, from the saved activations u2 u3 h3 h2 h1 (plain NHWC BF16);
 // it also forms every bias gradient (column sums of dy and of the stored
-// output gradients), written scaled by gscale into dparams.
+// output gradients), written scaled by gscale into dparams, or, with defer
+// set, recorded in *defer for grad_final_launch.
 drc_status fused_dgrad(drc_cae* h, int n, int H, int W, const float* dy, const void* u2, const void* u3,
                        const void* h3, const void* h2, const void* h1, void* dz_u2, void* dh1s, void* dz_u3,
                        void* dz_h3, void* dz_h2, void* dz_h1, float* bias_part, size_t bias_part_bytes,
-                       float* dparams, float gscale, hipStream_t s);
+                       float* dparams, float gscale, hipStream_t s, GradFinal* defer = nullptr);

@@ -339,10 +339,153 @@ static drc_status bias_grad(const void* g, bool g_raw, int C, long npix, float* 
 // Weight gradient of layer l. g: gradient at the layer output (pre-
 // activation; float32 when g_raw), s0/s1: the layer input (a concatenation
 // for D2 and D1; float32 x with a_raw_c channels for E1).
+// All deferred gradient sums of a backward pass in one launch (GradFinal):
+// workgroups [0, nbw) take 64 weight-gradient outputs each, exactly as
+// wgrad_final_kernel (16 waves add chunk rows w, w + 16, ... in order, then
+// the wave sums in order); the rest take four bias slots each, one 256-thread
+// group per slot, exactly as bias_final_kernel (strided row sums, then a
+// halving tree).
+struct GradFinalArgs {
+    GradFinal::Wjob w[6];
+    int wblock0[7];  // first workgroup of each weight job, then the first bias workgroup
+    const float* bpart;
+    int bnrows, bslots;
+    float bscale;
+    float* bdparams;
+    long boff[6];
+    int bs0[7];
+    int lblock;  // the loss workgroup (-1: none)
+    const double* lpart;
+    int lnparts;
+    long lcount;
+    float* loss;
+};
+static __global__ __launch_bounds__(1024) void grad_final_kernel(const GradFinalArgs a) {
+    __shared__ float red[1024];
+    __shared__ double lred[256];
+    const int b = blockIdx.x;
+    if (b == a.lblock) {  // threads 0..255 as l1_final_kernel's 256-thread workgroup
+        const int t = threadIdx.x;
+        if (t < 256) {
+            double s = 0.0;
+            for (int i = t; i < a.lnparts; i += 256) s += a.lpart[i];
+            lred[t] = s;
+        }
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) lred[t] += lred[t + o];
+            __syncthreads();
+        }
+        if (t == 0) a.loss[0] = (float)(lred[0] / (double)a.lcount);
+        return;
+    }
+    if (b < a.wblock0[6]) {
+        int j = 0;
+#pragma unroll
+        for (int k = 1; k < 6; ++k)
+            if (b >= a.wblock0[k]) j = k;
+        const GradFinal::Wjob& J = a.w[j];
+        const long count = 9L * J.qc * J.pc;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const long e = (b - a.wblock0[j]) * 64L + lane;
+        float s = 0.0f;
+        if (e < count) {
+            int k = wv;
+            for (; k + 48 < J.nchunks; k += 64) {
+                const float a0 = J.partial[(long)k * count + e], a1 = J.partial[(long)(k + 16) * count + e];
+                const float a2 = J.partial[(long)(k + 32) * count + e], a3 = J.partial[(long)(k + 48) * count + e];
+                s += a0; s += a1; s += a2; s += a3;
+            }
+            for (; k < J.nchunks; k += 16) s += J.partial[(long)k * count + e];
+        }
+        red[wv * 64 + lane] = s;
+        __syncthreads();
+        if (wv == 0 && e < count) {
+            float v = 0.0f;
+#pragma unroll
+            for (int w = 0; w < 16; ++w) v += red[w * 64 + lane];
+            const int cp = (int)(e % J.pc);
+            const int jj = (int)(e / J.pc);
+            const int t = jj / J.qc, c = jj - t * J.qc;
+            const int co = J.q_is_cout ? c : cp, ci = J.q_is_cout ? cp : c;
+            const int cin = J.q_is_cout ? J.pc : J.qc;
+            J.dw[((long)co * 9 + t) * cin + ci] = v * J.scale;
+        }
+        return;
+    }
+    // bias slots 4 (b - first) .. + 3
+    const int q = threadIdx.x >> 8, t = threadIdx.x & 255;
+    const int c = 4 * (b - a.wblock0[6]) + q;
+    float s = 0.0f;
+    if (c < a.bslots)
+        for (int r = t; r < a.bnrows; r += 256) s += a.bpart[(long)r * a.bslots + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (t == 0 && c < a.bslots) {
+        int l = 0;
+#pragma unroll
+        for (int k = 1; k < 6; ++k)
+            if (c >= a.bs0[k]) l = k;
+        a.bdparams[a.boff[l] + (c - a.bs0[l])] = red[threadIdx.x] * a.bscale;
+    }
+}
+
+drc_status grad_final_launch(const GradFinal& g, hipStream_t s) {
+    GradFinalArgs a;
+    memset(&a, 0, sizeof a);
+    int blocks = 0;
+    for (int k = 0; k < 6; ++k) {
+        a.wblock0[k] = blocks;
+        if (k < g.nw) {
+            a.w[k] = g.w[k];
+            blocks += (int)((9L * g.w[k].qc * g.w[k].pc + 63) / 64);
+        }
+    }
+    a.wblock0[6] = blocks;
+    if (g.bpart) {
+        a.bpart = g.bpart;
+        a.bnrows = g.bnrows;
+        a.bslots = g.bslots;
+        a.bscale = g.bscale;
+        a.bdparams = g.bdparams;
+        for (int l = 0; l < 6; ++l) a.boff[l] = g.boff[l];
+        for (int l = 0; l < 7; ++l) a.bs0[l] = g.bs0[l];
+        blocks += (g.bslots + 3) / 4;
+    }
+    a.lblock = -1;
+    if (g.loss) {
+        a.lblock = blocks++;
+        a.lpart = g.lpart;
+        a.lnparts = g.lnparts;
+        a.lcount = g.lcount;
+        a.loss = g.loss;
+    }
+    if (blocks == 0) return DRC_OK;
+    hipLaunchKernelGGL(grad_final_kernel, dim3(blocks), dim3(1024), 0, s, a);
+    return check_launch("gradient sums");
+}
+
 template <typename T>
 static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_raw, Src s0, Src s1,
                               int a_raw_c, float* partial, float* out, float scale, int circ, hipStream_t s,
-                              const int32_t* roll = nullptr, const int32_t* flip = nullptr) {
+                              const int32_t* roll = nullptr, const int32_t* flip = nullptr,
+                              GradFinal* defer = nullptr) {
+    // the fixed-order sum of the partial tiles: now, or recorded for grad_final_launch
+    auto final_sum = [&](int nchunks, const WgradPlan& wp) -> drc_status {
+        const long count = 9L * wp.qc * wp.pc;
+        if (defer) {
+            if (defer->nw >= 6) return drc_fail(DRC_ERR_STATE, "weight_grad: more than six deferred sums");
+            defer->w[defer->nw++] = GradFinal::Wjob{partial, nchunks, wp.qc, wp.pc, (int)kLayers[l].tconv, scale, out};
+            return check_launch("weight_grad");
+        }
+        hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)((count + 63) / 64)), dim3(1024), 0, s,
+                           (const float*)partial, nchunks, wp.qc, wp.pc, (int)kLayers[l].tconv, scale, out);
+        return check_launch("weight_grad");
+    };
     const LayerDef& L = kLayers[l];
     const WgradPlan wp = wgrad_plan(l, n, H, W, sizeof(T) == 2 ? P_BF16 : P_F32);
     int hin, win, hout, wout;
@@ -396,10 +539,7 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
             hipLaunchKernelGGL((wgrad_tr_kernel<4, 1, 4, 4, kWgradTGRaw3, kWgradTP, 3>), grid, block, wp.lds, s, b);
         else
             return drc_fail(DRC_ERR_STATE, "weight_grad: no transpose-read kernel for layer %d", l);
-        const long count = 9L * wp.qc * wp.pc;
-        hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)((count + 63) / 64)), dim3(1024), 0, s,
-                           (const float*)partial, wp.bchunks, wp.qc, wp.pc, (int)L.tconv, scale, out);
-        return check_launch("weight_grad");
+        return final_sum(wp.bchunks, wp);
     }
     if (wp.bf16) {
         WgradBArgs b;
@@ -430,10 +570,7 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
             hipLaunchKernelGGL((wgrad_bf16_kernel<5, 4, 32>), grid, dim3(256), wp.lds, s, b);
         else
             hipLaunchKernelGGL((wgrad_bf16_kernel<9, 4, 64>), grid, dim3(256), wp.lds, s, b);
-        const long count = 9L * wp.qc * wp.pc;
-        hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)((count + 63) / 64)), dim3(1024), 0, s,
-                           (const float*)partial, wp.bchunks, wp.qc, wp.pc, (int)L.tconv, scale, out);
-        return check_launch("weight_grad");
+        return final_sum(wp.bchunks, wp);
     }
     WgradArgs a;
     memset(&a, 0, sizeof a);
@@ -481,10 +618,7 @@ static drc_status weight_grad(int l, int n, int H, int W, const void* g, bool g_
         hipLaunchKernelGGL((wgrad_kernel<T, 4, 2, 1>), grid, dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL((wgrad_kernel<T, 2, 4, 1>), grid, dim3(256), 0, s, a);
-    const long count = 9L * wp.qc * wp.pc;
-    hipLaunchKernelGGL(wgrad_final_kernel, dim3((int)((count + 63) / 64)), dim3(1024), 0, s,
-                       (const float*)partial, 4 * wp.nchunks, wp.qc, wp.pc, (int)L.tconv, scale, out);
-    return check_launch("weight_grad");
+    return final_sum(4 * wp.nchunks, wp);
 }
 
 struct BwdBufs {
@@ -497,6 +631,12 @@ struct BwdBufs {
     BwdLayout L;
     const int32_t* roll = nullptr;  // x is read augmented (AugMap) by E1's weight gradient
     const int32_t* flip = nullptr;
+    // a training step's L1 loss partials, summed into *loss by the backward
+    // (with its other fixed-order sums when those are deferred)
+    const double* lpart = nullptr;
+    int lnparts = 0;
+    long lcount = 0;
+    float* loss = nullptr;
 };
 
 template <int P>
@@ -534,11 +674,29 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
     };
     ActSizes as = act_sizes(P, n, H, W);
     float* dp = b.dparams;
+    // on one stream, the fixed-order gradient sums (weights, and the biases
+    // of the data-gradient chain) run as one launch after the last weight
+    // gradient instead of one small launch each
+    GradFinal gf;
+    GradFinal* dfr = kFork ? nullptr : &gf;
+    if (b.loss) {
+        if (dfr) {
+            gf.lpart = b.lpart;
+            gf.lnparts = b.lnparts;
+            gf.lcount = b.lcount;
+            gf.loss = b.loss;
+        } else {
+            const long ltok = prof_begin(h, PROF_LOSS, s);
+            hipLaunchKernelGGL(l1_final_kernel, dim3(1), dim3(256), 0, s, b.lpart, b.lnparts, b.lcount, b.loss);
+            prof_end(h, ltok, s);
+            TRY(check_launch("step/l1 final"));
+        }
+    }
     // BF16 32x32 / 64x64: all data gradients of D1..E2 in one kernel first
     const bool fdg = P == P_BF16 && h->fused && fused_forward_size(H, W);
     if (fdg)
         TRY(fused_dgrad(h, n, H, W, b.dy, b.u2, b.u3, b.h3, b.h2, b.h1, dz_u2, dh1s, dz_u3, dz_h3, dz_h2, dz_h1,
-                        bpart, L.bpart_bytes, dp, gscale, s));
+                        bpart, L.bpart_bytes, dp, gscale, s, dfr));
 
     // D1: y = tconv([u2|h1]); its data gradient is a stride-2 conv of dy.
     {
@@ -557,7 +715,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         prof_end(h, tok, s); }
         TRY(wgrad_on(5, [&](float* wpart, hipStream_t ss) {
             return weight_grad<T>(5, n, H, W, b.dy, true, Src{b.u2, 32, 32}, Src{b.h1, 32, 32}, 0, wpart,
-                                  dp + layer_w_offset(5), gscale, circ, ss);
+                                  dp + layer_w_offset(5), gscale, circ, ss, nullptr, nullptr, dfr);
         }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(b.dy, true, 3, as.p0, bpart, dp + layer_b_offset(5), gscale, s));
@@ -579,7 +737,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         prof_end(h, tok, s); }
         TRY(wgrad_on(4, [&](float* wpart, hipStream_t ss) {
             return weight_grad<T>(4, n, H, W, dz_u2, false, Src{b.u3, 64, 64}, Src{b.h2, 64, 64}, 0, wpart,
-                                  dp + layer_w_offset(4), gscale, circ, ss);
+                                  dp + layer_w_offset(4), gscale, circ, ss, nullptr, nullptr, dfr);
         }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_u2, false, 32, as.p1, bpart, dp + layer_b_offset(4), gscale, s));
@@ -600,7 +758,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         prof_end(h, tok, s); }
         TRY(wgrad_on(3, [&](float* wpart, hipStream_t ss) {
             return weight_grad<T>(3, n, H, W, dz_u3, false, Src{b.h3, 128, 128}, Src{nullptr, 0, 0}, 0, wpart,
-                                  dp + layer_w_offset(3), gscale, circ, ss);
+                                  dp + layer_w_offset(3), gscale, circ, ss, nullptr, nullptr, dfr);
         }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_u3, false, 64, as.p2, bpart, dp + layer_b_offset(3), gscale, s));
@@ -623,7 +781,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         prof_end(h, tok, s); }
         TRY(wgrad_on(2, [&](float* wpart, hipStream_t ss) {
             return weight_grad<T>(2, n, H, W, dz_h3, false, Src{b.h2, 64, 64}, Src{nullptr, 0, 0}, 0, wpart,
-                                  dp + layer_w_offset(2), gscale, circ, ss);
+                                  dp + layer_w_offset(2), gscale, circ, ss, nullptr, nullptr, dfr);
         }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_h3, false, 128, as.p3, bpart, dp + layer_b_offset(2), gscale, s));
@@ -646,7 +804,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
         prof_end(h, tok, s); }
         TRY(wgrad_on(1, [&](float* wpart, hipStream_t ss) {
             return weight_grad<T>(1, n, H, W, dz_h2, false, Src{b.h1, 32, 32}, Src{nullptr, 0, 0}, 0, wpart,
-                                  dp + layer_w_offset(1), gscale, circ, ss);
+                                  dp + layer_w_offset(1), gscale, circ, ss, nullptr, nullptr, dfr);
         }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_h2, false, 64, as.p2, bpart, dp + layer_b_offset(1), gscale, s));
@@ -656,7 +814,7 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
     {
         TRY(wgrad_on(0, [&](float* wpart, hipStream_t ss) {
             return weight_grad<T>(0, n, H, W, dz_h1, false, Src{b.x, 7, 7}, Src{nullptr, 0, 0}, 7, wpart,
-                                  dp + layer_w_offset(0), gscale, circ, ss, b.roll, b.flip);
+                                  dp + layer_w_offset(0), gscale, circ, ss, b.roll, b.flip, dfr);
         }));
         if (!fdg) { const long tok = prof_begin(h, PROF_BIAS, s);
         TRY(bias_grad<T>(dz_h1, false, 32, as.p1, bpart, dp + layer_b_offset(0), gscale, s));
@@ -673,6 +831,11 @@ static drc_status backward_seq(drc_cae* h, const BwdBufs& b, int n, int H, int W
             TRY(run_gemm<P>(0, true, a, fit_npw(default_npw(P, 0, true), gemm_pixels(a), h->num_cu), h->num_cu, s));
             prof_end(h, tok, s); }
         }
+    }
+    if (dfr) {
+        const long tok = prof_begin(h, PROF_BIAS, s);
+        TRY(grad_final_launch(gf, s));
+        prof_end(h, tok, s);
     }
     // join the side streams
     for (int k = 0; k < drc_cae::kSide && kFork; ++k) {
@@ -827,8 +990,6 @@ static drc_status step_enqueue(drc_cae* h, float* d_params, float* d_m, float* d
     const long ltok = prof_begin(h, PROF_LOSS, s);
     hipLaunchKernelGGL(l1_partial_kernel, dim3(nparts), dim3(256), 0, s, (const float*)y, d_target, M, kLossPerBlock,
                        1.0f, dy, (double*)(ws + S.loss_part), roll, flip, H, W);
-    hipLaunchKernelGGL(l1_final_kernel, dim3(1), dim3(256), 0, s, (const double*)(ws + S.loss_part), nparts, M,
-                       d_loss);
     prof_end(h, ltok, s);
     TRY(check_launch("step/l1"));
 
@@ -846,6 +1007,10 @@ static drc_status step_enqueue(drc_cae* h, float* d_params, float* d_m, float* d
     b.L = bwd_layout(h->prec, n, H, W, h->recompute != 0);
     b.roll = roll;
     b.flip = flip;
+    b.lpart = (const double*)(ws + S.loss_part);  // the loss: summed by the backward
+    b.lnparts = nparts;
+    b.lcount = M;
+    b.loss = d_loss;
     if (h->recompute) TRY(recompute_acts(h, b, n, H, W, s));
     TRY(backward_dispatch(h, b, n, H, W, (float)(1.0 / (double)M), s));
 
