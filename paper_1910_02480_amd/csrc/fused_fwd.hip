@@ -402,7 +402,10 @@ __device__ __forceinline__ void pairs_panel_load(PairsPanel<CIN / 32, MT>& P, co
         for (int e = 0; e < 4; ++e) P.bias[m][e] = bias_g ? bg[(tr * MT + m) * 16 + g * 4 + e] : 0.0f;
 }
 
-template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW, int SET, int NPB, int ORING, class Epi>
+// IR0 / IR1 > 0: source 0 / 1 is a ring of that many rows in LDS (input row
+// r at slot r % IR); 0: the whole tensor, row r at slot r.
+template <int HI, int WI, int C0, int C1, int COUT, int MT, int NPW, int SET, int NPB, int ORING, class Epi,
+          int IR0 = 0, int IR1 = 0>
 __device__ __forceinline__ void pairs_tiles(const PairsPanel<(C0 + C1) / 32, MT>& P, char* smem, int in0, int in1,
                                             int zoff, int tr, int tp0, int tp_step, int pix0, const Epi& epi) {
     constexpr int CIN = C0 + C1, KSN = CIN / 32;
@@ -428,9 +431,19 @@ __device__ __forceinline__ void pairs_tiles(const PairsPanel<(C0 + C1) / 32, MT>
             for (int s = 0; s < NSRC; ++s)
 #pragma unroll
                 for (int dj = 0; dj < 2; ++dj) {
-                    const int b = (s ? in1 : in0) + loff<C0, WI>(ia[p], ib[p] + dj, g);
+                    constexpr int IR = 0;
+                    const int ir = s ? IR1 : IR0;
+                    int b, bd;
+                    if (ir == IR) {
+                        b = (s ? in1 : in0) + loff<C0, WI>(ia[p], ib[p] + dj, g);
+                        bd = b + ROW;
+                    } else {
+                        const int c = (s ? in1 : in0) + loff<C0, WI>(0, ib[p] + dj, g);
+                        b = c + (int)((unsigned)ia[p] % (unsigned)(ir > 0 ? ir : 1)) * ROW;
+                        bd = c + (int)((unsigned)(ia[p] + 1) % (unsigned)(ir > 0 ? ir : 1)) * ROW;
+                    }
                     off[p][s][dj] = (dj && !right) ? zoff : b;
-                    off[p][s][2 + dj] = ((dj && !right) || !down) ? zoff : b + ROW;
+                    off[p][s][2 + dj] = ((dj && !right) || !down) ? zoff : bd;
                     // a pixel block is one input row here: its upper neighbours are the
                     // lower neighbours of the block above, so the same offsets (and loads) serve
                     if constexpr (WI == 16)
@@ -756,6 +769,271 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
 }
 
 // ======================================================================
+// E3, D3 and D2 of large maps (128 x 128) in one kernel, by bands of rows:
+// the layer path's h2 (plain NHWC BF16 in HBM) in, u2 out; h3 and u3 never
+// leave LDS. One map per workgroup pass, in two sweeps over bands of two h3
+// rows (four h2 rows). Sweep 1: E3 turns h2 rows 4j - 1 .. 4j + 3 (a ring of
+// 5 rows, the next band's rows loaded during the MFMAs) into h3 rows 2j,
+// 2j + 1 (h3 is kept whole, 64 KB). Sweep 2: D3 writes the four u3 rows of
+// band j into a ring of 8 rows, and D2 then turns the four u3 rows of band
+// j - 1 (with the next row, written by band j's D3, as their lower
+// neighbours) and the same h2 rows (the ring, staged again) into eight u2
+// rows, stored straight from the MFMA results. GEMMs and epilogues are the
+// layer kernels', so u2 is bitwise the layer path's.
+//   RH3 [0, 256 H3 W3)  h3;  RU3 u3 ring (8 rows of W2 x 64 ch);  RH2 h2 ring
+//   (5 rows of W2 x 64 ch);  zeros.  116 KB at 128 x 128.
+
+// Stride-2 3x3 convolution over a band of output pixel blocks (CIN >= 32),
+// LDS -> epilogue, with the weights (MT row blocks of group tr, every K step)
+// already in registers and the input a ring of IR rows (input row r at slot
+// r % IR). Same taps, K order and epilogue as conv_phase.
+template <int KSTEPS, int MT>
+struct ConvPanel {
+    uint4 A[KSTEPS][MT];
+    float bias[MT][4];
+};
+template <int CIN, int MT>
+__device__ __forceinline__ void conv_panel_load(ConvPanel<(9 * CIN + 31) / 32, MT>& P, const uint16_t* wp,
+                                                const float* bias_g, int tr) {
+    constexpr int KSTEPS = (9 * CIN + 31) / 32;
+    const int lane = opaque_tid() & 63, g = lane >> 4;
+    const uint16_t* w = opaque(wp);
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS; ++ks)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            P.A[ks][m] = *(const uint4*)(w + ((size_t)((tr * MT + m) * KSTEPS + ks) * 64 + lane) * 8);
+    const float* bg = opaque(bias_g);
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) P.bias[m][e] = bg[(tr * MT + m) * 16 + g * 4 + e];
+}
+template <int HI, int WI, int CIN, int MT, int NPW, int NPB, int IR, class Epi>
+__device__ __forceinline__ void conv_tiles(const ConvPanel<(9 * CIN + 31) / 32, MT>& P, char* smem, int in,
+                                           int zoff, int tr, int tp0, int tp_step, int pix0, const Epi& epi) {
+    constexpr int WO = WI / 2;
+    constexpr int KSTEPS = (9 * CIN + 31) / 32;
+    constexpr int ROW = WI * CIN * 2;
+    constexpr int TP = NPB / NPW;
+    static_assert(CIN >= 32 && NPB % NPW == 0 && IR > 0, "band of whole tiles from a ring");
+    const int lane = opaque_tid() & 63;
+    const int g = lane >> 4, r16 = lane & 15;
+    for (int tp = tp0; tp < TP; tp += tp_step) {
+        int oy[NPW], ox[NPW];
+#pragma unroll
+        for (int p = 0; p < NPW; ++p) {
+            const int pix = pix0 + (tp * NPW + p) * 16 + r16;
+            oy[p] = (int)((unsigned)pix / WO);
+            ox[p] = (int)((unsigned)pix % WO);
+        }
+        int off[NPW][9];
+#pragma unroll
+        for (int p = 0; p < NPW; ++p) {
+            const bool top = oy[p] > 0, left = ox[p] > 0;
+#pragma unroll
+            for (int kw = 0; kw < 3; ++kw) {
+                const int c = in + loff<CIN, WI>(0, 2 * ox[p] + kw - 1, g);
+#pragma unroll
+                for (int kh = 0; kh < 3; ++kh) {
+                    const int r = 2 * oy[p] - 1 + kh;
+                    off[p][kh * 3 + kw] = ((kh == 0 && !top) || (kw == 0 && !left))
+                                              ? zoff
+                                              : c + (int)((unsigned)r % (unsigned)IR) * ROW;
+                }
+                if constexpr (WO == 16)
+                    if (p > 0) off[p][kw] = off[p - 1][6 + kw];
+            }
+        }
+        typename Epi::Pre pre[MT][NPW];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) epi.prefetch(pre[m][p], m, (tr * MT + m) * 16 + g * 4, oy[p], ox[p]);
+        f4 acc[MT][NPW];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) acc[m][p] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            uint4 b[NPW];
+            const int t = ks * 32 / CIN, c0 = ks * 32 % CIN;
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) b[p] = lds16(smem, off[p][t] ^ (c0 / 8 * 16));
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int p = 0; p < NPW; ++p) mma(acc[m][p], P.A[ks][m], b[p]);
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int ch = (tr * MT + m) * 16 + g * 4;
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) epi(pre[m][p], m, ch, oy[p], ox[p], acc[m][p], P.bias[m]);
+        }
+    }
+}
+
+// Epilogue: bias + ReLU, BF16 into a plain NHWC tensor (C channels, WO wide) in global memory.
+template <int C, int WO>
+struct GlobalOut {
+    uint16_t* dst;
+    struct Pre {};
+    __device__ __forceinline__ void prefetch(Pre&, int, int, int, int) const {}
+    __device__ __forceinline__ void operator()(const Pre&, int, int ch, int y, int x, const f4& acc,
+                                               const float* bias) const {
+        uint2 w;
+        w.x = pack_bf16x2(drc::relu(acc.x + bias[0]), drc::relu(acc.y + bias[1]));
+        w.y = pack_bf16x2(drc::relu(acc.z + bias[2]), drc::relu(acc.w + bias[3]));
+        *(uint2*)(dst + ((long)y * WO + x) * C + ch) = w;
+    }
+};
+
+// Rows [r0, r1) of a plain NHWC tensor (C channels, WI wide; src = its row 0)
+// into slots r % RING of an LDS ring with the column swizzle.
+template <int C, int WI, int RING>
+__device__ __forceinline__ void copy_rows_in(char* smem, int region, const char* src, int r0, int r1) {
+    constexpr int CH = C / 8, PER_ROW = WI * CH;
+    const int N = (r1 - r0) * PER_ROW;
+    for (int i = threadIdx.x; i < N; i += FT) {
+        const int r = r0 + (int)((unsigned)i / PER_ROW), rem = (int)((unsigned)i % PER_ROW);
+        const int x = rem / CH, j = rem - x * CH;
+        *(uint4*)(smem + region + (int)((unsigned)r % RING) * (WI * C * 2) + loff<C, WI>(0, x, j)) =
+            ((const uint4*)src)[(long)r0 * PER_ROW + i];
+    }
+}
+
+// NR rows of a plain NHWC tensor (C channels, WI wide) carried in registers
+// from their global loads (issued before the MFMAs of a band) to their LDS
+// stores (after it), rows at or past `rows` skipped.
+template <int C, int WI, int NR>
+struct RowsPiece {
+    static constexpr int PER_ROW = WI * C / 8, N = NR * PER_ROW, K = (N + FT - 1) / FT;
+    uint4 v[K];
+    __device__ __forceinline__ void load(const char* src, int r0, int rows) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = (int)threadIdx.x + k * FT;
+            if ((N % FT == 0 || i < N) && r0 + i / PER_ROW < rows)
+                v[k] = ((const uint4*)src)[(long)r0 * PER_ROW + i];
+        }
+    }
+    template <int RING>
+    __device__ __forceinline__ void store(char* smem, int region, int r0, int rows) const {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = (int)threadIdx.x + k * FT;
+            const int r = r0 + i / PER_ROW, rem = i % PER_ROW;
+            const int x = rem / (C / 8), j = rem - x * (C / 8);
+            if ((N % FT == 0 || i < N) && r < rows)
+                *(uint4*)(smem + region + (int)((unsigned)r % RING) * (WI * C * 2) + loff<C, WI>(0, x, j)) = v[k];
+        }
+    }
+};
+
+struct TailArgs {
+    const uint16_t* h2;  // [n][H/4][W/4][64]
+    uint16_t* u2;        // [n][H/2][W/2][32]
+    int nmaps;
+    const uint16_t* w[3];  // E3, D3, D2 forward packs in fragment order
+    const float* b[3];
+};
+
+template <int H, int W>
+struct TailLds {
+    static constexpr int H3 = H / 8, W3 = W / 8, W2 = W / 4;
+    static constexpr int RH3 = 0;
+    static constexpr int RU3 = H3 * W3 * 256;
+    static constexpr int RH2 = RU3 + 8 * W2 * 128;
+    static constexpr int ZO = RH2 + 5 * W2 * 128;
+    static constexpr int BYTES = ZO + kZeroBytes;
+};
+
+template <int H, int W>
+__global__ __launch_bounds__(FT) void cae_fused_tail_kernel(const TailArgs a) {
+    __shared__ __align__(16) char smem[TailLds<H, W>::BYTES];
+    typedef TailLds<H, W> L;
+    constexpr int H3 = H / 8, W3 = W / 8, H2 = H / 4, W2 = W / 4;
+    constexpr int NB = H3 / 2;  // bands of two h3 rows = four h2 rows
+    constexpr long S2 = (long)H2 * W2 * 64, SU = (long)(H / 2) * (W / 2) * 32;
+    static_assert(W3 == 16 && (2 * W3) % 16 == 0 && (4 * W2) % 16 == 0, "D3 pixel blocks are h3 rows");
+    if (threadIdx.x < kZeroBytes / 16) *(uint4*)(smem + L::ZO + 16 * threadIdx.x) = uint4{0u, 0u, 0u, 0u};
+    constexpr int E3PB = 2 * W3 / 16;  // output pixel blocks of an E3 band
+    constexpr int D3PB = 2 * W3 / 16;  // pixel blocks of a D3 band
+    constexpr int D2PB = 4 * W2 / 16;  // pixel blocks of a D2 band
+    for (int m = blockIdx.x; m < a.nmaps; m += gridDim.x) {
+        const char* h2m = (const char*)(a.h2 + m * S2);
+        // E3: 8 row blocks, one per wave; D3: 4 row blocks x 2 sets, one group
+        // per wave; D2: 2 row blocks x 2 sets, two waves per group. Formed per
+        // map from the opaque thread index, so that the weight addresses are
+        // not hoisted out of the map loop (they would be kept in registers).
+        const int wave = opaque_tid() >> 6;
+        const int tre = (wave + blockIdx.x) % 8;
+        const int g3 = (wave + blockIdx.x) % 8, tr3 = g3 >> 1, set3 = g3 & 1;
+        const int g2 = (wave + blockIdx.x) % 4, tr2 = g2 >> 1, set2 = g2 & 1;
+        {   // sweep 1: E3, h2 -> h3
+            ConvPanel<18, 1> PE;
+            conv_panel_load<64, 1>(PE, a.w[0], a.b[0], tre);
+            copy_rows_in<64, W2, 5>(smem, L::RH2, h2m, 0, 4);
+            const LdsOut<128, W3> h3out{smem, L::RH3};
+            __syncthreads();
+            for (int j = 0; j < NB; ++j) {
+                RowsPiece<64, W2, 4> hp;  // h2 rows 4j + 4 .. 4j + 7 of the next band
+                if (j + 1 < NB) hp.load(h2m, 4 * j + 4, H2);
+                conv_tiles<H2, W2, 64, 1, 2, E3PB, 5>(PE, smem, L::RH2, L::ZO, tre, 0, 1, j * E3PB * 16, h3out);
+                __syncthreads();
+                if (j + 1 < NB) {
+                    hp.template store<5>(smem, L::RH2, 4 * j + 4, H2);
+                    __syncthreads();
+                }
+            }
+        }
+        PairsPanel<4, 1> P3, P2;
+        pairs_panel_load<64, 128, 1>(P3, a.w[1], a.b[1], tr3, set3);
+        pairs_panel_load<32, 128, 1>(P2, a.w[2], a.b[2], tr2, set2);
+        copy_rows_in<64, W2, 5>(smem, L::RH2, h2m, 0, 5);
+        const LdsOut<64, W2> u3ring{smem, L::RU3};
+        const GlobalOut<32, W / 2> u2out{a.u2 + m * SU};
+        __syncthreads();
+        for (int j = 0; j <= NB; ++j) {
+            // h2 rows 4j + 1 .. 4j + 4 of D2 band j (row 4j is already in the
+            // ring): loaded now, stored once D2 band j - 1 is done with their slots
+            RowsPiece<64, W2, 4> hp;
+            const bool stage = j >= 1 && j < NB;
+            if (stage) hp.load(h2m, 4 * j + 1, H2);
+            // D3 band j: h3 rows [2j, 2j + 2) -> u3 rows [4j, 4j + 4)
+            if (j < NB) {
+                if (set3 == 0)
+                    pairs_tiles<H3, W3, 128, 0, 64, 1, 2, 0, D3PB, 8>(P3, smem, L::RH3, L::RH3, L::ZO, tr3, 0, 1,
+                                                                     j * D3PB * 16, u3ring);
+                else
+                    pairs_tiles<H3, W3, 128, 0, 64, 1, 2, 1, D3PB, 8>(P3, smem, L::RH3, L::RH3, L::ZO, tr3, 0, 1,
+                                                                     j * D3PB * 16, u3ring);
+            }
+            __syncthreads();
+            if (j == 0) continue;
+            // D2 band j - 1: [u3 | h2] rows [4j - 4, 4j) -> u2 rows [8j - 8, 8j)
+            const int jb = j - 1;
+            if (set2 == 0)
+                pairs_tiles<H2, W2, 64, 64, 32, 1, 1, 0, D2PB, 0, GlobalOut<32, W / 2>, 8, 5>(
+                    P2, smem, L::RU3, L::RH2, L::ZO, tr2, wave / 4, 2, jb * D2PB * 16, u2out);
+            else
+                pairs_tiles<H2, W2, 64, 64, 32, 1, 1, 1, D2PB, 0, GlobalOut<32, W / 2>, 8, 5>(
+                    P2, smem, L::RU3, L::RH2, L::ZO, tr2, wave / 4, 2, jb * D2PB * 16, u2out);
+            __syncthreads();
+            if (stage) hp.template store<5>(smem, L::RH2, 4 * j + 1, H2);
+        }
+    }
+}
+
+template <int H, int W>
+drc_status launch_tail(const TailArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((cae_fused_tail_kernel<H, W>), dim3(grid), dim3(FT), 0, s, a);
+    return check_launch("fused tail");
+}
+
+// ======================================================================
 // Data-gradient chain of the training backward (Sec. 4.3), one map per
 // workgroup pass: dy -> D1^T -> D2^T
 // -> D3^T -> E3^T -> E2^T, each a stride-2 (transposed) convolution with the
@@ -1049,6 +1327,29 @@ FusedArgs fused_args(const drc_cae* h, int n) {
 
 // Map sizes the fused kernel is built for.
 bool fused_forward_size(int H, int W) { return (H == 64 && W == 64) || (H == 32 && W == 32); }
+
+// Map sizes whose D3 and D2 run fused (fused_tail).
+bool fused_tail_size(int H, int W) { return H == 128 && W == 128; }
+
+drc_status fused_tail(drc_cae* h, int n, int H, int W, const void* h2, void* u2, hipStream_t s) {
+    if (h->prec != P_BF16 || !fused_tail_size(H, W) || h->desc.pad_w != DRC_PAD_ZERO)
+        return drc_fail(DRC_ERR_UNSUPPORTED, "fused tail: BF16 maps of 128x128 with zero padding only");
+    if (n < 1) return DRC_OK;
+    TailArgs a;
+    memset(&a, 0, sizeof a);
+    a.h2 = (const uint16_t*)h2;
+    a.u2 = (uint16_t*)u2;
+    a.nmaps = n;
+    for (int l = 2; l < 5; ++l) {
+        a.w[l - 2] = (const uint16_t*)h->wfrag[l];
+        a.b[l - 2] = h->bias + bias_slot(l);
+    }
+    const int grid = std::max(1, std::min(n, h->num_cu));
+    const long tok = prof_begin(h, PROF_FWD + 3, s);
+    const drc_status st = launch_tail<128, 128>(a, grid, s);
+    prof_end(h, tok, s);
+    return st;
+}
 
 // Workgroups of one fused launch over n maps of H x W.
 int fused_forward_grid(const drc_cae* h, int n, int H, int W) {

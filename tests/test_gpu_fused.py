@@ -119,6 +119,20 @@ def test_fused_training_step_matches_layer_path(params):
         np.testing.assert_array_equal(res[True][2][ws], res[False][2][ws])
 
 
+# BF16 128x128: D3 and D2 in the banded tail kernel (h3, h2 in; u2 out) against the layer path
+@pytest.mark.parametrize("n", [1, 3, 300])
+def test_fused_tail_128_matches_layer_path_bitwise(params, n):
+    from paper_1910_02480_amd.cae import CAE
+    print(f"[fused-tail] H=128 n={n}", flush=True)
+    cae = CAE("bf16", torch.from_numpy(params).to(DEV), device=DEV)
+    x = torch.from_numpy(synth.radiance_maps(n, 128, 128, seed=23)).to(DEV)
+    y_tail = cae.forward(x).cpu().numpy()
+    cae.set_fused(False)
+    y_layer = cae.forward(x).cpu().numpy()
+    assert np.isfinite(y_tail).all()
+    np.testing.assert_array_equal(y_tail, y_layer)
+
+
 # FP8 (e4m3, per-tensor scales): the whole-network kernel against the FP8 layer path
 @pytest.mark.parametrize("H,n", [(64, 1), (64, 3), (64, 600), (32, 1), (32, 1100)])
 def test_fused_fp8_matches_layer_path_bitwise(params, H, n):
