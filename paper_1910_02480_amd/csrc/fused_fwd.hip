@@ -769,19 +769,22 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
 }
 
 // ======================================================================
-// E3, D3 and D2 of large maps (128 x 128) in one kernel, by bands of rows:
-// the layer path's h2 (plain NHWC BF16 in HBM) in, u2 out; h3 and u3 never
-// leave LDS. One map per workgroup pass, in two sweeps over bands of two h3
-// rows (four h2 rows). Sweep 1: E3 turns h2 rows 4j - 1 .. 4j + 3 (a ring of
-// 5 rows, the next band's rows loaded during the MFMAs) into h3 rows 2j,
-// 2j + 1 (h3 is kept whole, 64 KB). Sweep 2: D3 writes the four u3 rows of
-// band j into a ring of 8 rows, and D2 then turns the four u3 rows of band
-// j - 1 (with the next row, written by band j's D3, as their lower
-// neighbours) and the same h2 rows (the ring, staged again) into eight u2
+// E2, E3, D3 and D2 of large maps (128 x 128) in one kernel, by bands of
+// rows: the layer path's h1 (plain NHWC BF16 in HBM) in, h2 (for D2) and u2
+// out; h3 and u3 never leave LDS. One map per workgroup pass, in two sweeps
+// over bands of two h3 rows (four h2 rows, eight h1 rows). Sweep 1: E2 turns
+// h1 rows 8j - 1 .. 8j + 7 (a ring of 9 rows, the next band's rows loaded
+// during the MFMAs) into h2 rows 4j .. 4j + 3, written to HBM and to a ring
+// of 5 h2 rows, from which E3 forms h3 rows 2j, 2j + 1 (h3 is kept whole,
+// 64 KB). Sweep 2: D3 writes the four u3 rows of band j into a ring of 8
+// rows (over the h1 ring), and D2 then turns the four u3 rows of band j - 1
+// (with the next row, written by band j's D3, as their lower neighbours)
+// and the same h2 rows (the ring, staged again from HBM) into eight u2
 // rows, stored straight from the MFMA results. GEMMs and epilogues are the
-// layer kernels', so u2 is bitwise the layer path's.
-//   RH3 [0, 256 H3 W3)  h3;  RU3 u3 ring (8 rows of W2 x 64 ch);  RH2 h2 ring
-//   (5 rows of W2 x 64 ch);  zeros.  116 KB at 128 x 128.
+// layer kernels', so h2 and u2 are bitwise the layer path's.
+//   RH3 [0, 256 H3 W3)  h3;  RX h1 ring (9 rows of W1 x 32 ch), then u3 ring
+//   (8 rows of W2 x 64 ch);  RH2 h2 ring (5 rows of W2 x 64 ch);  zeros.
+//   120 KB at 128 x 128.
 
 // Stride-2 3x3 convolution over a band of output pixel blocks (CIN >= 32),
 // LDS -> epilogue, with the weights (MT row blocks of group tr, every K step)
@@ -890,6 +893,26 @@ struct GlobalOut {
     }
 };
 
+// Epilogue: bias + ReLU, BF16, into a ring of RING rows in LDS (C channels,
+// WO wide, column swizzle) and into a plain NHWC tensor in global memory.
+template <int C, int WO, int RING>
+struct RingGlobalOut {
+    char* smem;
+    int region;
+    uint16_t* dst;
+    struct Pre {};
+    __device__ __forceinline__ void prefetch(Pre&, int, int, int, int) const {}
+    __device__ __forceinline__ void operator()(const Pre&, int, int ch, int y, int x, const f4& acc,
+                                               const float* bias) const {
+        uint2 w;
+        w.x = pack_bf16x2(drc::relu(acc.x + bias[0]), drc::relu(acc.y + bias[1]));
+        w.y = pack_bf16x2(drc::relu(acc.z + bias[2]), drc::relu(acc.w + bias[3]));
+        *(uint2*)(smem + region + (int)((unsigned)y % RING) * (WO * C * 2) + loff<C, WO>(0, x, ch >> 3) +
+                  ((ch >> 2) & 1) * 8) = w;
+        *(uint2*)(dst + ((long)y * WO + x) * C + ch) = w;
+    }
+};
+
 // Rows [r0, r1) of a plain NHWC tensor (C channels, WI wide; src = its row 0)
 // into slots r % RING of an LDS ring with the column swizzle.
 template <int C, int WI, int RING>
@@ -910,42 +933,77 @@ __device__ __forceinline__ void copy_rows_in(char* smem, int region, const char*
 template <int C, int WI, int NR>
 struct RowsPiece {
     static constexpr int PER_ROW = WI * C / 8, N = NR * PER_ROW, K = (N + FT - 1) / FT;
-    uint4 v[K];
-    __device__ __forceinline__ void load(const char* src, int r0, int rows) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
+    static_assert(K <= 4, "at most four 16-byte chunks per thread");
+    // named members of a native vector type, not an array of uint4: the
+    // latter's copies are memcpys that keep the whole piece in memory (LDS or
+    // scratch) rather than in registers
+    typedef unsigned V4 __attribute__((ext_vector_type(4)));
+    V4 v0, v1, v2, v3;
+    template <int k>
+    __device__ __forceinline__ V4& at() {
+        if constexpr (k == 0) return v0;
+        else if constexpr (k == 1) return v1;
+        else if constexpr (k == 2) return v2;
+        else return v3;
+    }
+    template <int k>
+    __device__ __forceinline__ const V4& at() const {
+        if constexpr (k == 0) return v0;
+        else if constexpr (k == 1) return v1;
+        else if constexpr (k == 2) return v2;
+        else return v3;
+    }
+    // every lane loads (chunks past the tensor read its first chunk and are
+    // never stored), so the loads carry no branches
+    template <int k>
+    __device__ __forceinline__ void load1(const char* src, int r0, int rows) {
+        if constexpr (k < K) {
             const int i = (int)threadIdx.x + k * FT;
-            if ((N % FT == 0 || i < N) && r0 + i / PER_ROW < rows)
-                v[k] = ((const uint4*)src)[(long)r0 * PER_ROW + i];
+            const bool ok = (N % FT == 0 || i < N) && r0 + i / PER_ROW < rows;
+            at<k>() = ((const V4*)src)[ok ? (long)r0 * PER_ROW + i : 0L];
         }
     }
-    template <int RING>
-    __device__ __forceinline__ void store(char* smem, int region, int r0, int rows) const {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
+    template <int RING, int k>
+    __device__ __forceinline__ void store1(char* smem, int region, int r0, int rows) const {
+        if constexpr (k < K) {
             const int i = (int)threadIdx.x + k * FT;
             const int r = r0 + i / PER_ROW, rem = i % PER_ROW;
             const int x = rem / (C / 8), j = rem - x * (C / 8);
             if ((N % FT == 0 || i < N) && r < rows)
-                *(uint4*)(smem + region + (int)((unsigned)r % RING) * (WI * C * 2) + loff<C, WI>(0, x, j)) = v[k];
+                *(V4*)(smem + region + (int)((unsigned)r % RING) * (WI * C * 2) + loff<C, WI>(0, x, j)) = at<k>();
         }
+    }
+    __device__ __forceinline__ void load(const char* src, int r0, int rows) {
+        load1<0>(src, r0, rows);
+        load1<1>(src, r0, rows);
+        load1<2>(src, r0, rows);
+        load1<3>(src, r0, rows);
+    }
+    template <int RING>
+    __device__ __forceinline__ void store(char* smem, int region, int r0, int rows) const {
+        store1<RING, 0>(smem, region, r0, rows);
+        store1<RING, 1>(smem, region, r0, rows);
+        store1<RING, 2>(smem, region, r0, rows);
+        store1<RING, 3>(smem, region, r0, rows);
     }
 };
 
 struct TailArgs {
-    const uint16_t* h2;  // [n][H/4][W/4][64]
+    const uint16_t* h1;  // [n][H/2][W/2][32]
+    uint16_t* h2;        // [n][H/4][W/4][64]
     uint16_t* u2;        // [n][H/2][W/2][32]
     int nmaps;
-    const uint16_t* w[3];  // E3, D3, D2 forward packs in fragment order
-    const float* b[3];
+    const uint16_t* w[4];  // E2, E3, D3, D2 forward packs in fragment order
+    const float* b[4];
 };
 
 template <int H, int W>
 struct TailLds {
-    static constexpr int H3 = H / 8, W3 = W / 8, W2 = W / 4;
+    static constexpr int H3 = H / 8, W3 = W / 8, W2 = W / 4, W1 = W / 2;
     static constexpr int RH3 = 0;
-    static constexpr int RU3 = H3 * W3 * 256;
-    static constexpr int RH2 = RU3 + 8 * W2 * 128;
+    static constexpr int RX = H3 * W3 * 256;
+    static constexpr int RX_BYTES = 9 * W1 * 64 > 8 * W2 * 128 ? 9 * W1 * 64 : 8 * W2 * 128;
+    static constexpr int RH2 = RX + RX_BYTES;
     static constexpr int ZO = RH2 + 5 * W2 * 128;
     static constexpr int BYTES = ZO + kZeroBytes;
 };
@@ -954,54 +1012,57 @@ template <int H, int W>
 __global__ __launch_bounds__(FT) void cae_fused_tail_kernel(const TailArgs a) {
     __shared__ __align__(16) char smem[TailLds<H, W>::BYTES];
     typedef TailLds<H, W> L;
-    constexpr int H3 = H / 8, W3 = W / 8, H2 = H / 4, W2 = W / 4;
-    constexpr int NB = H3 / 2;  // bands of two h3 rows = four h2 rows
-    constexpr long S2 = (long)H2 * W2 * 64, SU = (long)(H / 2) * (W / 2) * 32;
+    constexpr int H3 = H / 8, W3 = W / 8, H2 = H / 4, W2 = W / 4, H1 = H / 2, W1 = W / 2;
+    constexpr int NB = H3 / 2;  // bands of two h3 rows = four h2 rows = eight h1 rows
+    constexpr long S1 = (long)H1 * W1 * 32, S2 = (long)H2 * W2 * 64, SU = (long)(H / 2) * (W / 2) * 32;
     static_assert(W3 == 16 && (2 * W3) % 16 == 0 && (4 * W2) % 16 == 0, "D3 pixel blocks are h3 rows");
     if (threadIdx.x < kZeroBytes / 16) *(uint4*)(smem + L::ZO + 16 * threadIdx.x) = uint4{0u, 0u, 0u, 0u};
+    constexpr int E2PB = 4 * W2 / 16;  // output pixel blocks of an E2 band
     constexpr int E3PB = 2 * W3 / 16;  // output pixel blocks of an E3 band
     constexpr int D3PB = 2 * W3 / 16;  // pixel blocks of a D3 band
     constexpr int D2PB = 4 * W2 / 16;  // pixel blocks of a D2 band
     for (int m = blockIdx.x; m < a.nmaps; m += gridDim.x) {
+        const char* h1m = (const char*)(a.h1 + m * S1);
         const char* h2m = (const char*)(a.h2 + m * S2);
-        // E3: 8 row blocks, one per wave; D3: 4 row blocks x 2 sets, one group
-        // per wave; D2: 2 row blocks x 2 sets, two waves per group. Formed per
-        // map from the opaque thread index, so that the weight addresses are
-        // not hoisted out of the map loop (they would be kept in registers).
+        // E2: 4 row blocks, two waves each; E3: 8 row blocks, one per wave;
+        // D3: 4 row blocks x 2 sets, one group per wave; D2: 2 row blocks x 2
+        // sets, two waves per group. Formed per map from the opaque thread
+        // index, so that the weight addresses are not hoisted out of the map
+        // loop (they would be kept in registers).
         const int wave = opaque_tid() >> 6;
+        const int tr2e = (wave + blockIdx.x) % 4;
         const int tre = (wave + blockIdx.x) % 8;
         const int g3 = (wave + blockIdx.x) % 8, tr3 = g3 >> 1, set3 = g3 & 1;
         const int g2 = (wave + blockIdx.x) % 4, tr2 = g2 >> 1, set2 = g2 & 1;
-        {   // sweep 1: E3, h2 -> h3
+        {   // sweep 1: E2 (h1 -> h2, to the ring and to HBM), then E3 (h2 -> h3)
+            ConvPanel<9, 1> P2e;
+            conv_panel_load<32, 1>(P2e, a.w[0], a.b[0], tr2e);
             ConvPanel<18, 1> PE;
-            conv_panel_load<64, 1>(PE, a.w[0], a.b[0], tre);
-            copy_rows_in<64, W2, 5>(smem, L::RH2, h2m, 0, 4);
+            conv_panel_load<64, 1>(PE, a.w[1], a.b[1], tre);
+            copy_rows_in<32, W1, 9>(smem, L::RX, h1m, 0, 8);
+            const RingGlobalOut<64, W2, 5> h2out{smem, L::RH2, a.h2 + m * S2};
             const LdsOut<128, W3> h3out{smem, L::RH3};
             __syncthreads();
             for (int j = 0; j < NB; ++j) {
-                RowsPiece<64, W2, 4> hp;  // h2 rows 4j + 4 .. 4j + 7 of the next band
-                if (j + 1 < NB) hp.load(h2m, 4 * j + 4, H2);
+                RowsPiece<32, W1, 8> hp;  // h1 rows 8j + 8 .. 8j + 15 of the next band
+                if (j + 1 < NB) hp.load(h1m, 8 * j + 8, H1);
+                conv_tiles<H1, W1, 32, 1, 2, E2PB, 9>(P2e, smem, L::RX, L::ZO, tr2e, wave / 4, 2, j * E2PB * 16,
+                                                      h2out);
+                __syncthreads();
+                // E2 is done with h1 rows 8j - 1 .. 8j + 6: their slots take the next band's rows
+                if (j + 1 < NB) hp.template store<9>(smem, L::RX, 8 * j + 8, H1);
                 conv_tiles<H2, W2, 64, 1, 2, E3PB, 5>(PE, smem, L::RH2, L::ZO, tre, 0, 1, j * E3PB * 16, h3out);
                 __syncthreads();
-                if (j + 1 < NB) {
-                    hp.template store<5>(smem, L::RH2, 4 * j + 4, H2);
-                    __syncthreads();
-                }
             }
         }
         PairsPanel<4, 1> P3, P2;
-        pairs_panel_load<64, 128, 1>(P3, a.w[1], a.b[1], tr3, set3);
-        pairs_panel_load<32, 128, 1>(P2, a.w[2], a.b[2], tr2, set2);
+        pairs_panel_load<64, 128, 1>(P3, a.w[2], a.b[2], tr3, set3);
+        pairs_panel_load<32, 128, 1>(P2, a.w[3], a.b[3], tr2, set2);
         copy_rows_in<64, W2, 5>(smem, L::RH2, h2m, 0, 5);
-        const LdsOut<64, W2> u3ring{smem, L::RU3};
+        const LdsOut<64, W2> u3ring{smem, L::RX};
         const GlobalOut<32, W / 2> u2out{a.u2 + m * SU};
         __syncthreads();
         for (int j = 0; j <= NB; ++j) {
-            // h2 rows 4j + 1 .. 4j + 4 of D2 band j (row 4j is already in the
-            // ring): loaded now, stored once D2 band j - 1 is done with their slots
-            RowsPiece<64, W2, 4> hp;
-            const bool stage = j >= 1 && j < NB;
-            if (stage) hp.load(h2m, 4 * j + 1, H2);
             // D3 band j: h3 rows [2j, 2j + 2) -> u3 rows [4j, 4j + 4)
             if (j < NB) {
                 if (set3 == 0)
@@ -1017,12 +1078,13 @@ __global__ __launch_bounds__(FT) void cae_fused_tail_kernel(const TailArgs a) {
             const int jb = j - 1;
             if (set2 == 0)
                 pairs_tiles<H2, W2, 64, 64, 32, 1, 1, 0, D2PB, 0, GlobalOut<32, W / 2>, 8, 5>(
-                    P2, smem, L::RU3, L::RH2, L::ZO, tr2, wave / 4, 2, jb * D2PB * 16, u2out);
+                    P2, smem, L::RX, L::RH2, L::ZO, tr2, wave / 4, 2, jb * D2PB * 16, u2out);
             else
                 pairs_tiles<H2, W2, 64, 64, 32, 1, 1, 1, D2PB, 0, GlobalOut<32, W / 2>, 8, 5>(
-                    P2, smem, L::RU3, L::RH2, L::ZO, tr2, wave / 4, 2, jb * D2PB * 16, u2out);
+                    P2, smem, L::RX, L::RH2, L::ZO, tr2, wave / 4, 2, jb * D2PB * 16, u2out);
             __syncthreads();
-            if (stage) hp.template store<5>(smem, L::RH2, 4 * j + 1, H2);
+            // h2 rows 4j + 1 .. 4j + 4 of D2 band j (row 4j is already in the ring)
+            if (j < NB) copy_rows_in<64, W2, 5>(smem, L::RH2, h2m, 4 * j + 1, 4 * j + 5 < H2 ? 4 * j + 5 : H2);
         }
     }
 }
@@ -1331,21 +1393,22 @@ bool fused_forward_size(int H, int W) { return (H == 64 && W == 64) || (H == 32 
 // Map sizes whose D3 and D2 run fused (fused_tail).
 bool fused_tail_size(int H, int W) { return H == 128 && W == 128; }
 
-drc_status fused_tail(drc_cae* h, int n, int H, int W, const void* h2, void* u2, hipStream_t s) {
+drc_status fused_tail(drc_cae* h, int n, int H, int W, const void* h1, void* h2, void* u2, hipStream_t s) {
     if (h->prec != P_BF16 || !fused_tail_size(H, W) || h->desc.pad_w != DRC_PAD_ZERO)
         return drc_fail(DRC_ERR_UNSUPPORTED, "fused tail: BF16 maps of 128x128 with zero padding only");
     if (n < 1) return DRC_OK;
     TailArgs a;
     memset(&a, 0, sizeof a);
-    a.h2 = (const uint16_t*)h2;
+    a.h1 = (const uint16_t*)h1;
+    a.h2 = (uint16_t*)h2;
     a.u2 = (uint16_t*)u2;
     a.nmaps = n;
-    for (int l = 2; l < 5; ++l) {
-        a.w[l - 2] = (const uint16_t*)h->wfrag[l];
-        a.b[l - 2] = h->bias + bias_slot(l);
+    for (int l = 1; l < 5; ++l) {
+        a.w[l - 1] = (const uint16_t*)h->wfrag[l];
+        a.b[l - 1] = h->bias + bias_slot(l);
     }
     const int grid = std::max(1, std::min(n, h->num_cu));
-    const long tok = prof_begin(h, PROF_FWD + 3, s);
+    const long tok = prof_begin(h, PROF_FWD + 1, s);
     const drc_status st = launch_tail<128, 128>(a, grid, s);
     prof_end(h, tok, s);
     return st;
