@@ -769,22 +769,23 @@ __global__ __launch_bounds__(FT) void cae_fused_forward_kernel(const FusedArgs a
 }
 
 // ======================================================================
-// E2, E3, D3 and D2 of large maps (128 x 128) in one kernel, by bands of
-// rows: the layer path's h1 (plain NHWC BF16 in HBM) in, h2 (for D2) and u2
-// out; h3 and u3 never leave LDS. One map per workgroup pass, in two sweeps
-// over bands of two h3 rows (four h2 rows, eight h1 rows). Sweep 1: E2 turns
-// h1 rows 8j - 1 .. 8j + 7 (a ring of 9 rows, the next band's rows loaded
-// during the MFMAs) into h2 rows 4j .. 4j + 3, written to HBM and to a ring
-// of 5 h2 rows, from which E3 forms h3 rows 2j, 2j + 1 (h3 is kept whole,
-// 64 KB). Sweep 2: D3 writes the four u3 rows of band j into a ring of 8
+// E1, E2, E3, D3 and D2 of large maps (128 x 128) in one kernel, by bands
+// of rows: x (float32) in; h1 (for D1), h2 (for D2) and u2 out; h3 and u3
+// never leave LDS. One map per workgroup pass, in two sweeps over bands of
+// two h3 rows (four h2 rows, eight h1 rows, sixteen x rows). Sweep 1: E1
+// turns x rows 16j - 1 .. 16j + 15 (a ring of 17 rows as BF16, the next
+// band's rows loaded during the MFMAs) into h1 rows 8j .. 8j + 7, written to
+// HBM and to a ring of 9 rows; E2 turns h1 rows 8j - 1 .. 8j + 7 into h2
+// rows 4j .. 4j + 3, written to HBM and to a ring of 5 h2 rows, from which
+// E3 forms h3 rows 2j, 2j + 1 (h3 is kept whole, 64 KB). Sweep 2: D3 writes the four u3 rows of band j into a ring of 8
 // rows (over the h1 ring), and D2 then turns the four u3 rows of band j - 1
 // (with the next row, written by band j's D3, as their lower neighbours)
 // and the same h2 rows (the ring, staged again from HBM) into eight u2
 // rows, stored straight from the MFMA results. GEMMs and epilogues are the
-// layer kernels', so h2 and u2 are bitwise the layer path's.
-//   RH3 [0, 256 H3 W3)  h3;  RX h1 ring (9 rows of W1 x 32 ch), then u3 ring
-//   (8 rows of W2 x 64 ch);  RH2 h2 ring (5 rows of W2 x 64 ch);  zeros.
-//   120 KB at 128 x 128.
+// layer kernels', so h1, h2 and u2 are bitwise the layer path's.
+//   RH3 [0, 256 H3 W3)  h3;  RXR x ring (17 rows of W x 8 ch);  RX h1 ring
+//   (9 rows of W1 x 32 ch), then u3 ring (8 rows of W2 x 64 ch);  RH2 h2
+//   ring (5 rows of W2 x 64 ch);  zeros.  154 KB at 128 x 128.
 
 // Stride-2 3x3 convolution over a band of output pixel blocks (CIN >= 32),
 // LDS -> epilogue, with the weights (MT row blocks of group tr, every K step)
@@ -812,6 +813,63 @@ __device__ __forceinline__ void conv_panel_load(ConvPanel<(9 * CIN + 31) / 32, M
 #pragma unroll
         for (int e = 0; e < 4; ++e) P.bias[m][e] = bg[(tr * MT + m) * 16 + g * 4 + e];
 }
+// E1 over a band of output blocks (CIN = 8: x staged as BF16, 16 bytes per
+// pixel, no swizzle) from a ring of IR input rows, the weights already in
+// registers: the lane group g takes tap 4 ks + g of K step ks, exactly as
+// conv_phase does for CIN = 8.
+template <int HI, int WI, int MT, int NPW, int NPB, int IR, class Epi>
+__device__ __forceinline__ void conv8_tiles(const ConvPanel<3, MT>& P, char* smem, int in, int zoff, int tr, int tp0,
+                                            int tp_step, int pix0, const Epi& epi) {
+    constexpr int WO = WI / 2, KSTEPS = 3, ROW = WI * 16;
+    constexpr int TP = NPB / NPW;
+    static_assert(NPB % NPW == 0 && IR > 0, "band of whole tiles from a ring");
+    const int lane = opaque_tid() & 63;
+    const int g = lane >> 4, r16 = lane & 15;
+    for (int tp = tp0; tp < TP; tp += tp_step) {
+        int oy[NPW], ox[NPW], off[NPW][KSTEPS];
+#pragma unroll
+        for (int p = 0; p < NPW; ++p) {
+            const int pix = pix0 + (tp * NPW + p) * 16 + r16;
+            oy[p] = (int)((unsigned)pix / WO);
+            ox[p] = (int)((unsigned)pix % WO);
+            const bool top = oy[p] > 0, left = ox[p] > 0;
+#pragma unroll
+            for (int ks = 0; ks < KSTEPS; ++ks) {
+                const int t = ks * 4 + g, kh = t / 3, kw = t - (t / 3) * 3;
+                const bool ok = t < 9 && (top || kh != 0) && (left || kw != 0);
+                const int r = 2 * oy[p] - 1 + kh, c = 2 * ox[p] - 1 + kw;
+                off[p][ks] = ok ? in + (int)((unsigned)r % (unsigned)IR) * ROW + c * 16 : zoff;
+            }
+        }
+        typename Epi::Pre pre[MT][NPW];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) epi.prefetch(pre[m][p], m, (tr * MT + m) * 16 + g * 4, oy[p], ox[p]);
+        f4 acc[MT][NPW];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) acc[m][p] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            uint4 b[NPW];
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) b[p] = lds16(smem, off[p][ks]);
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int p = 0; p < NPW; ++p) mma(acc[m][p], P.A[ks][m], b[p]);
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int ch = (tr * MT + m) * 16 + g * 4;
+#pragma unroll
+            for (int p = 0; p < NPW; ++p) epi(pre[m][p], m, ch, oy[p], ox[p], acc[m][p], P.bias[m]);
+        }
+    }
+}
+
 template <int HI, int WI, int CIN, int MT, int NPW, int NPB, int IR, class Epi>
 __device__ __forceinline__ void conv_tiles(const ConvPanel<(9 * CIN + 31) / 32, MT>& P, char* smem, int in,
                                            int zoff, int tr, int tp0, int tp_step, int pix0, const Epi& epi) {
@@ -988,20 +1046,56 @@ struct RowsPiece {
     }
 };
 
+// NR rows of x (float32, 7 channels, WI wide) for the E1 ring: each thread
+// carries 4 consecutive pixels (7 float4 = 28 floats) from their global
+// loads, issued before the MFMAs of a band, to their LDS stores as BF16 with
+// 8 channels (channel 7 = 0, 16 bytes per pixel) after it. Native vector
+// members keep the piece in registers.
+template <int WI, int NR>
+struct XRowsPiece {
+    typedef float F4 __attribute__((ext_vector_type(4)));
+    static constexpr int Q = NR * WI / 4;  // pixel quads
+    static_assert(Q == FT, "one quad per thread");
+    F4 v0, v1, v2, v3, v4, v5, v6;
+    __device__ __forceinline__ void load(const float* xm, int r0) {
+        const F4* src = (const F4*)(xm + (long)r0 * WI * 7) + 7 * (int)threadIdx.x;
+        v0 = src[0]; v1 = src[1]; v2 = src[2]; v3 = src[3]; v4 = src[4]; v5 = src[5]; v6 = src[6];
+    }
+    template <int RING>
+    __device__ __forceinline__ void store(char* smem, int region, int r0) const {
+        const float f[28] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x, v2.y, v2.z, v2.w, v3.x, v3.y,
+                             v3.z, v3.w, v4.x, v4.y, v4.z, v4.w, v5.x, v5.y, v5.z, v5.w, v6.x, v6.y, v6.z, v6.w};
+        const int px = 4 * (int)threadIdx.x, r = r0 + px / WI, c = px % WI;
+        char* row = smem + region + (int)((unsigned)r % RING) * (WI * 16);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint4 o;
+            o.x = pack_bf16x2(f[7 * k + 0], f[7 * k + 1]);
+            o.y = pack_bf16x2(f[7 * k + 2], f[7 * k + 3]);
+            o.z = pack_bf16x2(f[7 * k + 4], f[7 * k + 5]);
+            o.w = pack_bf16x2(f[7 * k + 6], 0.0f);
+            *(uint4*)(row + (c + k) * 16) = o;
+        }
+    }
+};
+
 struct TailArgs {
-    const uint16_t* h1;  // [n][H/2][W/2][32]
+    const float* x;      // maps of H x W x 7 float32
+    const long* x_off;   // element offset of each map in x (null: packed)
+    uint16_t* h1;        // [n][H/2][W/2][32]
     uint16_t* h2;        // [n][H/4][W/4][64]
     uint16_t* u2;        // [n][H/2][W/2][32]
     int nmaps;
-    const uint16_t* w[4];  // E2, E3, D3, D2 forward packs in fragment order
-    const float* b[4];
+    const uint16_t* w[5];  // E1, E2, E3, D3, D2 forward packs in fragment order
+    const float* b[5];
 };
 
 template <int H, int W>
 struct TailLds {
     static constexpr int H3 = H / 8, W3 = W / 8, W2 = W / 4, W1 = W / 2;
     static constexpr int RH3 = 0;
-    static constexpr int RX = H3 * W3 * 256;
+    static constexpr int RXR = H3 * W3 * 256;            // x ring: 17 rows of W pixels, 16 bytes each
+    static constexpr int RX = RXR + 17 * W * 16;
     static constexpr int RX_BYTES = 9 * W1 * 64 > 8 * W2 * 128 ? 9 * W1 * 64 : 8 * W2 * 128;
     static constexpr int RH2 = RX + RX_BYTES;
     static constexpr int ZO = RH2 + 5 * W2 * 128;
@@ -1015,6 +1109,7 @@ __global__ __launch_bounds__(FT) void cae_fused_tail_kernel(const TailArgs a) {
     constexpr int H3 = H / 8, W3 = W / 8, H2 = H / 4, W2 = W / 4, H1 = H / 2, W1 = W / 2;
     constexpr int NB = H3 / 2;  // bands of two h3 rows = four h2 rows = eight h1 rows
     constexpr long S1 = (long)H1 * W1 * 32, S2 = (long)H2 * W2 * 64, SU = (long)(H / 2) * (W / 2) * 32;
+    constexpr int E1PB = 8 * W1 / 16;  // output pixel blocks of an E1 band
     static_assert(W3 == 16 && (2 * W3) % 16 == 0 && (4 * W2) % 16 == 0, "D3 pixel blocks are h3 rows");
     if (threadIdx.x < kZeroBytes / 16) *(uint4*)(smem + L::ZO + 16 * threadIdx.x) = uint4{0u, 0u, 0u, 0u};
     constexpr int E2PB = 4 * W2 / 16;  // output pixel blocks of an E2 band
@@ -1022,7 +1117,7 @@ __global__ __launch_bounds__(FT) void cae_fused_tail_kernel(const TailArgs a) {
     constexpr int D3PB = 2 * W3 / 16;  // pixel blocks of a D3 band
     constexpr int D2PB = 4 * W2 / 16;  // pixel blocks of a D2 band
     for (int m = blockIdx.x; m < a.nmaps; m += gridDim.x) {
-        const char* h1m = (const char*)(a.h1 + m * S1);
+        const float* xm = a.x + (a.x_off ? a.x_off[m] : (long)m * H * W * 7);
         const char* h2m = (const char*)(a.h2 + m * S2);
         // E2: 4 row blocks, two waves each; E3: 8 row blocks, one per wave;
         // D3: 4 row blocks x 2 sets, one group per wave; D2: 2 row blocks x 2
@@ -1034,30 +1129,44 @@ __global__ __launch_bounds__(FT) void cae_fused_tail_kernel(const TailArgs a) {
         const int tre = (wave + blockIdx.x) % 8;
         const int g3 = (wave + blockIdx.x) % 8, tr3 = g3 >> 1, set3 = g3 & 1;
         const int g2 = (wave + blockIdx.x) % 4, tr2 = g2 >> 1, set2 = g2 & 1;
-        {   // sweep 1: E2 (h1 -> h2, to the ring and to HBM), then E3 (h2 -> h3)
+        {   // sweep 1: E1 (x -> h1, to the ring and to HBM), E2 (h1 -> h2, to
+            // the ring and to HBM), E3 (h2 -> h3). Band j: E3 of band j - 1
+            // and E1 of band j, then E2 of band j.
+            ConvPanel<3, 2> P1e;
+            conv_panel_load<8, 2>(P1e, a.w[0], a.b[0], 0);
             ConvPanel<9, 1> P2e;
-            conv_panel_load<32, 1>(P2e, a.w[0], a.b[0], tr2e);
+            conv_panel_load<32, 1>(P2e, a.w[1], a.b[1], tr2e);
             ConvPanel<18, 1> PE;
-            conv_panel_load<64, 1>(PE, a.w[1], a.b[1], tre);
-            copy_rows_in<32, W1, 9>(smem, L::RX, h1m, 0, 8);
+            conv_panel_load<64, 1>(PE, a.w[2], a.b[2], tre);
+            {
+                XRowsPiece<W, 16> xq;
+                xq.load(xm, 0);
+                xq.template store<17>(smem, L::RXR, 0);
+            }
+            const RingGlobalOut<32, W1, 9> h1out{smem, L::RX, a.h1 + m * S1};
             const RingGlobalOut<64, W2, 5> h2out{smem, L::RH2, a.h2 + m * S2};
             const LdsOut<128, W3> h3out{smem, L::RH3};
             __syncthreads();
             for (int j = 0; j < NB; ++j) {
-                RowsPiece<32, W1, 8> hp;  // h1 rows 8j + 8 .. 8j + 15 of the next band
-                if (j + 1 < NB) hp.load(h1m, 8 * j + 8, H1);
+                if (j > 0)
+                    conv_tiles<H2, W2, 64, 1, 2, E3PB, 5>(PE, smem, L::RH2, L::ZO, tre, 0, 1, (j - 1) * E3PB * 16,
+                                                          h3out);
+                XRowsPiece<W, 16> xq;  // x rows 16j + 16 .. 16j + 31 of the next band
+                if (j + 1 < NB) xq.load(xm, 16 * j + 16);
+                conv8_tiles<H, W, 2, 2, E1PB, 17>(P1e, smem, L::RXR, L::ZO, 0, wave, 8, j * E1PB * 16, h1out);
+                __syncthreads();
+                // E1 is done with x rows 16j - 1 .. 16j + 14: their slots take the next band's rows
+                if (j + 1 < NB) xq.template store<17>(smem, L::RXR, 16 * j + 16);
                 conv_tiles<H1, W1, 32, 1, 2, E2PB, 9>(P2e, smem, L::RX, L::ZO, tr2e, wave / 4, 2, j * E2PB * 16,
                                                       h2out);
                 __syncthreads();
-                // E2 is done with h1 rows 8j - 1 .. 8j + 6: their slots take the next band's rows
-                if (j + 1 < NB) hp.template store<9>(smem, L::RX, 8 * j + 8, H1);
-                conv_tiles<H2, W2, 64, 1, 2, E3PB, 5>(PE, smem, L::RH2, L::ZO, tre, 0, 1, j * E3PB * 16, h3out);
-                __syncthreads();
             }
+            conv_tiles<H2, W2, 64, 1, 2, E3PB, 5>(PE, smem, L::RH2, L::ZO, tre, 0, 1, (NB - 1) * E3PB * 16, h3out);
+            __syncthreads();
         }
         PairsPanel<4, 1> P3, P2;
-        pairs_panel_load<64, 128, 1>(P3, a.w[2], a.b[2], tr3, set3);
-        pairs_panel_load<32, 128, 1>(P2, a.w[3], a.b[3], tr2, set2);
+        pairs_panel_load<64, 128, 1>(P3, a.w[3], a.b[3], tr3, set3);
+        pairs_panel_load<32, 128, 1>(P2, a.w[4], a.b[4], tr2, set2);
         copy_rows_in<64, W2, 5>(smem, L::RH2, h2m, 0, 5);
         const LdsOut<64, W2> u3ring{smem, L::RX};
         const GlobalOut<32, W / 2> u2out{a.u2 + m * SU};
@@ -1393,22 +1502,26 @@ bool fused_forward_size(int H, int W) { return (H == 64 && W == 64) || (H == 32 
 // Map sizes whose D3 and D2 run fused (fused_tail).
 bool fused_tail_size(int H, int W) { return H == 128 && W == 128; }
 
-drc_status fused_tail(drc_cae* h, int n, int H, int W, const void* h1, void* h2, void* u2, hipStream_t s) {
+drc_status fused_tail(drc_cae* h, int n, int H, int W, const float* x, const long* x_off, void* h1, void* h2,
+                      void* u2, hipStream_t s) {
     if (h->prec != P_BF16 || !fused_tail_size(H, W) || h->desc.pad_w != DRC_PAD_ZERO)
         return drc_fail(DRC_ERR_UNSUPPORTED, "fused tail: BF16 maps of 128x128 with zero padding only");
+    if ((uintptr_t)x % 16 != 0) return drc_fail(DRC_ERR_INVALID_ARG, "fused tail: x is not 16-byte aligned");
     if (n < 1) return DRC_OK;
     TailArgs a;
     memset(&a, 0, sizeof a);
-    a.h1 = (const uint16_t*)h1;
+    a.x = x;
+    a.x_off = x_off;
+    a.h1 = (uint16_t*)h1;
     a.h2 = (uint16_t*)h2;
     a.u2 = (uint16_t*)u2;
     a.nmaps = n;
-    for (int l = 1; l < 5; ++l) {
-        a.w[l - 1] = (const uint16_t*)h->wfrag[l];
-        a.b[l - 1] = h->bias + bias_slot(l);
+    for (int l = 0; l < 5; ++l) {
+        a.w[l] = (const uint16_t*)h->wfrag[l];
+        a.b[l] = h->bias + bias_slot(l);
     }
     const int grid = std::max(1, std::min(n, h->num_cu));
-    const long tok = prof_begin(h, PROF_FWD + 1, s);
+    const long tok = prof_begin(h, PROF_FWD + 0, s);
     const drc_status st = launch_tail<128, 128>(a, grid, s);
     prof_end(h, tok, s);
     return st;

@@ -179,11 +179,13 @@ drc_status fused_forward(drc_cae* h, const float* x, float* y, int n, int H, int
                          const long* y_off, void* scratch, size_t scratch_bytes, hipStream_t s,
                          char* const* save = nullptr, const int32_t* roll = nullptr,
                          const int32_t* flip = nullptr);
-// BF16 128x128 maps (zero padding): E2, E3, D3 and D2 in one kernel, h1 in
-// (plain NHWC, as the layer path writes it), h2 and u2 out; h3 and u3 stay
-// on chip.
+// BF16 128x128 maps (zero padding): E1, E2, E3, D3 and D2 in one kernel, x
+// in (16-byte aligned maps, x_off as in LayerArgs or null for packed maps),
+// h1, h2 and u2 out (plain NHWC, as the layer path writes them, for D1);
+// h3 and u3 stay on chip.
 bool fused_tail_size(int H, int W);
-drc_status fused_tail(drc_cae* h, int n, int H, int W, const void* h1, void* h2, void* u2, hipStream_t s);
+drc_status fused_tail(drc_cae* h, int n, int H, int W, const float* x, const long* x_off, void* h1, void* h2,
+                      void* u2, hipStream_t s);
 // h2 -> h3, u3, u2 (the layers a recomputing backward rebuilds), all plain NHWC.
 drc_status fused_recompute(drc_cae* h, int n, int H, int W, const void* h2, void* h3, void* u3, void* u2,
                            hipStream_t s);

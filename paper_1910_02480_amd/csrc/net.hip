@@ -316,9 +316,8 @@ extern "C" drc_status drc_cae_forward(drc_cae* h, const float* d_x, float* d_y, 
     }
     FwdBufs b{d_x, d_y, act[0], act[1], act[2], act[3], act[4], nullptr, nullptr};
     if (h->fused && h->prec == P_BF16 && !d_saved && fused_tail_size(H, W) && h->desc.pad_w == DRC_PAD_ZERO) {
-        // E1 and D1 through the layer kernels, E2, E3, D3 and D2 fused (h3 and u3 stay on chip)
-        TRY(forward_dispatch(h, b, n, H, W, 0, 0, (hipStream_t)stream));
-        TRY(fused_tail(h, n, H, W, b.h1, b.h2, b.u2, (hipStream_t)stream));
+        // E1-D2 in the banded kernel (h3 and u3 stay on chip), D1 through its layer kernel
+        TRY(fused_tail(h, n, H, W, d_x, nullptr, b.h1, b.h2, b.u2, (hipStream_t)stream));
         return forward_dispatch(h, b, n, H, W, 5, 5, (hipStream_t)stream);
     }
     return forward_dispatch(h, b, n, H, W, 0, 5, (hipStream_t)stream);

@@ -272,13 +272,14 @@ static drc_status plan_enqueue(drc_plan* p, const float* x, float* y, char* ws, 
             }
         for (int l = 0; l < 6; ++l) fc[0].npw[l] = p->cls[big].npw[l];
         const int nc = (int)fc.size();
-        // BF16 128x128 classes: E2, E3, D3 and D2 in the fused tail kernel
-        // (one launch per class), the other classes' through the layer kernels
+        // BF16 128x128 classes with 16-byte aligned maps: E1-D2 in the banded
+        // kernel (one launch per class), the other classes' through the
+        // layer kernels
         std::vector<FwdClass> rest;
         std::vector<int> tail;
         for (int k = 0; k < nc; ++k) {
             if (h->fused && h->prec == P_BF16 && fused_tail_size(fc[k].H, fc[k].W) &&
-                h->desc.pad_w == DRC_PAD_ZERO)
+                h->desc.pad_w == DRC_PAD_ZERO && fc[k].x_al16)
                 tail.push_back(k);
             else
                 rest.push_back(fc[k]);
@@ -288,14 +289,13 @@ static drc_status plan_enqueue(drc_plan* p, const float* x, float* y, char* ws, 
             if (h->prec == P_BF16) st = forward_classes<P_BF16>(h, h->wf, fc.data(), nc, 0, 5, s);
             if (h->prec == P_FP8) st = forward_classes<P_FP8>(h, h->wf, fc.data(), nc, 0, 5, s);
         } else {
-            st = forward_classes<P_BF16>(h, h->wf, fc.data(), nc, 0, 0, s);
-            if (st == DRC_OK && !rest.empty()) {
+            if (!rest.empty()) {
                 for (int l = 0; l < 6; ++l) rest[0].npw[l] = fc[0].npw[l];
-                st = forward_classes<P_BF16>(h, h->wf, rest.data(), (int)rest.size(), 1, 4, s);
+                st = forward_classes<P_BF16>(h, h->wf, rest.data(), (int)rest.size(), 0, 4, s);
             }
             for (size_t k = 0; k < tail.size() && st == DRC_OK; ++k) {
                 const FwdClass& f = fc[tail[k]];
-                st = fused_tail(h, f.n, f.H, f.W, f.b.h1, f.b.h2, f.b.u2, s);
+                st = fused_tail(h, f.n, f.H, f.W, f.b.x, f.b.x_off, f.b.h1, f.b.h2, f.b.u2, s);
             }
             if (st == DRC_OK) st = forward_classes<P_BF16>(h, h->wf, fc.data(), nc, 5, 5, s);
         }
