@@ -67,7 +67,7 @@ _LABELS = (
     (r"ut_upcat", "U-Net training upsample + concat"),
     (r"ut_out", "U-Net training output layer"),
     (r"ut_flip_kernel|ut_pad_|ut_fill_kernel", "U-Net training copies"),
-    (r"cae_fused_tail_kernel", "128x128 E2-D2 fused (banded)"),
+    (r"cae_fused_tail_kernel", "128x128 E1-D2 fused (banded)"),
     (r"(?<!w)grad_final_kernel", "gradient sums (weights, biases, loss)"),
     (r"cae_fused_dgrad_kernel", "fused data gradients"),
     (r"wgrad_tr_kernel", "weight gradient (BF16, transpose reads)"),
