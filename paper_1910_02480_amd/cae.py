@@ -38,8 +38,9 @@ class CAE:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
-            B.drc_cae_destroy(h)
+        destroy = getattr(B, "drc_cae_destroy", None)
+        if h and callable(destroy):  # the binding may be torn down first at interpreter exit
+            destroy(h)
             self.h = None
 
     def set_params(self, params: torch.Tensor):

@@ -1131,13 +1131,11 @@ __global__ __launch_bounds__(FT) void cae_fused_tail_kernel(const TailArgs a) {
         const int g2 = (wave + blockIdx.x) % 4, tr2 = g2 >> 1, set2 = g2 & 1;
         {   // sweep 1: E1 (x -> h1, to the ring and to HBM), E2 (h1 -> h2, to
             // the ring and to HBM), E3 (h2 -> h3). Band j: E3 of band j - 1
-            // and E1 of band j, then E2 of band j.
-            ConvPanel<3, 2> P1e;
-            conv_panel_load<8, 2>(P1e, a.w[0], a.b[0], 0);
-            ConvPanel<9, 1> P2e;
-            conv_panel_load<32, 1>(P2e, a.w[1], a.b[1], tr2e);
-            ConvPanel<18, 1> PE;
-            conv_panel_load<64, 1>(PE, a.w[2], a.b[2], tre);
+            // and E1 of band j, then E2 of band j. Each layer's weight panel
+            // is loaded from L2 where the layer runs, band after band: kept in
+            // registers across the whole sweep, the three panels (132 VGPRs)
+            // pushed the band loop into scratch spills, and each spill reload
+            // waited for every HBM store still in flight.
             {
                 XRowsPiece<W, 16> xq;
                 xq.load(xm, 0);
@@ -1148,12 +1146,19 @@ __global__ __launch_bounds__(FT) void cae_fused_tail_kernel(const TailArgs a) {
             const LdsOut<128, W3> h3out{smem, L::RH3};
             __syncthreads();
             for (int j = 0; j < NB; ++j) {
-                if (j > 0)
+                ConvPanel<3, 2> P1e;
+                conv_panel_load<8, 2>(P1e, a.w[0], a.b[0], 0);
+                if (j > 0) {
+                    ConvPanel<18, 1> PE;
+                    conv_panel_load<64, 1>(PE, a.w[2], a.b[2], tre);
                     conv_tiles<H2, W2, 64, 1, 2, E3PB, 5>(PE, smem, L::RH2, L::ZO, tre, 0, 1, (j - 1) * E3PB * 16,
                                                           h3out);
+                }
                 XRowsPiece<W, 16> xq;  // x rows 16j + 16 .. 16j + 31 of the next band
                 if (j + 1 < NB) xq.load(xm, 16 * j + 16);
                 conv8_tiles<H, W, 2, 2, E1PB, 17>(P1e, smem, L::RXR, L::ZO, 0, wave, 8, j * E1PB * 16, h1out);
+                ConvPanel<9, 1> P2e;
+                conv_panel_load<32, 1>(P2e, a.w[1], a.b[1], tr2e);
                 __syncthreads();
                 // E1 is done with x rows 16j - 1 .. 16j + 14: their slots take the next band's rows
                 if (j + 1 < NB) xq.template store<17>(smem, L::RXR, 16 * j + 16);
@@ -1161,7 +1166,12 @@ __global__ __launch_bounds__(FT) void cae_fused_tail_kernel(const TailArgs a) {
                                                       h2out);
                 __syncthreads();
             }
-            conv_tiles<H2, W2, 64, 1, 2, E3PB, 5>(PE, smem, L::RH2, L::ZO, tre, 0, 1, (NB - 1) * E3PB * 16, h3out);
+            {
+                ConvPanel<18, 1> PE;
+                conv_panel_load<64, 1>(PE, a.w[2], a.b[2], tre);
+                conv_tiles<H2, W2, 64, 1, 2, E3PB, 5>(PE, smem, L::RH2, L::ZO, tre, 0, 1, (NB - 1) * E3PB * 16,
+                                                      h3out);
+            }
             __syncthreads();
         }
         PairsPanel<4, 1> P3, P2;
