@@ -240,8 +240,8 @@ __global__ __launch_bounds__(kThreads) void d1_band_kernel(const E1Args e) {
     // chunks of band `item`: input rows a0 .. a0 + BR (the last one only when
     // inside the map), pixel by pixel 4 chunks of u2 then 4 of h1; every lane
     // loads (rows below the map read the map's first chunk and are zeroed)
-    uint4 vq[kD1Chunks];
-    auto load_band = [&](long item) {
+    typedef uint4 Piece[kD1Chunks];
+    auto load_band = [&](long item, Piece& vq) {
         const int c = class_of(item);
         const ClassGeom& G = a.cls[c];
         const long b = item - e.bg[c].band0;
@@ -261,8 +261,13 @@ __global__ __launch_bounds__(kThreads) void d1_band_kernel(const E1Args e) {
         }
     };
 
-    if (blockIdx.x < e.total) load_band(blockIdx.x);
-    for (long item = blockIdx.x; item < e.total; item += gridDim.x) {
+    // BF16: two bands in flight per workgroup, band item + 2 G (G =
+    // gridDim.x) loaded while band item is computed and stored and band
+    // item + G waiting in the other set of registers; FP8 (whose registers
+    // would then drop it to one workgroup per CU): one band ahead
+    constexpr bool kTwo = P != P_FP8;
+    const long step = (kTwo ? 2L : 1L) * gridDim.x;
+    auto run_band = [&](long item, Piece& vq) {
         const int c = class_of(item);
         const ClassGeom& G = a.cls[c];
         const int br = e.bg[c].br;
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(kThreads) void d1_band_kernel(const E1Args e) {
             if (i < nch) *(uint4*)(smem + (i / CPP) * PIXB + (i % CPP) * 16) = vq[k];
         }
         __syncthreads();
-        if (item + gridDim.x < e.total) load_band(item + gridDim.x);
+        if (item + step < e.total) load_band(item + step, vq);
 
         f4 acc[4];
         int al[4], bj[4];
@@ -328,6 +333,13 @@ __global__ __launch_bounds__(kThreads) void d1_band_kernel(const E1Args e) {
         } else {
             for (int i = tid; i < nf; i += kThreads) yd[i] = ys[i];
         }
+    };
+    Piece va, vb;
+    if (blockIdx.x < e.total) load_band(blockIdx.x, va);
+    if (kTwo && blockIdx.x + (long)gridDim.x < e.total) load_band(blockIdx.x + (long)gridDim.x, vb);
+    for (long item = blockIdx.x; item < e.total; item += step) {
+        run_band(item, va);
+        if (kTwo && item + gridDim.x < e.total) run_band(item + gridDim.x, vb);
     }
 }
 
