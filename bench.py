@@ -449,10 +449,36 @@ def main():
     torch.cuda.synchronize()
     B.drc_cae_profile(cae.h, 1)
     read_profile(B, cae.h)
-    log(f"timing bf16 forward: {args.steps} steps")
-    t = timed(fwd, args.steps, 0, do_settle=False)
-    ms_l, calls_l = read_profile(B, cae.h)
-    B.drc_cae_profile(cae.h, 0)
+    if fused_headline:
+        # one launch per forward: one profiled call shows that it is the
+        # whole-network kernel alone; the timed steps then run without
+        # per-launch events (they cost ~1.7 % of a 0.43 ms step), and two
+        # HIP events on the launch stream around the timed region give the
+        # kernel's average duration (gaps between launches included)
+        fwd()
+        ms_1, calls_1 = read_profile(B, cae.h)
+        B.drc_cae_profile(cae.h, 0)
+        if calls_1[FUSED_SLOT] != 1 or sum(calls_1) != 1:
+            raise RuntimeError(f"bf16 forward of {n}x{H}x{H}: expected one whole-network launch, got {calls_1}")
+        log(f"timing bf16 forward: {args.steps} steps")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(args.steps):
+            fwd()
+        e1.record()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        ms_l = [0.0] * len(ms_1)
+        calls_l = [0] * len(calls_1)
+        ms_l[FUSED_SLOT] = e0.elapsed_time(e1)
+        calls_l[FUSED_SLOT] = args.steps
+    else:
+        log(f"timing bf16 forward: {args.steps} steps")
+        t = timed(fwd, args.steps, 0, do_settle=False)
+        ms_l, calls_l = read_profile(B, cae.h)
+        B.drc_cae_profile(cae.h, 0)
     ACC_MAPS = min(512, n)  # maps checked against the oracle
     y_bf16 = y[:ACC_MAPS].cpu().numpy()
     value = n / t
