@@ -1530,7 +1530,9 @@ drc_status fused_tail(drc_cae* h, int n, int H, int W, const float* x, const lon
         a.w[l] = (const uint16_t*)h->wfrag[l];
         a.b[l] = h->bias + bias_slot(l);
     }
-    const int grid = std::max(1, std::min(n, h->num_cu));
+    // one workgroup per map: the dispatcher hands maps to CUs as they free
+    // up, also to CUs that another stream's launch leaves idle
+    const int grid = std::max(1, n);
     const long tok = prof_begin(h, PROF_FWD + 0, s);
     const drc_status st = launch_tail<128, 128>(a, grid, s);
     prof_end(h, tok, s);

@@ -214,33 +214,26 @@ extern "C" void drc_cae_plan_destroy(drc_plan* p) {
     delete p;
 }
 
-// Enqueue the six persistent layer launches of a frame.
+// Enqueue a frame. BF16 and FP8 classes the whole-network kernel is built
+// for run through it, one launch per class; BF16 128x128 classes (zero
+// padding, 16-byte aligned maps) run E1-D2 in the banded kernel; the rest
+// share one persistent launch per layer, and D1 of every class that is not
+// whole-network is one launch.
 static drc_status plan_enqueue(drc_plan* p, const float* x, float* y, char* ws, hipStream_t s) {
     drc_cae* h = p->h;
     const bool prof = h->prof;
     h->prof = false;
-    // BF16 classes the whole-network kernel is built for run through it, one
-    // launch per class; the rest share one persistent launch per layer.
+    const bool x16 = (uintptr_t)x % 16 == 0;
+    // (its input staging reads 16-byte vectors: every map must start on a 16-byte boundary)
+    auto whole_network = [&](const PlanClass& pc) {
+        return h->fused && (h->prec == P_FP8 || h->prec == P_BF16) && fused_forward_size(pc.H, pc.W) &&
+               pc.x_al16 && x16;
+    };
     std::vector<FwdClass> fc;
     std::vector<int> from;
-    drc_status st = DRC_OK;
-    for (size_t c = 0; c < p->cls.size() && st == DRC_OK; ++c) {
+    for (size_t c = 0; c < p->cls.size(); ++c) {
         const PlanClass& pc = p->cls[c];
-        const long* xo = (const long*)(p->d_tables + pc.dev_xoff);
-        const long* yo = (const long*)(p->d_tables + pc.dev_yoff);
-        // (its input staging reads 16-byte vectors: every map must start on a 16-byte boundary)
-        if (h->fused && h->prec == P_FP8 && fused_forward_size(pc.H, pc.W) && pc.x_al16 &&
-            (uintptr_t)x % 16 == 0) {
-            st = fused_fp8_forward(h, x, y, pc.n, pc.H, pc.W, xo, yo, s);
-            continue;
-        }
-        if (h->fused && h->prec == P_BF16 && fused_forward_size(pc.H, pc.W) && pc.x_al16 &&
-            (uintptr_t)x % 16 == 0) {
-            // the class's h1 region (n maps) holds the per-workgroup slots
-            st = fused_forward(h, x, y, pc.n, pc.H, pc.W, xo, yo, ws + pc.act[0],
-                               (size_t)pc.n * 16 * pc.H * pc.W, s);
-            continue;
-        }
+        if (whole_network(pc)) continue;
         FwdClass f;
         memset(&f, 0, sizeof f);
         f.b.x = x;
@@ -250,17 +243,18 @@ static drc_status plan_enqueue(drc_plan* p, const float* x, float* y, char* ws, 
         f.b.h3 = ws + pc.act[2];
         f.b.u3 = ws + pc.act[3];
         f.b.u2 = ws + pc.act[4];
-        f.b.x_off = xo;
-        f.b.y_off = yo;
+        f.b.x_off = (const long*)(p->d_tables + pc.dev_xoff);
+        f.b.y_off = (const long*)(p->d_tables + pc.dev_yoff);
         f.n = pc.n;
         f.H = pc.H;
         f.W = pc.W;
-        f.x_al16 = pc.x_al16 && (uintptr_t)x % 16 == 0;
+        f.x_al16 = pc.x_al16 && x16;
         for (int l = 0; l < 6; ++l) f.tile_px[l] = pc.tile_px[l];
         fc.push_back(f);
         from.push_back((int)c);
     }
-    if (st == DRC_OK && !fc.empty()) {
+    const int nc = (int)fc.size();
+    if (nc) {
         // The GEMM tile (NPW) is shared by the classes of a launch: take the
         // tuned choice of the class with the most work.
         long best = -1;
@@ -271,35 +265,65 @@ static drc_status plan_enqueue(drc_plan* p, const float* x, float* y, char* ws, 
                 big = from[k];
             }
         for (int l = 0; l < 6; ++l) fc[0].npw[l] = p->cls[big].npw[l];
-        const int nc = (int)fc.size();
-        // BF16 128x128 classes with 16-byte aligned maps: E1-D2 in the banded
-        // kernel (one launch per class), the other classes' through the
-        // layer kernels
-        std::vector<FwdClass> rest;
-        std::vector<int> tail;
-        for (int k = 0; k < nc; ++k) {
-            if (h->fused && h->prec == P_BF16 && fused_tail_size(fc[k].H, fc[k].W) &&
-                h->desc.pad_w == DRC_PAD_ZERO && fc[k].x_al16)
-                tail.push_back(k);
-            else
-                rest.push_back(fc[k]);
+    }
+    std::vector<FwdClass> rest;
+    std::vector<int> tail;
+    for (int k = 0; k < nc; ++k) {
+        if (h->fused && h->prec == P_BF16 && fused_tail_size(fc[k].H, fc[k].W) && h->desc.pad_w == DRC_PAD_ZERO &&
+            fc[k].x_al16)
+            tail.push_back(k);
+        else
+            rest.push_back(fc[k]);
+    }
+    if (!rest.empty() && !tail.empty())
+        for (int l = 0; l < 6; ++l) rest[0].npw[l] = fc[0].npw[l];
+    // When every class outside the banded kernel is whole-network, the
+    // banded chain (one workgroup per map, so freed CUs take its maps as they
+    // come) runs on a side stream, enqueued first, next to the whole-network
+    // launches: each launch's last, partly filled wave of workgroups then
+    // overlaps the other stream's work instead of leaving CUs idle.
+    const bool fork = !tail.empty() && rest.empty();
+    hipStream_t sb = fork ? h->side[0] : s;
+    drc_status st = DRC_OK;
+    if (fork) {
+        if (hipEventRecord(h->ev_fork[0], s) != hipSuccess || hipStreamWaitEvent(sb, h->ev_fork[0], 0) != hipSuccess) {
+            h->prof = prof;
+            return drc_fail(DRC_ERR_HIP, "plan: side stream fork failed");
         }
+    }
+    auto banded_chain = [&]() -> drc_status {
+        for (size_t k = 0; k < tail.size(); ++k) {
+            const FwdClass& f = fc[tail[k]];
+            TRY(fused_tail(h, f.n, f.H, f.W, f.b.x, f.b.x_off, f.b.h1, f.b.h2, f.b.u2, sb));
+        }
+        return forward_classes<P_BF16>(h, h->wf, fc.data(), nc, 5, 5, sb);
+    };
+    if (fork) st = banded_chain();
+    for (size_t c = 0; c < p->cls.size() && st == DRC_OK; ++c) {
+        const PlanClass& pc = p->cls[c];
+        if (!whole_network(pc)) continue;
+        const long* xo = (const long*)(p->d_tables + pc.dev_xoff);
+        const long* yo = (const long*)(p->d_tables + pc.dev_yoff);
+        if (h->prec == P_FP8)
+            st = fused_fp8_forward(h, x, y, pc.n, pc.H, pc.W, xo, yo, s);
+        else  // the class's h1 region (n maps) holds the per-workgroup slots
+            st = fused_forward(h, x, y, pc.n, pc.H, pc.W, xo, yo, ws + pc.act[0],
+                               (size_t)pc.n * 16 * pc.H * pc.W, s);
+    }
+    if (st == DRC_OK && nc && !fork) {
         if (tail.empty()) {
             if (h->prec == P_F32) st = forward_classes<P_F32>(h, h->wf, fc.data(), nc, 0, 5, s);
             if (h->prec == P_BF16) st = forward_classes<P_BF16>(h, h->wf, fc.data(), nc, 0, 5, s);
             if (h->prec == P_FP8) st = forward_classes<P_FP8>(h, h->wf, fc.data(), nc, 0, 5, s);
         } else {
-            if (!rest.empty()) {
-                for (int l = 0; l < 6; ++l) rest[0].npw[l] = fc[0].npw[l];
-                st = forward_classes<P_BF16>(h, h->wf, rest.data(), (int)rest.size(), 0, 4, s);
-            }
-            for (size_t k = 0; k < tail.size() && st == DRC_OK; ++k) {
-                const FwdClass& f = fc[tail[k]];
-                st = fused_tail(h, f.n, f.H, f.W, f.b.x, f.b.x_off, f.b.h1, f.b.h2, f.b.u2, s);
-            }
-            if (st == DRC_OK) st = forward_classes<P_BF16>(h, h->wf, fc.data(), nc, 5, 5, s);
+            st = forward_classes<P_BF16>(h, h->wf, rest.data(), (int)rest.size(), 0, 4, s);
+            if (st == DRC_OK) st = banded_chain();
         }
     }
+    // join the side stream whatever happened (a capture needs every fork joined)
+    if (fork && (hipEventRecord(h->ev_join[0], sb) != hipSuccess || hipStreamWaitEvent(s, h->ev_join[0], 0) != hipSuccess) &&
+        st == DRC_OK)
+        st = drc_fail(DRC_ERR_HIP, "plan: side stream join failed");
     h->prof = prof;
     return st;
 }
