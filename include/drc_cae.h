@@ -309,7 +309,13 @@ drc_status drc_cae_get_fp8_scales(const drc_cae* h, float out[10], void* stream)
  * stream as one captured HIP graph, recorded on the first launch for a
  * given (workspace, stream, x, y) and after any call that changes the
  * handle (set_params, calibrate_fp8, set_fused, set_tile, autotune), and
- * replayed otherwise; on the null stream directly. Errors:
+ * replayed otherwise; on the null stream directly. When the frame's BF16
+ * 128x128 classes run through the banded kernel and every other class
+ * through the whole-network kernel, their chain runs on one of the
+ * handle's internal streams, forked from and joined back to the given
+ * stream (inside the graph when captured), so the launch is still ordered
+ * on the given stream as a whole; one handle's launches must not overlap
+ * (a handle is not thread-safe). Errors:
  * DRC_ERR_INVALID_ARG for NULL / misaligned pointers, DRC_ERR_WORKSPACE,
  * DRC_ERR_STATE before set_params (FP8: calibrate_fp8). plan_destroy frees
  * the plan and its graph; the handle must outlive its plans. */
