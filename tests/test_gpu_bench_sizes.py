@@ -110,8 +110,11 @@ def test_backward_bf16_large_batch(oracle, params, n):
 
 def test_mixed_frame_6000_sampled(oracle, params):
     """The benchmark's 6000-map frame (50 % 32x32, 35 % 64x64, 15 % 128x128,
-    shuffled by seed 2), one captured-graph launch; 4 maps of each size,
-    drawn by seed, against the oracle map by map (max_rel <= 1e-2)."""
+    shuffled by seed 2), one captured-graph launch and two replays (the
+    128x128 chain on the handle's side stream beside the whole-network
+    launches); 4 maps of each size, drawn by seed, against the oracle map by
+    map (max_rel <= 1e-2), and every map of every launch bitwise equal to
+    uniform forwards of its size class on one stream."""
     from paper_1910_02480_amd.cae import CAE
     res = synth.mixed_resolutions(6000)
     x, xo, yo = synth.mixed_frame(res)
@@ -126,13 +129,26 @@ def test_mixed_frame_6000_sampled(oracle, params):
         yd = torch.full((ny,), float("nan"), device=DEV)
         stream = torch.cuda.Stream(device=DEV)
         torch.cuda.synchronize()
-        with torch.cuda.stream(stream):
-            B.drc_cae_plan_launch(plan, xd, yd, ws)
-        torch.cuda.synchronize()
-        y = yd.cpu().numpy()
+        ys = []
+        for rep in range(3):
+            print(f"[frame 6000] launch {rep}", flush=True)
+            with torch.cuda.stream(stream):
+                yd.fill_(float("nan"))
+                B.drc_cae_plan_launch(plan, xd, yd, ws)
+            torch.cuda.synchronize()
+            ys.append(yd.cpu().numpy())
+        assert B.drc_cae_plan_captures(plan) == 1
     finally:
         B.drc_cae_plan_destroy(plan)
+    y = ys[0]
     assert np.all(np.isfinite(y))
+    for r in (32, 64, 128):
+        idx = np.flatnonzero(res == r)
+        xs = torch.from_numpy(np.stack([x[xo[m]:xo[m] + r * r * 7].reshape(r, r, 7) for m in idx])).to(DEV)
+        ref = cae.forward(xs).cpu().numpy().reshape(len(idx), -1)
+        for k, yk in enumerate(ys):
+            got = np.stack([yk[yo[m]:yo[m] + r * r * 3] for m in idx])
+            np.testing.assert_array_equal(got, ref, err_msg=f"{r}x{r} class, launch {k}")
     rng = np.random.default_rng(7)
     for r in (32, 64, 128):
         pick = rng.choice(np.flatnonzero(res == r), size=4, replace=False)
