@@ -334,7 +334,7 @@ def accuracy(outputs, x_host, params_np, k):
 
 def mixed_frame_leg(cae, tune_path, args):
     """6000 cache points (50 % 32x32, 35 % 64x64, 15 % 128x128, shuffled),
-    BF16, one persistent hipGraph-captured pass per frame; p50/p99 latency
+    BF16, one hipGraph-captured pass per frame; p50/p99 latency
     over replays. Tile shapes come from the autotuner, run per resolution."""
     import numpy as np
     import torch
@@ -402,6 +402,8 @@ def main():
                     help="run each leg's workload this long before its warmup steps (clock ramp-up)")
     ap.add_argument("--frame-maps", type=int, default=6000)
     ap.add_argument("--frame-reps", type=int, default=200)
+    ap.add_argument("--frame-only", action="store_true",
+                    help="time only the mixed frame (for a kernel trace of it); prints that leg, not the bench line")
     args = ap.parse_args()
 
     global SETTLE_S
@@ -419,6 +421,12 @@ def main():
     from paper_1910_02480_amd.cae import CAE, Trainer
 
     dev = torch.device("cuda:0")
+    if args.frame_only:
+        params = torch.from_numpy(synth.init_params(0)).to(dev)
+        cae = CAE("bf16", params, device=dev)
+        tune_path = os.path.join(tempfile.gettempdir(), f"drc_tune_{os.getpid()}.jsonl")
+        print(json.dumps({"bf16_mixed_frame": mixed_frame_leg(cae, tune_path, args)}), flush=True)
+        return
     n, H = args.maps, args.res
     log(f"generating {n} maps of {H}x{H}")
     x_host = gen_maps(n, H)

@@ -5,6 +5,8 @@
         --cmd "..." --out X.md
     python -m paper_1910_02480_amd.prof_summary counters <pass1 csv> <pass2 csv> --agent <agent csv> \
         --cmd "..." --cmd "..." --out X.md
+    python -m paper_1910_02480_amd.prof_summary timeline <run_kernel_trace.csv> --labels a,b --last 50 \
+        --cmd "..." --out X.md
 
 `stats` turns a `--kernel-trace --stats` kernel table into a markdown table
 with the layer each kernel instantiation serves. `traffic` turns two `--pmc`
@@ -276,6 +278,51 @@ def read_traffic(md_path: str):
     return doc if doc["kernels"] else None
 
 
+def timeline(trace_csv: str, cmd: str, title: str, labels: list[str], last: int) -> str:
+    """Launch timeline of a repeated pass (a frame replayed many times) from
+    a `--kernel-trace` CSV: the last `last` dispatches of each kernel label
+    are taken as the last `last` passes, one dispatch per label per pass;
+    for each label the median start (relative to the pass's first start) and
+    duration, and the median span of a pass."""
+    ev = collections.defaultdict(list)
+    names = {}
+    with open(trace_csv, newline="") as fh:
+        for r in csv.DictReader(fh):
+            lab = label(r["Kernel_Name"])
+            m = re.search(r"cae_fused_forward_kernel<(\d+), (\d+)", r["Kernel_Name"])
+            if lab and m:  # the whole-network kernel of each map size
+                lab = f"{lab} {m.group(1)}x{m.group(2)}"
+            if lab in labels:
+                ev[lab].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+                names[lab] = r["Kernel_Name"]
+    missing = [lab for lab in labels if len(ev[lab]) < last]
+    if missing:
+        raise SystemExit(f"timeline: fewer than {last} dispatches of {missing}")
+    for lab in labels:
+        ev[lab].sort()
+    spans, start, dur = [], collections.defaultdict(list), collections.defaultdict(list)
+    for i in range(1, last + 1):
+        pas = {lab: ev[lab][-i] for lab in labels}
+        t0 = min(v[0] for v in pas.values())
+        spans.append((max(v[1] for v in pas.values()) - t0) / 1e3)
+        for lab, (b, e) in pas.items():
+            start[lab].append((b - t0) / 1e3)
+            dur[lab].append((e - b) / 1e3)
+
+    def med(v):
+        v = sorted(v)
+        return v[len(v) // 2] if len(v) % 2 else 0.5 * (v[len(v) // 2 - 1] + v[len(v) // 2])
+
+    out = [f"# {title}", "", "Command (run from /tmp with TMPDIR=/tmp; $R = repository root):", "", f"    {cmd}", "",
+           f"Source hash of the kernels: `{source_hash()}`", "",
+           f"Last {last} passes; medians over them (us). Span of a pass: {med(spans):.1f} us "
+           f"(min {min(spans):.1f}).", "", "| Kernel | Serves | Start | Duration | End |", "|---|---|--:|--:|--:|"]
+    for lab in sorted(labels, key=lambda x: med(start[x])):
+        out.append(f"| `{_short(names[lab])}` | {lab} | {med(start[lab]):.1f} | {med(dur[lab]):.1f} | "
+                   f"{med(start[lab]) + med(dur[lab]):.1f} |")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -298,8 +345,17 @@ def main():
     c.add_argument("--cmd", action="append", required=True, help="the command of each pass")
     c.add_argument("--title", default="SQ counters")
     c.add_argument("--out", required=True)
+    tl = sub.add_parser("timeline")
+    tl.add_argument("csv", help="run_kernel_trace.csv of a --kernel-trace run")
+    tl.add_argument("--labels", required=True, help="comma-separated kernel labels of one pass")
+    tl.add_argument("--last", type=int, default=50)
+    tl.add_argument("--cmd", required=True)
+    tl.add_argument("--title", default="Launch timeline")
+    tl.add_argument("--out", required=True)
     a = ap.parse_args()
-    if a.cmd_name == "stats":
+    if a.cmd_name == "timeline":
+        text = timeline(a.csv, a.cmd, a.title, a.labels.split(","), a.last)
+    elif a.cmd_name == "stats":
         text = stats(a.csv, a.cmd, a.title, a.top)
     elif a.cmd_name == "counters":
         text = counters(a.csv, a.agent, a.cmd, a.title)
