@@ -158,9 +158,10 @@ struct FwdClass {
 
 drc_status forward_dispatch(drc_cae* h, const FwdBufs& b, int n, int H, int W, int l0, int l1,
                             hipStream_t s);
+// d1_per_cu: persistent workgroups per CU of the band-staged D1 launch
 template <int P>
 drc_status forward_classes(drc_cae* h, void* const* packs, const FwdClass* fc, int nclass, int l0, int l1,
-                           hipStream_t s);
+                           hipStream_t s, int d1_per_cu = 2);
 int pick_npw(const drc_cae* h, int l, int H, int prec, bool bwd);
 
 // Tile shapes: pixel blocks of 16 per wave built for each layer GEMM.

@@ -382,7 +382,7 @@ bool d1_band_fits(int Hin, int Win) {
     return Hin % br == 0 && (br + 1) * Win <= kD1MaxPx && (br + 1) * Win * 8 <= kThreads * kD1Chunks;
 }
 
-drc_status d1_band_forward(const LayerArgs& a, int prec, int num_cu, hipStream_t s) {
+drc_status d1_band_forward(const LayerArgs& a, int prec, int num_cu, int per_cu, hipStream_t s) {
     E1Args e;
     e.a = a;
     long total = 0;
@@ -399,7 +399,10 @@ drc_status d1_band_forward(const LayerArgs& a, int prec, int num_cu, hipStream_t
     }
     e.total = total;
     if (total == 0) return DRC_OK;
-    const long grid = std::min(total, (long)num_cu * 2);
+    // per_cu persistent workgroups per CU (two resident at a time): alone,
+    // two; beside another stream's launches, more and shorter band lists, so
+    // that workgroups that start late finish with the rest
+    const long grid = std::min(total, (long)num_cu * std::max(1, per_cu));
     if (prec == P_FP8)
         hipLaunchKernelGGL(d1_band_kernel<P_FP8>, dim3((unsigned)grid), dim3(kThreads), kD1YOff + 12 * kBandPx * 4, s,
                            e);

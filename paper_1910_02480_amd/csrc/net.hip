@@ -64,7 +64,7 @@ namespace drc {
 bool e1_band_fits(int Hin, int Win);
 drc_status e1_band_forward(const LayerArgs& a, int prec, int num_cu, hipStream_t s);
 bool d1_band_fits(int Hin, int Win);
-drc_status d1_band_forward(const LayerArgs& a, int prec, int num_cu, hipStream_t s);
+drc_status d1_band_forward(const LayerArgs& a, int prec, int num_cu, int per_cu, hipStream_t s);
 }  // namespace drc
 
 static Seg seg_none() {
@@ -182,7 +182,7 @@ static void fwd_tensors(int l, const FwdBufs& b, int final_relu, float qout, Cla
 // nclass classes of maps (one launch per layer covers all classes).
 template <int P>
 drc_status forward_classes(drc_cae* h, void* const* packs, const FwdClass* fc, int nclass, int l0, int l1,
-                           hipStream_t s) {
+                           hipStream_t s, int d1_per_cu) {
     if (nclass < 1 || nclass > kMaxClasses) return drc_fail(DRC_ERR_INVALID_ARG, "forward: %d classes", nclass);
     const float* sc = h->host_scales;
     for (int l = l0; l <= l1; ++l) {
@@ -215,7 +215,7 @@ drc_status forward_classes(drc_cae* h, void* const* packs, const FwdClass* fc, i
         }
         if (band) {
             const long tok = prof_begin(h, PROF_FWD + l, s);
-            TRY(l == 0 ? e1_band_forward(a, P, h->num_cu, s) : d1_band_forward(a, P, h->num_cu, s));
+            TRY(l == 0 ? e1_band_forward(a, P, h->num_cu, s) : d1_band_forward(a, P, h->num_cu, d1_per_cu, s));
             prof_end(h, tok, s);
             continue;
         }
@@ -235,9 +235,12 @@ drc_status forward_classes(drc_cae* h, void* const* packs, const FwdClass* fc, i
     }
     return DRC_OK;
 }
-template drc_status forward_classes<P_F32>(drc_cae*, void* const*, const FwdClass*, int, int, int, hipStream_t);
-template drc_status forward_classes<P_BF16>(drc_cae*, void* const*, const FwdClass*, int, int, int, hipStream_t);
-template drc_status forward_classes<P_FP8>(drc_cae*, void* const*, const FwdClass*, int, int, int, hipStream_t);
+template drc_status forward_classes<P_F32>(drc_cae*, void* const*, const FwdClass*, int, int, int, hipStream_t,
+                                            int);
+template drc_status forward_classes<P_BF16>(drc_cae*, void* const*, const FwdClass*, int, int, int, hipStream_t,
+                                            int);
+template drc_status forward_classes<P_FP8>(drc_cae*, void* const*, const FwdClass*, int, int, int, hipStream_t,
+                                            int);
 
 template <int P>
 static drc_status forward_seq(drc_cae* h, void* const* packs, const FwdBufs& b, int n, int H, int W,
